@@ -1,0 +1,280 @@
+"""Seeded synthetic inputs shared by the GPU library's tests/bench and the CPU oracle.
+
+This module holds no arithmetic of the MPPI method itself: it only draws the
+inputs the method consumes (costmaps, dynamics-network parameters, initial
+states, problem parameters).  The paper's own inputs (a GPS-surveyed dirt
+track turned into a spline cost map, Section VI-C; a network trained on a
+30-minute driving dataset, Section VI-B) are not available, so every input
+here is a synthetic stand-in with the shapes the paper describes:
+
+* cost maps with values in [0, 1] that are 0 on the track and rise to 1 past
+  its boundary (the paper's map is |spline| with +-1 on the boundaries,
+  capped at 2.5; Section VI-C "Track Cost");
+* a 6 -> h -> h -> 4 tanh network (h = 32 gives the paper's 1412 parameters,
+  Section VI-B-2) with Xavier-uniform weights and zero biases;
+* vehicle states (p_x, p_y, theta, roll, v_x, v_y, theta_dot) (Section VI-B).
+
+All floating-point inputs are generated in float64 and rounded once to float32;
+both sides receive the identical float32 arrays.
+"""
+from __future__ import annotations
+
+import functools
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+
+N_STATE = 7
+N_CTRL = 2
+MLP_IN = 6
+MLP_OUT = 4
+
+
+# ----------------------------------------------------------------------------
+# Dynamics network parameters
+# ----------------------------------------------------------------------------
+
+def mlp_param_count(hidden: int) -> int:
+    """Packed parameter count of the 6 -> h -> h -> 4 network (W1,b1,W2,b2,W3,b3)."""
+    return MLP_IN * hidden + hidden + hidden * hidden + hidden + MLP_OUT * hidden + MLP_OUT
+
+
+def mlp_params(hidden: int = 32, seed: int = 0, bias_scale: float = 0.0) -> np.ndarray:
+    """Xavier-uniform weights (+-sqrt(6/(fan_in+fan_out))), zero biases by default.
+
+    Packing (float32, row-major [out][in]): W1[h][6], b1[h], W2[h][h], b2[h],
+    W3[4][h], b3[4].
+    """
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((MLP_IN, hidden), (hidden, hidden), (hidden, MLP_OUT)):
+        bound = math.sqrt(6.0 / (fan_in + fan_out))
+        w = rng.uniform(-bound, bound, size=(fan_out, fan_in))
+        b = rng.uniform(-bias_scale, bias_scale, size=(fan_out,)) if bias_scale > 0 else np.zeros(fan_out)
+        parts += [w.ravel(), b]
+    out = np.concatenate(parts).astype(np.float32)
+    assert out.size == mlp_param_count(hidden)
+    return out
+
+
+def mlp_unpack(params: np.ndarray, hidden: int):
+    """Split a packed parameter vector into (W1, b1, W2, b2, W3, b3) views."""
+    h = hidden
+    sizes = [(h, MLP_IN), (h,), (h, h), (h,), (MLP_OUT, h), (MLP_OUT,)]
+    out, off = [], 0
+    for s in sizes:
+        n = int(np.prod(s))
+        out.append(params[off:off + n].reshape(s))
+        off += n
+    assert off == params.size
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Cost maps
+# ----------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class CostMap:
+    data: np.ndarray          # [H][W] float32, row i = y, column j = x
+    origin_x: float           # world x of cell (i, j=0)
+    origin_y: float           # world y of cell (i=0, j)
+    resolution: float         # metres per cell
+
+    @property
+    def H(self) -> int:
+        return int(self.data.shape[0])
+
+    @property
+    def W(self) -> int:
+        return int(self.data.shape[1])
+
+
+def _blur_clamp(mask: np.ndarray, sigma_cells: float) -> np.ndarray:
+    from scipy.ndimage import gaussian_filter
+    out = gaussian_filter(mask.astype(np.float64), sigma=sigma_cells, mode="reflect")
+    return np.clip(out, 0.0, 1.0).astype(np.float32)
+
+
+@functools.lru_cache(maxsize=4)
+def ring_map(H: int = 256, W: int = 256, resolution: float = 0.1,
+             center=(12.8, 12.8), radius: float = 8.0, half_width: float = 2.0,
+             blur_sigma_cells: float = 2.0) -> CostMap:
+    """Circular ring track: 0 within half_width of the centre-line circle, 1 outside,
+    then Gaussian-blurred (reflect padding) and clamped to [0, 1]."""
+    res = np.float32(resolution)
+    ys = (np.arange(H) * float(res))[:, None]
+    xs = (np.arange(W) * float(res))[None, :]
+    d = np.hypot(xs - center[0], ys - center[1]) - radius
+    mask = (np.abs(d) > half_width).astype(np.float64)
+    data = _blur_clamp(mask, blur_sigma_cells)
+    data.setflags(write=False)
+    return CostMap(data, 0.0, 0.0, float(res))
+
+
+def _ellipse_distance(px: np.ndarray, py: np.ndarray, cx: float, cy: float, a: float, b: float,
+                      n_samples: int = 40000) -> np.ndarray:
+    """Unsigned distance from points to an ellipse curve (nearest of a dense sampling)."""
+    from scipy.spatial import cKDTree
+    phi = np.linspace(0.0, 2.0 * np.pi, n_samples, endpoint=False)
+    curve = np.stack([cx + a * np.cos(phi), cy + b * np.sin(phi)], axis=1)
+    tree = cKDTree(curve)
+    d, _ = tree.query(np.stack([px.ravel(), py.ravel()], axis=1), workers=-1)
+    return d.reshape(px.shape)
+
+
+@functools.lru_cache(maxsize=2)
+def ellipse_map(H: int = 2048, W: int = 2048, resolution: float = 0.05,
+                center=(51.2, 51.2), semi_axes=(40.0, 25.0), half_width: float = 5.0,
+                blur_sigma_cells: float = 5.0) -> CostMap:
+    """Closed elliptical track 2*half_width wide around an elliptical centre line;
+    walls blurred with a Gaussian (reflect) and clamped to [0, 1]."""
+    res = np.float32(resolution)
+    ys, xs = np.meshgrid(np.arange(H) * float(res), np.arange(W) * float(res), indexing="ij")
+    d = _ellipse_distance(xs, ys, center[0], center[1], semi_axes[0], semi_axes[1])
+    mask = (d > half_width).astype(np.float64)
+    data = _blur_clamp(mask, blur_sigma_cells)
+    data.setflags(write=False)
+    return CostMap(data, 0.0, 0.0, float(res))
+
+
+def constant_map(value: float, H: int = 64, W: int = 64, resolution: float = 0.5,
+                 origin=(0.0, 0.0)) -> CostMap:
+    data = np.full((H, W), value, dtype=np.float32)
+    return CostMap(data, float(np.float32(origin[0])), float(np.float32(origin[1])),
+                   float(np.float32(resolution)))
+
+
+def affine_map(a: float, b: float, c: float, H: int = 64, W: int = 64, resolution: float = 0.5,
+               origin=(0.0, 0.0)) -> CostMap:
+    """m[i][j] = a + b*i + c*j (rounded to float32)."""
+    i = np.arange(H, dtype=np.float64)[:, None]
+    j = np.arange(W, dtype=np.float64)[None, :]
+    data = (a + b * i + c * j).astype(np.float32)
+    return CostMap(data, float(np.float32(origin[0])), float(np.float32(origin[1])),
+                   float(np.float32(resolution)))
+
+
+# ----------------------------------------------------------------------------
+# Problem parameters
+# ----------------------------------------------------------------------------
+
+@dataclass
+class CostParams:
+    """State cost c(x, t):  w_map*h + crash_cost*crash_decay^t*[h > map_thresh]
+    + w_speed*(v_x - v_des)^2 + w_slip*zeta^2 + slip_cost*[|zeta| > slip_thresh],
+    zeta = -atan2(v_y, |v_x|)."""
+    w_map: float = 100.0
+    w_speed: float = 1.0
+    w_slip: float = 0.0
+    v_des: float = 6.0
+    crash_cost: float = 0.0
+    crash_decay: float = 1.0
+    map_thresh: float = float("inf")
+    slip_cost: float = 0.0
+    slip_thresh: float = float("inf")
+
+
+@dataclass
+class Problem:
+    K: int
+    T: int
+    hidden: int = 32
+    dt: float = 0.02
+    lam: float = 1.0
+    gamma: Optional[float] = None        # None -> gamma = lambda
+    sigma2: tuple = (0.3, 0.35)          # covariance diagonal (variances)
+    u_lo: tuple = (-1.0, -1.0)
+    u_hi: tuple = (1.0, 1.0)
+    sg_window: int = 1
+    sg_order: int = 0
+    seed: int = 0
+    instance: int = 0
+    cost: CostParams = field(default_factory=CostParams)
+
+    @property
+    def gamma_value(self) -> float:
+        return self.lam if self.gamma is None else self.gamma
+
+
+# ----------------------------------------------------------------------------
+# The five workload shapes
+# ----------------------------------------------------------------------------
+
+C1_X0 = np.array([20.8, 12.8, math.pi / 2, 0.0, 4.0, 0.0, 0.0], dtype=np.float32)
+C2_X0 = np.array([91.2, 51.2, math.pi / 2, 0.0, 4.0, 0.0, 0.0], dtype=np.float32)
+
+
+def c1_problem(seed: int = 0) -> Problem:
+    """Plain MPPI: K=256, T=30, ring map, cost 100*h + (v_x-6)^2, lambda=1, SGF off."""
+    return Problem(K=256, T=30, hidden=32, dt=0.02, lam=1.0, sigma2=(0.3, 0.35),
+                   sg_window=1, sg_order=0, seed=seed,
+                   cost=CostParams(w_map=100.0, w_speed=1.0, v_des=6.0))
+
+
+def c2_cost() -> CostParams:
+    return CostParams(w_map=100.0, w_speed=1.0, w_slip=1.0, v_des=8.0,
+                      crash_cost=1.0e4, crash_decay=0.9, map_thresh=0.99,
+                      slip_cost=1.0e4, slip_thresh=0.75)
+
+
+def c2_problem(seed: int = 0) -> Problem:
+    """Paper-shaped: K=1920, T=100, elliptical 2048^2 map, speed 8 m/s, slip and crash
+    impulses, lambda=6.7, Savitzky-Golay window 9 / order 2."""
+    return Problem(K=1920, T=100, hidden=32, dt=0.02, lam=6.7, sigma2=(0.3, 0.35),
+                   sg_window=9, sg_order=2, seed=seed, cost=c2_cost())
+
+
+def c3_problem(K: int = 16384, seed: int = 0) -> Problem:
+    """Precision form: hidden 64, T=100, C1's map and cost."""
+    return Problem(K=K, T=100, hidden=64, dt=0.02, lam=1.0, sigma2=(0.3, 0.35),
+                   sg_window=1, sg_order=0, seed=seed,
+                   cost=CostParams(w_map=100.0, w_speed=1.0, v_des=6.0))
+
+
+def c5_problem(seed: int = 0) -> Problem:
+    """Differentiation form: K=4096, T=100, hidden 32, C1's smooth cost."""
+    return Problem(K=4096, T=100, hidden=32, dt=0.02, lam=1.0, sigma2=(0.3, 0.35),
+                   sg_window=1, sg_order=0, seed=seed,
+                   cost=CostParams(w_map=100.0, w_speed=1.0, v_des=6.0))
+
+
+def ellipse_pose(phi: float, v_x: float, center=(51.2, 51.2), semi_axes=(40.0, 25.0)) -> np.ndarray:
+    """A pose on the elliptical centre line at parameter phi, heading along the
+    counter-clockwise tangent, with forward speed v_x and other states 0."""
+    a, b = semi_axes
+    x = center[0] + a * math.cos(phi)
+    y = center[1] + b * math.sin(phi)
+    heading = math.atan2(b * math.cos(phi), -a * math.sin(phi))
+    return np.array([x, y, heading, 0.0, v_x, 0.0, 0.0], dtype=np.float32)
+
+
+@dataclass
+class BatchInstance:
+    K: int
+    T: int
+    x0: np.ndarray
+
+
+def c4_instances(n: int = 512, seed: int = 0) -> list:
+    """Batched form: K_i ~ U{512,1024,2048,4096}, T_i ~ U{50,75,100,150}, start poses on
+    the elliptical centre line with v_x ~ U[2,10]."""
+    rng = np.random.default_rng(seed)
+    Ks = rng.choice([512, 1024, 2048, 4096], size=n)
+    Ts = rng.choice([50, 75, 100, 150], size=n)
+    phis = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    vxs = rng.uniform(2.0, 10.0, size=n)
+    return [BatchInstance(int(Ks[i]), int(Ts[i]), ellipse_pose(float(phis[i]), float(vxs[i])))
+            for i in range(n)]
+
+
+def random_controls(T: int, seed: int, scale: float = 0.3) -> np.ndarray:
+    """A nominal control sequence [T][2] for tests that start away from zero."""
+    rng = np.random.default_rng(10_000 + seed)
+    return (scale * rng.standard_normal((T, N_CTRL))).astype(np.float32)
+
+
+def with_(p: Problem, **kw) -> Problem:
+    return replace(p, **kw)
