@@ -1,0 +1,185 @@
+/*
+ * mppi.h - C ABI of the MI355X (gfx950) MPPI library (libmppi.so).
+ *
+ * One call of mppi_iterate() is one iteration of the sampling-based MPC of
+ * Williams et al., "Information Theoretic Model Predictive Control: Theory and
+ * Applications to Autonomous Driving" (arXiv 1707.02342), Algorithm 1 without
+ * its last block: draw K perturbation sequences E^k = (eps_0..eps_{T-1}),
+ * eps ~ N(0, Sigma); roll every sample through x <- F(x, g(u_t + eps_t));
+ * accumulate S_k += c(x) + gamma * u_t^T Sigma^-1 eps_t; form the weights of
+ * Algorithm 2; and update U <- U + SGF * sum_k w_k E^k.  mppi_shift() is the
+ * last block (send u_0, slide the sequence, u_{T-1} <- (0,0), Table 2).
+ *
+ * The problem follows the paper's statement: discrete dynamics x_{t+1} = F(x_t, v_t)
+ * with v_t ~ N(u_t, Sigma) (Section II, Eq. Dynamics), the state cost
+ * S(V; x0) = C(H(V; x0)) (Eq. State-Cost), the importance-sampling control law
+ * (Eq. IT-Controls) with the cost shift of Section III-D-1, the decoupled
+ * control-cost weight gamma of Section III-D-2, the clamp g of Section III-D-3
+ * and Savitzky-Golay smoothing of Section III-D-4.  The vehicle model is the
+ * paper's (Section VI-B): state (p_x, p_y, theta, roll, v_x, v_y, theta_dot),
+ * control (steer, throttle), kinematic states by explicit Euler and the dynamic
+ * states by a 6 -> h -> h -> 4 tanh network (h = 32 is the paper's 1412-parameter
+ * network); the cost is the paper's track + speed + stabilising cost
+ * (Section VI-C) on a cost map given as a grid.
+ *
+ * Conventions for every entry point:
+ *   - All inputs are COPIED into library-owned device memory; the library never
+ *     keeps a caller pointer.  Pointers named *_dev are device pointers valid on
+ *     the context's device; all others are host pointers.
+ *   - Work is enqueued on the stream given to mppi_create (NULL = the device's
+ *     null stream).  Calls that return data to the host synchronise that stream.
+ *   - No C++ exception crosses this interface.  Every call returns an
+ *     mppi_status; on failure the context's last-error string says why.
+ *   - A context belongs to one host thread at a time.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mppi_ctx mppi_ctx;
+
+typedef enum {
+  MPPI_OK = 0,
+  MPPI_E_INVAL = 1,     /* an argument is out of range or inconsistent            */
+  MPPI_E_STATE = 2,     /* call order: cost map / dynamics not set yet            */
+  MPPI_E_NOMEM = 3,     /* device allocation failed                               */
+  MPPI_E_DEVICE = 4,    /* a HIP runtime call or kernel launch failed             */
+  MPPI_E_NONFINITE = 5  /* every sampled cost was non-finite; U was left unchanged */
+} mppi_status;
+
+enum { MPPI_PREC_FP32 = 0, MPPI_PREC_BF16 = 1, MPPI_PREC_FP16 = 2 };
+
+/* Kernel schedule for the rollout (0 = pick automatically). */
+enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2 };
+
+#define MPPI_T_MAX 256
+#define MPPI_STATE_DIM 7
+#define MPPI_CTRL_DIM 2
+
+/* Algorithm 1 "Given" block: K, T, Sigma, gamma, lambda, g and the SGF.
+ * Invalid (MPPI_E_INVAL): K < 1 or K > 1<<22; T < 1 or T > MPPI_T_MAX; dt, lambda
+ * not finite and > 0; sigma2[i] not finite and > 0 (Sigma^-1 must exist); gamma not
+ * finite; u_lo[i] > u_hi[i]; sg_window even, < 1 or > T; sg_order < 0 or
+ * >= sg_window; precision not one of MPPI_PREC_*; schedule not one of MPPI_SCHED_*. */
+typedef struct {
+  int32_t K;            /* samples per iteration                                   */
+  int32_t T;            /* horizon (time steps)                                    */
+  float dt;             /* Euler step of the model, seconds                        */
+  float lambda;         /* inverse temperature (Algorithm 2)                       */
+  float gamma;          /* control-cost weight, gamma = lambda (1 - alpha)         */
+  float sigma2[2];      /* Sigma = diag(sigma2): variances of steer, throttle noise */
+  float u_lo[2];        /* clamp g: lower bounds                                   */
+  float u_hi[2];        /* clamp g: upper bounds                                   */
+  int32_t sg_window;    /* Savitzky-Golay window (odd); 1 = smoothing off          */
+  int32_t sg_order;     /* Savitzky-Golay polynomial degree; 0 with window 1       */
+  int32_t precision;    /* MPPI_PREC_*: arithmetic of the dynamics network         */
+  int32_t schedule;     /* MPPI_SCHED_*                                            */
+  uint64_t seed;        /* Philox4x32-10 key (lo, hi 32-bit words)                 */
+  uint32_t instance;    /* fourth Philox counter word                              */
+} mppi_config;
+
+/* State cost c(x, t) at the post-step state x_t, t = 1..T (Section VI-C):
+ *   w_map * h(p_x, p_y) + crash_cost * fl32(crash_decay^t) * [h > map_thresh]
+ *   + w_speed * (v_x - v_des)^2 + w_slip * zeta^2 + slip_cost * [|zeta| > slip_thresh],
+ *   zeta = -atan2(v_y, |v_x|)  (side-slip angle).
+ * All fields finite except the thresholds, which may be +inf (term off). */
+typedef struct {
+  float w_map, w_speed, w_slip, v_des;
+  float crash_cost, crash_decay, map_thresh;
+  float slip_cost, slip_thresh;
+} mppi_cost;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream` (a
+ * hipStream_t, or NULL).  Allocates all device buffers for K and T.  U starts at 0. */
+mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int device,
+                        void* hip_stream, mppi_ctx** out);
+
+/* Free everything the context owns.  NULL-safe.  Synchronises its stream. */
+void mppi_destroy(mppi_ctx* ctx);
+
+/* Human-readable reason of the last failing call on ctx ("" if none).  With
+ * ctx == NULL: the reason of the last mppi_create failure on this thread. */
+const char* mppi_last_error(const mppi_ctx* ctx);
+
+/* Cost map h: a [H][W] row-major float grid, cell (i, j) at world
+ * (origin_x + j*resolution, origin_y + i*resolution); bilinear interpolation with
+ * indices clamped to the map edge (the paper keeps it in texture memory,
+ * Section VI-C).  Copied.  INVAL: H or W < 2, resolution not > 0, non-finite origin. */
+mppi_status mppi_set_costmap(mppi_ctx* ctx, const float* map, int32_t H, int32_t W,
+                             float origin_x, float origin_y, float resolution);
+
+/* Dynamics network f(x_d, g(v)) (Section VI-B-2).  dims = {6, h, h, 4} with
+ * h = 32 or 64.  params = W1[h][6], b1[h], W2[h][h], b2[h], W3[4][h], b3[4]
+ * (row-major [out][in]); inputs (roll, v_x, v_y, theta_dot, steer, throttle),
+ * outputs d/dt of (roll, v_x, v_y, theta_dot).  Copied.  INVAL: other dims,
+ * non-finite parameters, or a precision the given h does not support. */
+mppi_status mppi_set_dynamics(mppi_ctx* ctx, const int32_t dims[4], const float* params);
+
+/* Replace the nominal control sequence U ([T][2], steer/throttle per step).  Copied. */
+mppi_status mppi_set_controls(mppi_ctx* ctx, const float* U);
+
+/* One MPPI iteration from state x0[7] (host).  Enqueued; returns without waiting
+ * unless costs_out ([K] host floats, the S_k of this iteration, +inf for a
+ * non-finite sample) is given, in which case it synchronises and also reports
+ * MPPI_E_NONFINITE.  The Philox counter's third word is the iteration count,
+ * which starts at 0 and increments on every call.
+ * STATE: map or dynamics not set. */
+mppi_status mppi_iterate(mppi_ctx* ctx, const float x0[7], float* costs_out);
+
+/* As mppi_iterate, with x0 read from device memory (7 floats) when the kernel runs. */
+mppi_status mppi_iterate_device(mppi_ctx* ctx, const float* x0_dev);
+
+/* Copy U ([T][2]) to the host.  Synchronises.  Returns MPPI_E_NONFINITE if the
+ * most recent iteration found no finite cost (U was then left unchanged). */
+mppi_status mppi_get_controls(mppi_ctx* ctx, float* U_out);
+
+/* Algorithm 1's last block: u0_out = u_0; u_{t-1} <- u_t; u_{T-1} <- (0, 0).
+ * Synchronises.  Returns MPPI_E_NONFINITE like mppi_get_controls. */
+mppi_status mppi_shift(mppi_ctx* ctx, float u0_out[2]);
+
+/* Noise-free plant step x_out = F(x, g(u)) with the context's model (FP32, on the
+ * GPU).  Synchronises.  Used to drive a receding-horizon loop on a synthetic plant. */
+mppi_status mppi_plant_step(mppi_ctx* ctx, const float x[7], const float u[2], float x_out[7]);
+
+/* n_iter receding-horizon steps entirely on the device: iterate from x, shift,
+ * then x <- F(x, g(u_0)).  u_hist ([n_iter][2]) and x_hist ([n_iter+1][7], x_hist[0]
+ * = x0) may be NULL.  Synchronises at the end only. */
+mppi_status mppi_run_receding(mppi_ctx* ctx, const float x0[7], int32_t n_iter,
+                              float* u_hist, float* x_hist);
+
+/* Diagnostics of the most recent iteration (synchronises): rho = min_k S_k,
+ * eta~ = sum_k exp(-(S_k - rho)/lambda), and the unsmoothed update
+ * Delta_t = sum_k w_k eps_{k,t} ([T][2]).  Any output pointer may be NULL. */
+mppi_status mppi_get_stats(mppi_ctx* ctx, float* rho, float* eta, float* delta_out);
+
+/* The perturbations eps ([K][T][2]) that the device generator draws for
+ * iteration `iter` (the generator of the rollout kernels, run on its own).
+ * Synchronises. */
+mppi_status mppi_get_noise(mppi_ctx* ctx, uint32_t iter, float* eps_out);
+
+/* Iteration counter (the Philox counter's third word) for checkpoint/resume:
+ * U (mppi_get_controls / mppi_set_controls), the seed and this counter
+ * reproduce the next iteration bit for bit. */
+mppi_status mppi_get_iteration(const mppi_ctx* ctx, uint32_t* iter);
+mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iter);
+
+/* Rollout schedule actually used (MPPI_SCHED_LANE or MPPI_SCHED_WAVE). */
+mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
+
+/* Per-kernel device time, measured with HIP events recorded on the context's
+ * stream around every launch once enabled.  times_ms[0] = rollout kernel,
+ * times_ms[1] = weights/update kernel, summed since the last reset; counts[0..1]
+ * = launches.  Synchronises. */
+mppi_status mppi_set_timing(mppi_ctx* ctx, int32_t enable);
+mppi_status mppi_get_timing(mppi_ctx* ctx, double times_ms[2], int64_t counts[2]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPPI_H */

@@ -83,6 +83,8 @@ def lib():
         L.orc_toy_iterate.argtypes = [C.c_double, C.c_double, C.c_double, C.c_float, C.c_float,
                                       C.c_double, C.c_int, C.c_int, dp, C.c_uint64, C.c_uint32,
                                       C.c_double, dp]
+        L.orc_threshold_margins.argtypes = [pp, fp, fp, fp, dp]
+        L.orc_threshold_margins.restype = C.c_int
         L.orc_mlp_forward.argtypes = [pp, dp, dp]
         L.orc_costmap.argtypes = [pp, C.c_double, C.c_double, dp]
         L.orc_costmap.restype = C.c_double
@@ -312,3 +314,15 @@ def state_cost(op: OracleProblem, x, t: int):
     g = np.zeros(7)
     c = lib().orc_state_cost(op.ref(), _ptr(x, C.c_double), int(t), _ptr(g, C.c_double))
     return c, g
+
+
+def threshold_margins(op: OracleProblem, x0, U, eps) -> np.ndarray:
+    x0 = _f32(x0)
+    U = _f32(U)
+    eps = _f32(eps)
+    m = np.zeros(op.K)
+    st = lib().orc_threshold_margins(op.ref(), _ptr(x0, C.c_float), _ptr(U, C.c_float),
+                                     _ptr(eps, C.c_float), _ptr(m, C.c_double))
+    if st != OK:
+        raise ValueError("oracle margins status")
+    return m

@@ -701,6 +701,30 @@ int orc_objective_grad(const orc_problem* p, const float* x0, const double* U, c
   return ORC_OK;
 }
 
+// Per sample, the smallest distance over t = 1..T of the map value to map_thresh
+// and of |zeta| to slip_thresh along the FP64 trajectory: samples that pass within
+// a rounding error of an impulse threshold can legitimately flip an indicator.
+int orc_threshold_margins(const orc_problem* p, const float* x0, const float* U, const float* eps,
+                          double* margin) {
+  if (!valid_problem(p)) return ORC_E_INVAL;
+  Prob<double> P = make_prob<double>(p);
+  const int T = P.T;
+  parallel_for(P.K, p->nthreads, [&](int k) {
+    std::vector<double> tr((size_t)(T + 1) * 7);
+    rollout_one(P, x0, U, eps + (size_t)k * T * 2, tr.data());
+    double m = std::numeric_limits<double>::infinity();
+    for (int t = 1; t <= T; ++t) {
+      const double* x = &tr[(size_t)t * 7];
+      const double h = costmap(P, x[0], x[1]);
+      const double zeta = -std::atan2(x[5], std::fabs(x[4]));
+      if (std::isfinite((double)P.map_thresh)) m = std::min(m, std::fabs(h - P.map_thresh));
+      if (std::isfinite((double)P.slip_thresh)) m = std::min(m, std::fabs(std::fabs(zeta) - P.slip_thresh));
+    }
+    margin[k] = m;
+  });
+  return ORC_OK;
+}
+
 // Single-step pieces, exported so each can be pinned on its own.
 int orc_mlp_forward(const orc_problem* p, const double* in, double* out) {
   if (!p || !p->params || p->hidden <= 0) return ORC_E_INVAL;

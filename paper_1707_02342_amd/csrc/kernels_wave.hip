@@ -1,0 +1,339 @@
+// Rollout schedule "wave": 32 lanes per sample, two samples per wavefront, for the
+// latency-bound regime (a few thousand samples, e.g. K = 1920, T = 100), where one
+// lane per sample would leave most of the chip idle while each lane walks a
+// 100-step serial chain.
+//
+// Only the dynamic states x_d = (roll, v_x, v_y, theta_dot) form a serial chain: the
+// network reads x_d and the control, never the pose (Section VI-B).  So the kernel
+// splits each sample's work into four phases:
+//
+//  A. noise: each of the sample's 32 lanes draws eps for steps t = lane + 32 i
+//     (Philox + Box-Muller), kept in registers and copied to LDS;
+//  B. the serial x_d chain, one network evaluation per step with the 32 hidden
+//     units spread one per lane:
+//       layer 1: lane (row r, column c) owns neuron j = 16 r + c; the four state
+//                components live in the lanes of each quad (component = lane & 3) and
+//                reach every lane through quad_perm DPP operands of v_fmac_f32;
+//       layer 2: each lane accumulates two outputs (c and 16 + c) over the 16 inputs
+//                of its own row, reading them with row_ror DPP operands of
+//                v_fmac_f32; v_permlane16_swap then exchanges the half sums between
+//                the sample's two rows, so lane (r, c) ends with neuron 16 r + c;
+//       layer 3: four products per lane, a reduce-scatter over each row (quad_perm
+//                exchanges for bits 0 and 1 of the lane, row_ror 8 and 4 for bits 3
+//                and 2) leaves output (lane & 3) in every lane, and a second
+//                permlane16 swap adds the two rows;
+//       update:  x_d += dt f in compensated (two-sum) form, one component per lane;
+//  C. kinematics and cost, lane-parallel over t: theta and the position are prefix
+//     sums of their Euler increments (scans across the 32 lanes), then the cost at
+//     every post-step state and the control-cost term, summed over t;
+//  D. the block's softmin partial (rho_g, eta_g, N_g) for the merge kernel.
+//
+// The network arithmetic of phase B is exactly the FP32 network of the lane
+// schedule with a different summation order.
+#include "kernels_common.hip.h"
+
+namespace mppi {
+
+constexpr int kWaveBlock = 256;
+constexpr int kWaveSlots = 8;        // samples per block
+constexpr int kWaveNT = kTMax / 32;  // chunks of 32 steps
+
+__device__ __forceinline__ float as_f(uint32_t v) { return __builtin_bit_cast(float, v); }
+__device__ __forceinline__ uint32_t as_u(float v) { return __builtin_bit_cast(uint32_t, v); }
+
+// acc += src[dpp lane] * w, as one v_fmac_f32 with a DPP source operand.  The first
+// use after src was written is preceded by two wait states (VALU write -> DPP read).
+#define FMAC_DPP(acc, src, w, ctrl) \
+  asm volatile("v_fmac_f32_dpp %0, %1, %2 " ctrl " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(w))
+#define FMAC_DPP_FIRST(acc, src, w, ctrl)                                                        \
+  asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 " ctrl " row_mask:0xf bank_mask:0xf" : "+v"(acc) \
+      : "v"(src), "v"(w))
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return as_f((uint32_t)__builtin_amdgcn_mov_dpp((int)as_u(v), CTRL, 0xf, 0xf, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+
+constexpr int kRowRor = 0x120;        // row_ror:s = 0x120 + s
+constexpr int kQuadXor1 = 0xB1;       // quad_perm:[1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;       // quad_perm:[2,3,0,1]
+
+// Column (0..15) whose value lane `col` reads through row_ror:S.
+template <int S>
+__device__ __forceinline__ int ror_src(int col) {
+  return dpp_i<kRowRor + S>(col);
+}
+
+// Exchange between the two 16-lane rows of each 32-lane half: returns the pair
+// (new first operand, new second operand) of v_permlane16_swap.
+__device__ __forceinline__ void swap_rows(float& a, float& b) {
+  auto r = __builtin_amdgcn_permlane16_swap(as_u(a), as_u(b), false, false);
+  a = as_f(r[0]);
+  b = as_f(r[1]);
+}
+
+// Sum of v over the sample's two rows, the same bits in both rows.
+__device__ __forceinline__ float add_rows(float v) {
+  float x = v, y = v;
+  swap_rows(x, y);
+  return x + y;
+}
+
+__device__ __forceinline__ float scan32_incl(float v, int c32) {
+#pragma unroll
+  for (int d = 1; d < 32; d <<= 1) {
+    const float o = __shfl_up(v, d, 32);
+    if (c32 >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float sum32(float v) {
+#pragma unroll
+  for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
+  return v;
+}
+
+template <int HID>
+__global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a) {
+  static_assert(HID == 32, "the wave schedule maps 32 hidden units onto 32 lanes");
+  extern __shared__ float smem[];
+  const int T = a.T;
+  const int T4 = (T + 4) & ~3;                       // padded row counts (16-byte aligned)
+  float* sU = smem;                                  // [2T]
+  float* sE = sU + ((2 * T + 3) & ~3);               // [8][2T]
+  float* sX = sE + kWaveSlots * ((2 * T + 3) & ~3);  // [8][T4][4]
+  float* red = sX + kWaveSlots * T4 * 4;             // [4][2T]
+  float* scratch = red + 4 * ((2 * T + 3) & ~3);     // [16]
+  const int eStride = (2 * T + 3) & ~3;
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int half = lane >> 5;
+  const int c32 = lane & 31;
+  const int r = c32 >> 4;
+  const int col = lane & 15;
+  const int comp = lane & 3;
+  const int slot = wv * 2 + half;
+  const int k = blockIdx.x * kWaveSlots + slot;
+  const bool valid = k < a.K;
+  float* myE = sE + slot * eStride;
+  float4* myX = reinterpret_cast<float4*>(sX + slot * T4 * 4);
+
+  for (int i = threadIdx.x; i < 2 * T; i += kWaveBlock) sU[i] = a.U[i];
+
+  // ---- per-lane network constants --------------------------------------------------
+  const float* W1 = a.params;
+  const float* b1 = W1 + HID * 6;
+  const float* W2 = b1 + HID;
+  const float* b2 = W2 + HID * HID;
+  const float* W3 = b2 + HID;
+  const float* b3 = W3 + 4 * HID;
+  const int j = 16 * r + col;
+  float w1[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) w1[i] = W1[j * 6 + i];
+  const float bb1 = b1[j];
+  float wP[16], wQ[16];
+  int src[16];
+  src[0] = col;
+  src[1] = ror_src<1>(col);   src[2] = ror_src<2>(col);   src[3] = ror_src<3>(col);
+  src[4] = ror_src<4>(col);   src[5] = ror_src<5>(col);   src[6] = ror_src<6>(col);
+  src[7] = ror_src<7>(col);   src[8] = ror_src<8>(col);   src[9] = ror_src<9>(col);
+  src[10] = ror_src<10>(col); src[11] = ror_src<11>(col); src[12] = ror_src<12>(col);
+  src[13] = ror_src<13>(col); src[14] = ror_src<14>(col); src[15] = ror_src<15>(col);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    wP[s] = W2[col * HID + 16 * r + src[s]];
+    wQ[s] = W2[(16 + col) * HID + 16 * r + src[s]];
+  }
+  const float bP = (r == 0) ? b2[col] : 0.0f;
+  const float bQ = (r == 1) ? b2[16 + col] : 0.0f;
+  float w3[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) w3[o] = W3[o * HID + j];
+  const float b3c = b3[comp];
+  const bool bit0 = (lane & 1) != 0;
+  const bool bit1 = (lane & 2) != 0;
+
+  float x0v[kStateDim];
+#pragma unroll
+  for (int i = 0; i < kStateDim; ++i) x0v[i] = a.x0_dev ? a.x0_dev[i] : a.x0[i];
+
+  // ---- A: noise ---------------------------------------------------------------------
+  float ea[kWaveNT], eb[kWaveNT];
+#pragma unroll
+  for (int i = 0; i < kWaveNT; ++i) {
+    const int t = 32 * i + c32;
+    ea[i] = 0.0f;
+    eb[i] = 0.0f;
+    if (t < T) {
+      draw_eps((uint32_t)t, (uint32_t)k, a.nk, ea[i], eb[i]);
+      myE[2 * t] = ea[i];
+      myE[2 * t + 1] = eb[i];
+    }
+  }
+  Acc xd{x0v[3 + comp], 0.0f};
+  if (c32 < 4) sX[slot * T4 * 4 + c32] = x0v[3 + c32];
+  __syncthreads();
+
+  // ---- B: serial chain of the dynamic states ---------------------------------------
+  for (int t = 0; t < T; ++t) {
+    const float2 u = *reinterpret_cast<const float2*>(sU + 2 * t);
+    const float2 e = *reinterpret_cast<const float2*>(myE + 2 * t);
+    const float vc0 = fminf(fmaxf(u.x + e.x, a.u_lo0), a.u_hi0);
+    const float vc1 = fminf(fmaxf(u.y + e.y, a.u_lo1), a.u_hi1);
+    // layer 1
+    float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
+    acc1 = __builtin_fmaf(w1[5], vc1, acc1);
+    const float xh = xd.hi;
+    FMAC_DPP_FIRST(acc1, xh, w1[0], "quad_perm:[0,0,0,0]");
+    FMAC_DPP(acc1, xh, w1[1], "quad_perm:[1,1,1,1]");
+    FMAC_DPP(acc1, xh, w1[2], "quad_perm:[2,2,2,2]");
+    FMAC_DPP(acc1, xh, w1[3], "quad_perm:[3,3,3,3]");
+    const float h1 = tanh_f(acc1);
+    // layer 2: four interleaved chains (P, Q for even and odd rotations) so that no
+    // accumulator is read by the instruction right after the one that wrote it
+    float P = __builtin_fmaf(wP[0], h1, bP);
+    float Q = __builtin_fmaf(wQ[0], h1, bQ);
+    float P2 = wP[1] * dpp_f<kRowRor + 1>(h1);
+    float Q2 = wQ[1] * dpp_f<kRowRor + 1>(h1);
+    FMAC_DPP(P, h1, wP[2], "row_ror:2");
+    FMAC_DPP(Q, h1, wQ[2], "row_ror:2");
+    FMAC_DPP(P2, h1, wP[3], "row_ror:3");
+    FMAC_DPP(Q2, h1, wQ[3], "row_ror:3");
+    FMAC_DPP(P, h1, wP[4], "row_ror:4");
+    FMAC_DPP(Q, h1, wQ[4], "row_ror:4");
+    FMAC_DPP(P2, h1, wP[5], "row_ror:5");
+    FMAC_DPP(Q2, h1, wQ[5], "row_ror:5");
+    FMAC_DPP(P, h1, wP[6], "row_ror:6");
+    FMAC_DPP(Q, h1, wQ[6], "row_ror:6");
+    FMAC_DPP(P2, h1, wP[7], "row_ror:7");
+    FMAC_DPP(Q2, h1, wQ[7], "row_ror:7");
+    FMAC_DPP(P, h1, wP[8], "row_ror:8");
+    FMAC_DPP(Q, h1, wQ[8], "row_ror:8");
+    FMAC_DPP(P2, h1, wP[9], "row_ror:9");
+    FMAC_DPP(Q2, h1, wQ[9], "row_ror:9");
+    FMAC_DPP(P, h1, wP[10], "row_ror:10");
+    FMAC_DPP(Q, h1, wQ[10], "row_ror:10");
+    FMAC_DPP(P2, h1, wP[11], "row_ror:11");
+    FMAC_DPP(Q2, h1, wQ[11], "row_ror:11");
+    FMAC_DPP(P, h1, wP[12], "row_ror:12");
+    FMAC_DPP(Q, h1, wQ[12], "row_ror:12");
+    FMAC_DPP(P2, h1, wP[13], "row_ror:13");
+    FMAC_DPP(Q2, h1, wQ[13], "row_ror:13");
+    FMAC_DPP(P, h1, wP[14], "row_ror:14");
+    FMAC_DPP(Q, h1, wQ[14], "row_ror:14");
+    FMAC_DPP(P2, h1, wP[15], "row_ror:15");
+    FMAC_DPP(Q2, h1, wQ[15], "row_ror:15");
+    P = P + P2;
+    Q = Q + Q2;
+    swap_rows(P, Q);                    // row 0: (P0, P1) -> out c;  row 1: (Q0, Q1) -> out 16+c
+    const float h2 = tanh_f(P + Q);
+    // layer 3: reduce-scatter of the four outputs over the row
+    const float a0 = w3[0] * h2, a1 = w3[1] * h2, a2 = w3[2] * h2, a3 = w3[3] * h2;
+    const float send0 = bit0 ? a0 : a1, keep0 = bit0 ? a1 : a0;
+    const float send1 = bit0 ? a2 : a3, keep1 = bit0 ? a3 : a2;
+    const float g0 = keep0 + dpp_f<kQuadXor1>(send0);        // output bit0
+    const float g1 = keep1 + dpp_f<kQuadXor1>(send1);        // output 2 + bit0
+    const float send2 = bit1 ? g0 : g1, keep2 = bit1 ? g1 : g0;
+    float f = keep2 + dpp_f<kQuadXor2>(send2);               // output lane & 3
+    f = f + dpp_f<kRowRor + 8>(f);
+    f = f + dpp_f<kRowRor + 4>(f);
+    f = add_rows(f) + b3c;
+    xd.add(a.dt * f);
+    if (c32 < 4) sX[slot * T4 * 4 + (t + 1) * 4 + c32] = xd.value();
+  }
+  __syncthreads();
+
+  // ---- C: kinematics and cost, parallel over t ---------------------------------------
+  float thb = x0v[2], pxb = x0v[0], pyb = x0v[1];
+  Acc Sacc{0.0f, 0.0f};
+  bool ok = true;
+  const int NT = (T + 31) >> 5;
+#pragma unroll
+  for (int i = 0; i < kWaveNT; ++i) {
+    if (i < NT) {
+      const int t = 32 * i + c32;
+      const bool act = t < T;
+      const int tt = act ? t : 0;
+      const float4 xs = myX[tt];
+      const float4 xn = myX[tt + 1];
+      const float dth = act ? a.dt * xs.w : 0.0f;
+      const float ith = scan32_incl(dth, c32);
+      float eth = __shfl_up(ith, 1, 32);
+      if (c32 == 0) eth = 0.0f;
+      const float th = thb + eth;
+      float sn, cs;
+      sincosf(th, &sn, &cs);
+      const float dpx = act ? a.dt * (cs * xs.y - sn * xs.z) : 0.0f;
+      const float dpy = act ? a.dt * (sn * xs.y + cs * xs.z) : 0.0f;
+      const float ipx = scan32_incl(dpx, c32);
+      const float ipy = scan32_incl(dpy, c32);
+      const float px1 = pxb + ipx, py1 = pyb + ipy, th1 = thb + ith;
+      if (act) {
+        Sacc.add(state_cost(a.cost, a.map, a.decay, px1, py1, xn.y, xn.z, t + 1));
+        Sacc.add(a.gcs0 * (sU[2 * t] * ea[i]) + a.gcs1 * (sU[2 * t + 1] * eb[i]));
+        ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1) && finite_f(xn.x) &&
+             finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
+      }
+      thb += __shfl(ith, 31, 32);
+      pxb += __shfl(ipx, 31, 32);
+      pyb += __shfl(ipy, 31, 32);
+    }
+  }
+  float S = sum32(Sacc.value());
+  int okc = ok ? 1 : 0;
+#pragma unroll
+  for (int m = 16; m >= 1; m >>= 1) okc &= __shfl_xor(okc, m, 32);
+  if (!valid || !okc || !finite_f(S)) S = kInf;
+  if (valid && c32 == 0) a.S[k] = S;
+
+  // ---- D: softmin partial of the block's samples ------------------------------------
+  const float wmin = fminf(S, __shfl_xor(S, 32, 64));
+  if (lane == 0) scratch[wv] = wmin;
+  __syncthreads();
+  const float rho = fminf(fminf(scratch[0], scratch[1]), fminf(scratch[2], scratch[3]));
+  const float e = rel_weight(S, rho, a.inv_lambda);
+  const float epair = e + __shfl_xor(e, 32, 64);
+  if (lane == 0) scratch[4 + wv] = epair;
+  const int eStrideRed = eStride;
+#pragma unroll
+  for (int i = 0; i < kWaveNT; ++i) {
+    if (i < NT) {
+      const int t = 32 * i + c32;
+      const float n0 = e * ea[i], n1 = e * eb[i];
+      const float p0 = n0 + __shfl_xor(n0, 32, 64);
+      const float p1 = n1 + __shfl_xor(n1, 32, 64);
+      if (half == 0 && t < T) {
+        red[wv * eStrideRed + 2 * t] = p0;
+        red[wv * eStrideRed + 2 * t + 1] = p1;
+      }
+    }
+  }
+  __syncthreads();
+  const int stride = 2 + 2 * T;
+  float* out = a.part + (size_t)blockIdx.x * stride;
+  for (int o = threadIdx.x; o < 2 * T; o += kWaveBlock)
+    out[2 + o] = ((red[o] + red[eStrideRed + o]) + red[2 * eStrideRed + o]) + red[3 * eStrideRed + o];
+  if (threadIdx.x == 0) {
+    out[0] = rho;
+    out[1] = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
+  }
+}
+
+template __global__ void rollout_wave_kernel<32>(RolloutArgs);
+
+// Dynamic LDS bytes the wave kernel needs for horizon T.
+size_t wave_smem_bytes(int T) {
+  const size_t e = (size_t)((2 * T + 3) & ~3);
+  const size_t T4 = (size_t)((T + 4) & ~3);
+  return sizeof(float) * (e + kWaveSlots * e + kWaveSlots * T4 * 4 + 4 * e + 16);
+}
+
+}  // namespace mppi

@@ -1,0 +1,695 @@
+// Host runtime of libmppi.so: the C ABI declared in include/mppi.h.
+//
+// The context owns every device buffer, binds one HIP stream, validates every
+// argument before anything is enqueued, and launches the rollout kernel (one
+// of two schedules) followed by the merge/update kernel for each iteration.
+// No C++ exception escapes: every entry point catches and maps to a status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mppi.h"
+#include "mppi_types.h"
+
+namespace mppi {
+template <int HID> __global__ void rollout_lane_kernel(RolloutArgs);
+template <int HID> __global__ void rollout_wave_kernel(RolloutArgs);
+size_t wave_smem_bytes(int T);
+__global__ void merge_update_kernel(MergeArgs, float*);
+__global__ void shift_kernel(float*, int, float*);
+template <int HID>
+__global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
+                             float, float, float);
+__global__ void noise_kernel(NoiseKey, int, int, float*);
+constexpr int kLaneBlockHost = 256;
+constexpr int kWaveSamplesPerBlock = 8;   // 4 waves x 2 samples of 32 lanes
+constexpr int kWaveBlockThreads = 256;
+}  // namespace mppi
+
+using namespace mppi;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int32_t kMaxK = 1 << 22;
+// Automatic schedule: 32 lanes per sample while that still fits the chip in a few
+// waves per SIMD (latency-bound regime), one lane per sample beyond.
+constexpr int32_t kWaveAutoMaxK = 32768;
+
+struct PendingTiming {
+  hipEvent_t e0, e1, e2;
+};
+
+}  // namespace
+
+struct mppi_ctx {
+  mppi_config cfg{};
+  mppi_cost cost{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int hidden = 0;
+  bool have_map = false, have_dyn = false;
+  int H = 0, W = 0;
+  float ox = 0, oy = 0, res = 1;
+  float* d_U = nullptr;
+  float* d_map = nullptr;
+  float* d_params = nullptr;
+  float* d_decay = nullptr;
+  float* d_S = nullptr;
+  float* d_part = nullptr;
+  float* d_scale = nullptr;
+  float* d_stats = nullptr;
+  float* d_sg = nullptr;
+  float* d_x = nullptr;      // [7] device-resident state for the receding loop
+  float* d_u0 = nullptr;     // [2]
+  int* d_status = nullptr;
+  float* d_hist_u = nullptr;
+  float* d_hist_x = nullptr;
+  int hist_cap = 0;
+  int part_cap = 0;          // partial rows allocated
+  uint32_t iter = 0;
+  int schedule = MPPI_SCHED_LANE;
+  float sig[2] = {0, 0};
+  std::string err;
+  bool timing = false;
+  std::vector<PendingTiming> pending;
+  std::vector<hipEvent_t> event_pool;
+  double t_ms[2] = {0, 0};
+  int64_t t_cnt[2] = {0, 0};
+};
+
+namespace {
+
+mppi_status fail(mppi_ctx* c, mppi_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_error = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? MPPI_E_NOMEM : MPPI_E_DEVICE, "%s: %s", \
+                  #expr, hipGetErrorString(e_));                                             \
+  } while (0)
+
+bool finite(float v) { return std::isfinite(v); }
+
+int sched_ok(int s) { return s == MPPI_SCHED_AUTO || s == MPPI_SCHED_LANE || s == MPPI_SCHED_WAVE; }
+
+mppi_status validate_config(const mppi_config* c) {
+  if (!c) return fail(nullptr, MPPI_E_INVAL, "config is NULL");
+  if (c->K < 1 || c->K > kMaxK) return fail(nullptr, MPPI_E_INVAL, "K=%d outside [1, %d]", c->K, kMaxK);
+  if (c->T < 1 || c->T > MPPI_T_MAX) return fail(nullptr, MPPI_E_INVAL, "T=%d outside [1, %d]", c->T, MPPI_T_MAX);
+  if (!finite(c->dt) || !(c->dt > 0)) return fail(nullptr, MPPI_E_INVAL, "dt must be finite and > 0");
+  if (!finite(c->lambda) || !(c->lambda > 0)) return fail(nullptr, MPPI_E_INVAL, "lambda must be finite and > 0");
+  if (!finite(c->gamma)) return fail(nullptr, MPPI_E_INVAL, "gamma must be finite");
+  for (int i = 0; i < 2; ++i) {
+    if (!finite(c->sigma2[i]) || !(c->sigma2[i] > 0))
+      return fail(nullptr, MPPI_E_INVAL, "sigma2[%d] must be finite and > 0 (Sigma^-1 must exist)", i);
+    if (!finite(c->u_lo[i]) || !finite(c->u_hi[i]) || c->u_lo[i] > c->u_hi[i])
+      return fail(nullptr, MPPI_E_INVAL, "clamp bounds u_lo[%d] <= u_hi[%d] must be finite", i, i);
+  }
+  if (c->sg_window < 1 || c->sg_window % 2 == 0 || c->sg_window > c->T)
+    return fail(nullptr, MPPI_E_INVAL, "sg_window=%d must be odd and in [1, T]", c->sg_window);
+  if (c->sg_order < 0 || c->sg_order >= c->sg_window)
+    return fail(nullptr, MPPI_E_INVAL, "sg_order=%d must be in [0, sg_window)", c->sg_order);
+  if (c->precision != MPPI_PREC_FP32 && c->precision != MPPI_PREC_BF16 && c->precision != MPPI_PREC_FP16)
+    return fail(nullptr, MPPI_E_INVAL, "unknown precision %d", c->precision);
+  if (!sched_ok(c->schedule)) return fail(nullptr, MPPI_E_INVAL, "unknown schedule %d", c->schedule);
+  return MPPI_OK;
+}
+
+mppi_status validate_cost(const mppi_cost* c) {
+  if (!c) return fail(nullptr, MPPI_E_INVAL, "cost is NULL");
+  const float v[] = {c->w_map, c->w_speed, c->w_slip, c->v_des, c->crash_cost, c->crash_decay, c->slip_cost};
+  for (float x : v)
+    if (!finite(x)) return fail(nullptr, MPPI_E_INVAL, "cost weights must be finite");
+  if (std::isnan(c->map_thresh) || std::isnan(c->slip_thresh))
+    return fail(nullptr, MPPI_E_INVAL, "cost thresholds must not be NaN");
+  return MPPI_OK;
+}
+
+// Savitzky-Golay rows [T][w]: row t evaluates at t the degree-d least-squares
+// polynomial through the w points starting at lo = clamp(t - w/2, 0, T - w).
+// Computed by a modified Gram-Schmidt QR of the (scaled) Vandermonde matrix: the
+// value at t of the fit is e_0^T R^-1 Q^T y with positions measured from t.
+std::vector<float> savgol_rows(int T, int w, int d) {
+  std::vector<float> out((size_t)T * w, 0.0f);
+  const int n = d + 1;
+  const double scale = std::max(1.0, (double)w);
+  for (int t = 0; t < T; ++t) {
+    const int lo = std::min(std::max(t - w / 2, 0), T - w);
+    std::vector<double> Q((size_t)w * n), R((size_t)n * n, 0.0);
+    for (int r = 0; r < w; ++r)
+      for (int p = 0; p < n; ++p) Q[(size_t)r * n + p] = std::pow((double)(lo + r - t) / scale, p);
+    for (int p = 0; p < n; ++p) {
+      for (int q = 0; q < p; ++q) {
+        double dot = 0;
+        for (int r = 0; r < w; ++r) dot += Q[(size_t)r * n + q] * Q[(size_t)r * n + p];
+        R[(size_t)q * n + p] = dot;
+        for (int r = 0; r < w; ++r) Q[(size_t)r * n + p] -= dot * Q[(size_t)r * n + q];
+      }
+      double nrm = 0;
+      for (int r = 0; r < w; ++r) nrm += Q[(size_t)r * n + p] * Q[(size_t)r * n + p];
+      nrm = std::sqrt(nrm);
+      R[(size_t)p * n + p] = nrm;
+      for (int r = 0; r < w; ++r) Q[(size_t)r * n + p] /= nrm;
+    }
+    // row 0 of R^-1: solve R^T z = e_0 (forward substitution), then coef = Q z
+    std::vector<double> z(n, 0.0);
+    for (int p = 0; p < n; ++p) {
+      double s = (p == 0) ? 1.0 : 0.0;
+      for (int q = 0; q < p; ++q) s -= R[(size_t)q * n + p] * z[q];
+      z[p] = s / R[(size_t)p * n + p];
+    }
+    for (int r = 0; r < w; ++r) {
+      double cr = 0;
+      for (int p = 0; p < n; ++p) cr += Q[(size_t)r * n + p] * z[p];
+      out[(size_t)t * w + r] = (float)cr;
+    }
+  }
+  return out;
+}
+
+hipEvent_t take_event(mppi_ctx* c) {
+  hipEvent_t e = nullptr;
+  if (!c->event_pool.empty()) {
+    e = c->event_pool.back();
+    c->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+mppi_status drain_timing(mppi_ctx* c) {
+  for (auto& p : c->pending) {
+    HIP_TRY(c, hipEventSynchronize(p.e2));
+    float a = 0, b = 0;
+    HIP_TRY(c, hipEventElapsedTime(&a, p.e0, p.e1));
+    HIP_TRY(c, hipEventElapsedTime(&b, p.e1, p.e2));
+    c->t_ms[0] += a;
+    c->t_ms[1] += b;
+    c->t_cnt[0] += 1;
+    c->t_cnt[1] += 1;
+    c->event_pool.push_back(p.e0);
+    c->event_pool.push_back(p.e1);
+    c->event_pool.push_back(p.e2);
+  }
+  c->pending.clear();
+  return MPPI_OK;
+}
+
+int blocks_for(const mppi_ctx* c, int sched) {
+  const int K = c->cfg.K;
+  if (sched == MPPI_SCHED_WAVE) return (K + kWaveSamplesPerBlock - 1) / kWaveSamplesPerBlock;
+  return (K + kLaneBlockHost - 1) / kLaneBlockHost;
+}
+
+RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x0_dev) {
+  RolloutArgs a{};
+  a.U = c->d_U;
+  a.map = c->d_map;
+  a.params = c->d_params;
+  a.decay = c->d_decay;
+  a.x0_dev = x0_dev;
+  a.S = c->d_S;
+  a.part = c->d_part;
+  for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
+  a.K = c->cfg.K;
+  a.T = c->cfg.T;
+  a.dt = c->cfg.dt;
+  a.inv_lambda = 1.0f / c->cfg.lambda;
+  a.gcs0 = c->cfg.gamma / c->cfg.sigma2[0];
+  a.gcs1 = c->cfg.gamma / c->cfg.sigma2[1];
+  a.u_lo0 = c->cfg.u_lo[0];
+  a.u_lo1 = c->cfg.u_lo[1];
+  a.u_hi0 = c->cfg.u_hi[0];
+  a.u_hi1 = c->cfg.u_hi[1];
+  a.nk.key_lo = (uint32_t)c->cfg.seed;
+  a.nk.key_hi = (uint32_t)(c->cfg.seed >> 32);
+  a.nk.iter = c->iter;
+  a.nk.instance = c->cfg.instance;
+  a.nk.sig0 = c->sig[0];
+  a.nk.sig1 = c->sig[1];
+  a.cost.H = c->H;
+  a.cost.W = c->W;
+  a.cost.ox = c->ox;
+  a.cost.oy = c->oy;
+  a.cost.res = c->res;
+  a.cost.w_map = c->cost.w_map;
+  a.cost.w_speed = c->cost.w_speed;
+  a.cost.w_slip = c->cost.w_slip;
+  a.cost.v_des = c->cost.v_des;
+  a.cost.crash_cost = c->cost.crash_cost;
+  a.cost.map_thresh = c->cost.map_thresh;
+  a.cost.slip_cost = c->cost.slip_cost;
+  a.cost.slip_thresh = c->cost.slip_thresh;
+  return a;
+}
+
+// Enqueue one iteration: rollout kernel, then weights/update kernel.
+mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0_dev) {
+  if (!c->have_map || !c->have_dyn)
+    return fail(c, MPPI_E_STATE, "set the cost map and the dynamics before iterating");
+  const int sched = c->schedule;
+  const int G = blocks_for(c, sched);
+  if (G > c->part_cap) return fail(c, MPPI_E_INVAL, "internal: %d partial blocks > capacity %d", G, c->part_cap);
+  RolloutArgs a = rollout_args(c, x0_host, x0_dev);
+  PendingTiming pt{};
+  if (c->timing) {
+    pt.e0 = take_event(c);
+    pt.e1 = take_event(c);
+    pt.e2 = take_event(c);
+    if (!pt.e0 || !pt.e1 || !pt.e2) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
+    HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
+  }
+  if (sched == MPPI_SCHED_WAVE) {
+    if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
+    hipLaunchKernelGGL(rollout_wave_kernel<32>, dim3(G), dim3(kWaveBlockThreads),
+                       wave_smem_bytes(c->cfg.T), c->stream, a);
+  } else if (c->hidden == 32) {
+    hipLaunchKernelGGL(rollout_lane_kernel<32>, dim3(G), dim3(kLaneBlockHost), 0, c->stream, a);
+  } else {
+    hipLaunchKernelGGL(rollout_lane_kernel<64>, dim3(G), dim3(kLaneBlockHost), 0, c->stream, a);
+  }
+  HIP_TRY(c, hipGetLastError());
+  if (c->timing) HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
+  MergeArgs m{};
+  m.part = c->d_part;
+  m.sg = c->d_sg;
+  m.U = c->d_U;
+  m.stats = c->d_stats;
+  m.status = c->d_status;
+  m.G = G;
+  m.T = c->cfg.T;
+  m.sg_window = c->cfg.sg_window;
+  m.inv_lambda = 1.0f / c->cfg.lambda;
+  hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(512), 0, c->stream, m, c->d_scale);
+  HIP_TRY(c, hipGetLastError());
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(pt.e2, c->stream));
+    c->pending.push_back(pt);
+    if (c->pending.size() >= 512) {
+      mppi_status st = drain_timing(c);
+      if (st != MPPI_OK) return st;
+    }
+  }
+  c->iter += 1;
+  return MPPI_OK;
+}
+
+mppi_status read_status(mppi_ctx* c) {
+  int st = 0;
+  HIP_TRY(c, hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (st == MPPI_E_NONFINITE) return fail(c, MPPI_E_NONFINITE, "no sample had a finite cost; U unchanged");
+  return MPPI_OK;
+}
+
+template <class F>
+mppi_status guarded(mppi_ctx* c, F&& fn) {
+  try {
+    return fn();
+  } catch (const std::bad_alloc&) {
+    return fail(c, MPPI_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c, MPPI_E_DEVICE, "unexpected internal error");
+  }
+}
+
+mppi_status launch_plant(mppi_ctx* c, const float* x_in_dev, const float* u_dev, float* x_out_dev,
+                         float* x_copy_dev) {
+  const mppi_config& g = c->cfg;
+  if (c->hidden == 32)
+    hipLaunchKernelGGL(plant_kernel<32>, dim3(1), dim3(64), 0, c->stream, c->d_params, x_in_dev, u_dev,
+                       x_out_dev, x_copy_dev, g.dt, g.u_lo[0], g.u_lo[1], g.u_hi[0], g.u_hi[1]);
+  else
+    hipLaunchKernelGGL(plant_kernel<64>, dim3(1), dim3(64), 0, c->stream, c->d_params, x_in_dev, u_dev,
+                       x_out_dev, x_copy_dev, g.dt, g.u_lo[0], g.u_lo[1], g.u_hi[0], g.u_hi[1]);
+  HIP_TRY(c, hipGetLastError());
+  return MPPI_OK;
+}
+
+void free_all(mppi_ctx* c) {
+  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_part, &c->d_scale,
+                    &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x};
+  for (float** b : bufs) {
+    if (*b) (void)hipFree(*b);
+    *b = nullptr;
+  }
+  if (c->d_status) (void)hipFree(c->d_status);
+  c->d_status = nullptr;
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.e0);
+    (void)hipEventDestroy(p.e1);
+    (void)hipEventDestroy(p.e2);
+  }
+  c->pending.clear();
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  c->event_pool.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mppi_last_error(const mppi_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int device, void* hip_stream,
+                        mppi_ctx** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, MPPI_E_INVAL, "out is NULL");
+  *out = nullptr;
+  mppi_status st = validate_config(cfg);
+  if (st != MPPI_OK) return st;
+  st = validate_cost(cost);
+  if (st != MPPI_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, MPPI_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, MPPI_E_INVAL, "device %d outside [0, %d)", device, ndev);
+  mppi_ctx* c = new (std::nothrow) mppi_ctx();
+  if (!c) return fail(nullptr, MPPI_E_NOMEM, "host allocation failed");
+  st = guarded(c, [&]() -> mppi_status {
+    c->cfg = *cfg;
+    c->cost = *cost;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    HIP_TRY(c, hipSetDevice(device));
+    const int K = cfg->K, T = cfg->T;
+    c->sig[0] = std::sqrt(cfg->sigma2[0]);
+    c->sig[1] = std::sqrt(cfg->sigma2[1]);
+    c->schedule = cfg->schedule;
+    c->part_cap = std::max(blocks_for(c, MPPI_SCHED_LANE), blocks_for(c, MPPI_SCHED_WAVE));
+    HIP_TRY(c, hipMalloc(&c->d_U, sizeof(float) * 2 * T));
+    HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
+    HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
+    HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
+    HIP_TRY(c, hipMalloc(&c->d_scale, sizeof(float) * (size_t)c->part_cap));
+    HIP_TRY(c, hipMalloc(&c->d_stats, sizeof(float) * (2 + 2 * T)));
+    HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(float) * (2 + 2 * T), c->stream));
+    HIP_TRY(c, hipMalloc(&c->d_status, sizeof(int)));
+    HIP_TRY(c, hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+    HIP_TRY(c, hipMalloc(&c->d_x, sizeof(float) * kStateDim));
+    HIP_TRY(c, hipMalloc(&c->d_u0, sizeof(float) * 2));
+    std::vector<float> decay(T + 1);
+    for (int t = 0; t <= T; ++t) decay[t] = (float)std::pow((double)cost->crash_decay, (double)t);
+    HIP_TRY(c, hipMalloc(&c->d_decay, sizeof(float) * (T + 1)));
+    HIP_TRY(c, hipMemcpy(c->d_decay, decay.data(), sizeof(float) * (T + 1), hipMemcpyHostToDevice));
+    if (cfg->sg_window > 1) {
+      std::vector<float> rows = savgol_rows(T, cfg->sg_window, cfg->sg_order);
+      HIP_TRY(c, hipMalloc(&c->d_sg, sizeof(float) * rows.size()));
+      HIP_TRY(c, hipMemcpy(c->d_sg, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MPPI_OK;
+  });
+  if (st != MPPI_OK) {
+    g_create_error = c->err;
+    free_all(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return MPPI_OK;
+}
+
+void mppi_destroy(mppi_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+}
+
+mppi_status mppi_set_costmap(mppi_ctx* c, const float* map, int32_t H, int32_t W, float origin_x,
+                             float origin_y, float resolution) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!map) return fail(c, MPPI_E_INVAL, "map is NULL");
+    if (H < 2 || W < 2 || (int64_t)H * W > (int64_t)1 << 30)
+      return fail(c, MPPI_E_INVAL, "map size %d x %d unsupported", H, W);
+    if (!finite(origin_x) || !finite(origin_y) || !finite(resolution) || !(resolution > 0))
+      return fail(c, MPPI_E_INVAL, "origin must be finite and resolution > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->d_map && (c->H != H || c->W != W)) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipFree(c->d_map));
+      c->d_map = nullptr;
+    }
+    if (!c->d_map) HIP_TRY(c, hipMalloc(&c->d_map, sizeof(float) * (size_t)H * W));
+    HIP_TRY(c, hipMemcpyAsync(c->d_map, map, sizeof(float) * (size_t)H * W, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->H = H;
+    c->W = W;
+    c->ox = origin_x;
+    c->oy = origin_y;
+    c->res = resolution;
+    c->have_map = true;
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* params) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!dims || !params) return fail(c, MPPI_E_INVAL, "dims or params is NULL");
+    const int h = dims[1];
+    if (dims[0] != 6 || dims[3] != 4 || dims[1] != dims[2] || (h != 32 && h != 64))
+      return fail(c, MPPI_E_INVAL, "dims must be {6, h, h, 4} with h = 32 or 64");
+    if (c->cfg.precision != MPPI_PREC_FP32)
+      return fail(c, MPPI_E_INVAL, "this build runs the FP32 network only");
+    if (c->cfg.schedule == MPPI_SCHED_WAVE && h != 32)
+      return fail(c, MPPI_E_INVAL, "the wave schedule supports h = 32 only");
+    const size_t n = (size_t)6 * h + h + (size_t)h * h + h + 4 * (size_t)h + 4;
+    for (size_t i = 0; i < n; ++i)
+      if (!finite(params[i])) return fail(c, MPPI_E_INVAL, "parameter %zu is not finite", i);
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->d_params && c->hidden != h) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipFree(c->d_params));
+      c->d_params = nullptr;
+    }
+    if (!c->d_params) HIP_TRY(c, hipMalloc(&c->d_params, sizeof(float) * n));
+    HIP_TRY(c, hipMemcpyAsync(c->d_params, params, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->hidden = h;
+    c->have_dyn = true;
+    if (c->cfg.schedule == MPPI_SCHED_AUTO)
+      c->schedule = (h == 32 && c->cfg.K <= kWaveAutoMaxK) ? MPPI_SCHED_WAVE : MPPI_SCHED_LANE;
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_set_controls(mppi_ctx* c, const float* U) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!U) return fail(c, MPPI_E_INVAL, "U is NULL");
+    for (int i = 0; i < 2 * c->cfg.T; ++i)
+      if (!finite(U[i])) return fail(c, MPPI_E_INVAL, "U[%d] is not finite", i);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(c->d_U, U, sizeof(float) * 2 * c->cfg.T, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_iterate(mppi_ctx* c, const float x0[7], float* costs_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x0) return fail(c, MPPI_E_INVAL, "x0 is NULL");
+    for (int i = 0; i < kStateDim; ++i)
+      if (!finite(x0[i])) return fail(c, MPPI_E_INVAL, "x0[%d] is not finite", i);
+    HIP_TRY(c, hipSetDevice(c->device));
+    mppi_status st = enqueue_iteration(c, x0, nullptr);
+    if (st != MPPI_OK) return st;
+    if (!costs_out) return MPPI_OK;
+    HIP_TRY(c, hipMemcpyAsync(costs_out, c->d_S, sizeof(float) * c->cfg.K, hipMemcpyDeviceToHost, c->stream));
+    return read_status(c);
+  });
+}
+
+mppi_status mppi_iterate_device(mppi_ctx* c, const float* x0_dev) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x0_dev) return fail(c, MPPI_E_INVAL, "x0_dev is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return enqueue_iteration(c, nullptr, x0_dev);
+  });
+}
+
+mppi_status mppi_get_controls(mppi_ctx* c, float* U_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!U_out) return fail(c, MPPI_E_INVAL, "U_out is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(U_out, c->d_U, sizeof(float) * 2 * c->cfg.T, hipMemcpyDeviceToHost, c->stream));
+    return read_status(c);
+  });
+}
+
+mppi_status mppi_shift(mppi_ctx* c, float u0_out[2]) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!u0_out) return fail(c, MPPI_E_INVAL, "u0_out is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(512), 0, c->stream, c->d_U, c->cfg.T, c->d_u0);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(u0_out, c->d_u0, sizeof(float) * 2, hipMemcpyDeviceToHost, c->stream));
+    return read_status(c);
+  });
+}
+
+mppi_status mppi_plant_step(mppi_ctx* c, const float x[7], const float u[2], float x_out[7]) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x || !u || !x_out) return fail(c, MPPI_E_INVAL, "NULL argument");
+    if (!c->have_dyn) return fail(c, MPPI_E_STATE, "set the dynamics first");
+    HIP_TRY(c, hipSetDevice(c->device));
+    float buf[9];
+    std::memcpy(buf, x, 7 * sizeof(float));
+    std::memcpy(buf + 7, u, 2 * sizeof(float));
+    // the device state buffer d_x (7) and d_u0 (2) are reused as staging
+    HIP_TRY(c, hipMemcpyAsync(c->d_x, buf, 7 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_u0, buf + 7, 2 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    mppi_status st = launch_plant(c, c->d_x, c->d_u0, c->d_x, nullptr);
+    if (st != MPPI_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(x_out, c->d_x, 7 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_run_receding(mppi_ctx* c, const float x0[7], int32_t n_iter, float* u_hist,
+                              float* x_hist) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x0 || n_iter < 0 || n_iter > (1 << 20)) return fail(c, MPPI_E_INVAL, "bad x0 or n_iter");
+    for (int i = 0; i < kStateDim; ++i)
+      if (!finite(x0[i])) return fail(c, MPPI_E_INVAL, "x0[%d] is not finite", i);
+    if (!c->have_map || !c->have_dyn) return fail(c, MPPI_E_STATE, "set the cost map and the dynamics first");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (n_iter + 1 > c->hist_cap) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      if (c->d_hist_u) HIP_TRY(c, hipFree(c->d_hist_u));
+      if (c->d_hist_x) HIP_TRY(c, hipFree(c->d_hist_x));
+      c->d_hist_u = c->d_hist_x = nullptr;
+      c->hist_cap = n_iter + 1;
+      HIP_TRY(c, hipMalloc(&c->d_hist_u, sizeof(float) * 2 * c->hist_cap));
+      HIP_TRY(c, hipMalloc(&c->d_hist_x, sizeof(float) * 7 * c->hist_cap));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_x, x0, 7 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_hist_x, x0, 7 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    int nonfinite = 0;
+    for (int i = 0; i < n_iter; ++i) {
+      mppi_status st = enqueue_iteration(c, nullptr, c->d_x);
+      if (st != MPPI_OK) return st;
+      hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(512), 0, c->stream, c->d_U, c->cfg.T, c->d_hist_u + 2 * i);
+      HIP_TRY(c, hipGetLastError());
+      st = launch_plant(c, c->d_x, c->d_hist_u + 2 * i, c->d_x, c->d_hist_x + 7 * (i + 1));
+      if (st != MPPI_OK) return st;
+    }
+    if (u_hist && n_iter > 0)
+      HIP_TRY(c, hipMemcpyAsync(u_hist, c->d_hist_u, sizeof(float) * 2 * n_iter, hipMemcpyDeviceToHost, c->stream));
+    if (x_hist)
+      HIP_TRY(c, hipMemcpyAsync(x_hist, c->d_hist_x, sizeof(float) * 7 * (n_iter + 1), hipMemcpyDeviceToHost, c->stream));
+    (void)nonfinite;
+    return read_status(c);
+  });
+}
+
+mppi_status mppi_get_stats(mppi_ctx* c, float* rho, float* eta, float* delta_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::vector<float> buf(2 + 2 * c->cfg.T);
+    HIP_TRY(c, hipMemcpyAsync(buf.data(), c->d_stats, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (rho) *rho = buf[0];
+    if (eta) *eta = buf[1];
+    if (delta_out) std::memcpy(delta_out, buf.data() + 2, sizeof(float) * 2 * c->cfg.T);
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_get_noise(mppi_ctx* c, uint32_t iter, float* eps_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!eps_out) return fail(c, MPPI_E_INVAL, "eps_out is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t n = (size_t)c->cfg.K * c->cfg.T;
+    float* d = nullptr;
+    HIP_TRY(c, hipMalloc(&d, sizeof(float) * 2 * n));
+    NoiseKey nk{(uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32), iter, c->cfg.instance, c->sig[0], c->sig[1]};
+    hipLaunchKernelGGL(noise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, nk, c->cfg.K,
+                       c->cfg.T, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(eps_out, d, sizeof(float) * 2 * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(c, MPPI_E_DEVICE, "noise dump: %s", hipGetErrorString(e));
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_get_iteration(const mppi_ctx* c, uint32_t* iter) {
+  if (!c || !iter) return MPPI_E_INVAL;
+  *iter = c->iter;
+  return MPPI_OK;
+}
+
+mppi_status mppi_set_iteration(mppi_ctx* c, uint32_t iter) {
+  if (!c) return MPPI_E_INVAL;
+  c->iter = iter;
+  return MPPI_OK;
+}
+
+mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
+  if (!c || !schedule) return MPPI_E_INVAL;
+  *schedule = c->schedule;
+  return MPPI_OK;
+}
+
+mppi_status mppi_set_timing(mppi_ctx* c, int32_t enable) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    mppi_status st = drain_timing(c);
+    if (st != MPPI_OK) return st;
+    c->timing = enable != 0;
+    c->t_ms[0] = c->t_ms[1] = 0;
+    c->t_cnt[0] = c->t_cnt[1] = 0;
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_get_timing(mppi_ctx* c, double times_ms[2], int64_t counts[2]) {
+  if (!c || !times_ms || !counts) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    mppi_status st = drain_timing(c);
+    if (st != MPPI_OK) return st;
+    times_ms[0] = c->t_ms[0];
+    times_ms[1] = c->t_ms[1];
+    counts[0] = c->t_cnt[0];
+    counts[1] = c->t_cnt[1];
+    return MPPI_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Kernel argument blocks shared by the host runtime and the HIP kernels.
+// Passed by value as kernel arguments (no constant-memory uploads per call).
+#pragma once
+
+#include <stdint.h>
+
+namespace mppi {
+
+constexpr int kStateDim = 7;
+constexpr int kCtrlDim = 2;
+constexpr int kNetIn = 6;
+constexpr int kNetOut = 4;
+constexpr int kTMax = 256;
+
+// Philox key and counter words that are fixed within one iteration, plus the
+// noise standard deviations sqrt(Sigma_ii) (FP32, correctly rounded on the host).
+struct NoiseKey {
+  uint32_t key_lo, key_hi;   // seed words
+  uint32_t iter;             // third counter word
+  uint32_t instance;         // fourth counter word
+  float sig0, sig1;
+};
+
+// Cost map geometry and state-cost weights.
+struct CostArgs {
+  int H, W;
+  float ox, oy, res;
+  float w_map, w_speed, w_slip, v_des;
+  float crash_cost, map_thresh, slip_cost, slip_thresh;
+};
+
+// One rollout launch: K samples, T steps, from x0 (by value, or read from x0_dev).
+struct RolloutArgs {
+  const float* U;          // [T][2] nominal controls
+  const float* map;        // [H][W]
+  const float* params;     // packed network parameters (FP32)
+  const float* decay;      // [T+1] fl32(crash_decay^t)
+  const float* x0_dev;     // nullable: read x0 from here instead of x0[]
+  float* S;                // [K] trajectory costs
+  float* part;             // [G][2 + 2T] per-block (rho_g, eta_g, N_g[T][2])
+  float x0[kStateDim];
+  int K, T;
+  float dt;
+  float inv_lambda;
+  float gcs0, gcs1;        // gamma / Sigma_ii (control-cost weights)
+  float u_lo0, u_lo1, u_hi0, u_hi1;
+  NoiseKey nk;
+  CostArgs cost;
+};
+
+// Merge of the per-block partials, Savitzky-Golay smoothing and the update of U.
+struct MergeArgs {
+  const float* part;       // [G][2 + 2T]
+  const float* sg;         // [T][sg_window] smoothing rows (null when window == 1)
+  float* U;                // [T][2], updated in place
+  float* stats;            // [2 + 2T]: rho, eta~, Delta[T][2]
+  int* status;             // 0 or MPPI_E_NONFINITE for this iteration
+  int G, T;
+  int sg_window;
+  float inv_lambda;
+};
+
+}  // namespace mppi

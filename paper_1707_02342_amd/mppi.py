@@ -1,0 +1,329 @@
+"""Thin ctypes binding of libmppi.so (include/mppi.h): argument marshalling only.
+
+Every computation of the MPPI iteration runs in the library's HIP kernels.
+There is no CPU fallback: if the library is not built, loading fails loudly.
+PyTorch is used, when present, only to hand the library a HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+from typing import Optional
+
+import numpy as np
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "libmppi.so"
+
+MPPI_OK, MPPI_E_INVAL, MPPI_E_STATE, MPPI_E_NOMEM, MPPI_E_DEVICE, MPPI_E_NONFINITE = range(6)
+MPPI_PREC_FP32, MPPI_PREC_BF16, MPPI_PREC_FP16 = 0, 1, 2
+MPPI_SCHED_AUTO, MPPI_SCHED_LANE, MPPI_SCHED_WAVE = 0, 1, 2
+MPPI_T_MAX = 256
+
+STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_NOMEM",
+                4: "MPPI_E_DEVICE", 5: "MPPI_E_NONFINITE"}
+
+# Every function the header declares; tests check that the library exports each.
+EXPORTED = [
+    "mppi_create", "mppi_destroy", "mppi_last_error", "mppi_set_costmap", "mppi_set_dynamics",
+    "mppi_set_controls", "mppi_iterate", "mppi_iterate_device", "mppi_get_controls", "mppi_shift",
+    "mppi_plant_step", "mppi_run_receding", "mppi_get_stats", "mppi_get_noise",
+    "mppi_get_iteration", "mppi_set_iteration", "mppi_get_schedule", "mppi_set_timing",
+    "mppi_get_timing",
+]
+
+
+class mppi_config(C.Structure):
+    _fields_ = [("K", C.c_int32), ("T", C.c_int32), ("dt", C.c_float), ("lam", C.c_float),
+                ("gamma", C.c_float), ("sigma2", C.c_float * 2), ("u_lo", C.c_float * 2),
+                ("u_hi", C.c_float * 2), ("sg_window", C.c_int32), ("sg_order", C.c_int32),
+                ("precision", C.c_int32), ("schedule", C.c_int32), ("seed", C.c_uint64),
+                ("instance", C.c_uint32)]
+
+
+class mppi_cost(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("w_map", "w_speed", "w_slip", "v_des", "crash_cost",
+                                         "crash_decay", "map_thresh", "slip_cost", "slip_thresh")]
+
+
+class MppiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libmppi.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1707_02342_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(str(LIB_PATH))
+        vp = C.c_void_p
+        fp = C.POINTER(C.c_float)
+        L.mppi_create.argtypes = [C.POINTER(mppi_config), C.POINTER(mppi_cost), C.c_int, vp, C.POINTER(vp)]
+        L.mppi_destroy.argtypes = [vp]
+        L.mppi_destroy.restype = None
+        L.mppi_last_error.argtypes = [vp]
+        L.mppi_last_error.restype = C.c_char_p
+        L.mppi_set_costmap.argtypes = [vp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float]
+        L.mppi_set_dynamics.argtypes = [vp, C.POINTER(C.c_int32), fp]
+        L.mppi_set_controls.argtypes = [vp, fp]
+        L.mppi_iterate.argtypes = [vp, fp, fp]
+        L.mppi_iterate_device.argtypes = [vp, vp]
+        L.mppi_get_controls.argtypes = [vp, fp]
+        L.mppi_shift.argtypes = [vp, fp]
+        L.mppi_plant_step.argtypes = [vp, fp, fp, fp]
+        L.mppi_run_receding.argtypes = [vp, fp, C.c_int32, fp, fp]
+        L.mppi_get_stats.argtypes = [vp, fp, fp, fp]
+        L.mppi_get_noise.argtypes = [vp, C.c_uint32, fp]
+        L.mppi_get_iteration.argtypes = [vp, C.POINTER(C.c_uint32)]
+        L.mppi_set_iteration.argtypes = [vp, C.c_uint32]
+        L.mppi_get_schedule.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.mppi_set_timing.argtypes = [vp, C.c_int32]
+        L.mppi_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for name in EXPORTED:
+            if name not in ("mppi_destroy", "mppi_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _f32(a, shape=None) -> np.ndarray:
+    out = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and out.shape != tuple(shape):
+        out = out.reshape(shape)
+    return out
+
+
+def _fp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+# ---------------------------------------------------------------------------
+# Same-named wrappers of the C entry points
+# ---------------------------------------------------------------------------
+
+def _check(ctx, st: int, allow=(MPPI_OK,)) -> int:
+    if st not in allow:
+        raise MppiError(st, mppi_last_error(ctx))
+    return st
+
+
+def mppi_last_error(ctx) -> str:
+    r = lib().mppi_last_error(ctx)
+    return r.decode() if r else ""
+
+
+def mppi_create(cfg: mppi_config, cost: mppi_cost, device: int = 0, stream: int = 0):
+    out = C.c_void_p()
+    st = lib().mppi_create(C.byref(cfg), C.byref(cost), device, C.c_void_p(stream or None), C.byref(out))
+    if st != MPPI_OK:
+        raise MppiError(st, mppi_last_error(None))
+    return out
+
+
+def mppi_destroy(ctx) -> None:
+    lib().mppi_destroy(ctx)
+
+
+def mppi_set_costmap(ctx, data, origin_x: float, origin_y: float, resolution: float) -> None:
+    m = _f32(data)
+    _check(ctx, lib().mppi_set_costmap(ctx, _fp(m), m.shape[0], m.shape[1], origin_x, origin_y, resolution))
+
+
+def mppi_set_dynamics(ctx, hidden: int, params) -> None:
+    dims = (C.c_int32 * 4)(6, hidden, hidden, 4)
+    p = _f32(params)
+    _check(ctx, lib().mppi_set_dynamics(ctx, dims, _fp(p)))
+
+
+def mppi_set_controls(ctx, U) -> None:
+    u = _f32(U)
+    _check(ctx, lib().mppi_set_controls(ctx, _fp(u)))
+
+
+def mppi_iterate(ctx, x0, costs_out: Optional[np.ndarray] = None) -> int:
+    x = _f32(x0)
+    return _check(ctx, lib().mppi_iterate(ctx, _fp(x), _fp(costs_out)), allow=(MPPI_OK, MPPI_E_NONFINITE))
+
+
+def mppi_iterate_device(ctx, x0_dev_ptr: int) -> None:
+    _check(ctx, lib().mppi_iterate_device(ctx, C.c_void_p(x0_dev_ptr)))
+
+
+def mppi_get_controls(ctx, T: int):
+    U = np.zeros((T, 2), dtype=np.float32)
+    st = _check(ctx, lib().mppi_get_controls(ctx, _fp(U)), allow=(MPPI_OK, MPPI_E_NONFINITE))
+    return U, st
+
+
+def mppi_shift(ctx):
+    u0 = np.zeros(2, dtype=np.float32)
+    st = _check(ctx, lib().mppi_shift(ctx, _fp(u0)), allow=(MPPI_OK, MPPI_E_NONFINITE))
+    return u0, st
+
+
+def mppi_plant_step(ctx, x, u):
+    xi = _f32(x)
+    ui = _f32(u)
+    xo = np.zeros(7, dtype=np.float32)
+    _check(ctx, lib().mppi_plant_step(ctx, _fp(xi), _fp(ui), _fp(xo)))
+    return xo
+
+
+def mppi_run_receding(ctx, x0, n_iter: int):
+    x = _f32(x0)
+    uh = np.zeros((n_iter, 2), dtype=np.float32)
+    xh = np.zeros((n_iter + 1, 7), dtype=np.float32)
+    st = _check(ctx, lib().mppi_run_receding(ctx, _fp(x), n_iter, _fp(uh), _fp(xh)),
+                allow=(MPPI_OK, MPPI_E_NONFINITE))
+    return uh, xh, st
+
+
+def mppi_get_stats(ctx, T: int):
+    rho, eta = C.c_float(), C.c_float()
+    d = np.zeros((T, 2), dtype=np.float32)
+    _check(ctx, lib().mppi_get_stats(ctx, C.byref(rho), C.byref(eta), _fp(d)))
+    return rho.value, eta.value, d
+
+
+def mppi_get_noise(ctx, it: int, K: int, T: int):
+    e = np.zeros((K, T, 2), dtype=np.float32)
+    _check(ctx, lib().mppi_get_noise(ctx, it, _fp(e)))
+    return e
+
+
+def mppi_get_iteration(ctx) -> int:
+    v = C.c_uint32()
+    _check(ctx, lib().mppi_get_iteration(ctx, C.byref(v)))
+    return v.value
+
+
+def mppi_set_iteration(ctx, it: int) -> None:
+    _check(ctx, lib().mppi_set_iteration(ctx, it))
+
+
+def mppi_get_schedule(ctx) -> int:
+    v = C.c_int32()
+    _check(ctx, lib().mppi_get_schedule(ctx, C.byref(v)))
+    return v.value
+
+
+def mppi_set_timing(ctx, enable: bool) -> None:
+    _check(ctx, lib().mppi_set_timing(ctx, 1 if enable else 0))
+
+
+def mppi_get_timing(ctx):
+    t = (C.c_double * 2)()
+    n = (C.c_int64 * 2)()
+    _check(ctx, lib().mppi_get_timing(ctx, t, n))
+    return (t[0], t[1]), (n[0], n[1])
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+
+def make_config(prob, precision: int = MPPI_PREC_FP32, schedule: int = MPPI_SCHED_AUTO) -> mppi_config:
+    c = mppi_config()
+    c.K, c.T = int(prob.K), int(prob.T)
+    c.dt, c.lam = prob.dt, prob.lam
+    c.gamma = prob.lam if getattr(prob, "gamma", None) is None else prob.gamma
+    c.sigma2[:] = list(prob.sigma2)
+    c.u_lo[:] = list(prob.u_lo)
+    c.u_hi[:] = list(prob.u_hi)
+    c.sg_window, c.sg_order = int(prob.sg_window), int(prob.sg_order)
+    c.precision, c.schedule = precision, schedule
+    c.seed = int(prob.seed)
+    c.instance = int(getattr(prob, "instance", 0))
+    return c
+
+
+def make_cost(cost) -> mppi_cost:
+    c = mppi_cost()
+    for f, _ in mppi_cost._fields_:
+        setattr(c, f, getattr(cost, f))
+    return c
+
+
+def current_stream() -> int:
+    """The HIP stream torch uses on the current device (0 when torch/GPU is absent)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # pragma: no cover
+        pass
+    return 0
+
+
+class Controller:
+    """One MPPI controller on one GPU (owns one library context)."""
+
+    def __init__(self, prob, cmap, params, device: int = 0, stream: Optional[int] = None,
+                 precision: int = MPPI_PREC_FP32, schedule: int = MPPI_SCHED_AUTO):
+        self.K, self.T, self.hidden = int(prob.K), int(prob.T), int(prob.hidden)
+        self.ctx = mppi_create(make_config(prob, precision, schedule), make_cost(prob.cost), device,
+                               current_stream() if stream is None else stream)
+        try:
+            mppi_set_costmap(self.ctx, cmap.data, cmap.origin_x, cmap.origin_y, cmap.resolution)
+            mppi_set_dynamics(self.ctx, self.hidden, params)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mppi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_controls(self, U):
+        mppi_set_controls(self.ctx, U)
+
+    def iterate(self, x0, want_costs: bool = False):
+        if want_costs:
+            S = np.zeros(self.K, dtype=np.float32)
+            st = mppi_iterate(self.ctx, x0, S)
+            return S, st
+        return None, mppi_iterate(self.ctx, x0)
+
+    def controls(self):
+        return mppi_get_controls(self.ctx, self.T)[0]
+
+    def shift(self):
+        return mppi_shift(self.ctx)[0]
+
+    def plant_step(self, x, u):
+        return mppi_plant_step(self.ctx, x, u)
+
+    def stats(self):
+        return mppi_get_stats(self.ctx, self.T)
+
+    def noise(self, it: int):
+        return mppi_get_noise(self.ctx, it, self.K, self.T)
+
+    @property
+    def iteration(self) -> int:
+        return mppi_get_iteration(self.ctx)
+
+    @iteration.setter
+    def iteration(self, it: int):
+        mppi_set_iteration(self.ctx, it)
+
+    @property
+    def schedule(self) -> int:
+        return mppi_get_schedule(self.ctx)

@@ -115,14 +115,25 @@ def ring_map(H: int = 256, W: int = 256, resolution: float = 0.1,
 
 
 def _ellipse_distance(px: np.ndarray, py: np.ndarray, cx: float, cy: float, a: float, b: float,
-                      n_samples: int = 40000) -> np.ndarray:
-    """Unsigned distance from points to an ellipse curve (nearest of a dense sampling)."""
-    from scipy.spatial import cKDTree
-    phi = np.linspace(0.0, 2.0 * np.pi, n_samples, endpoint=False)
-    curve = np.stack([cx + a * np.cos(phi), cy + b * np.sin(phi)], axis=1)
-    tree = cKDTree(curve)
-    d, _ = tree.query(np.stack([px.ravel(), py.ravel()], axis=1), workers=-1)
-    return d.reshape(px.shape)
+                      iters: int = 12) -> np.ndarray:
+    """Unsigned distance from points to the ellipse (cx + a cos phi, cy + b sin phi): Newton
+    on the stationarity condition of |curve(phi) - p|^2 from three starting angles, keeping
+    the nearest stationary point found."""
+    x = (px - cx).astype(np.float64)
+    y = (py - cy).astype(np.float64)
+    base = np.arctan2(a * y, b * x)
+    best = np.full(x.shape, np.inf)
+    for off in (0.0, 0.35, -0.35):
+        phi = base + off
+        for _ in range(iters):
+            c, s = np.cos(phi), np.sin(phi)
+            f = (a * a - b * b) * s * c - x * a * s + y * b * c
+            df = (a * a - b * b) * (c * c - s * s) - x * a * c - y * b * s
+            step = np.where(np.abs(df) > 1e-12, f / np.where(df == 0, 1.0, df), 0.0)
+            phi = phi - np.clip(step, -0.5, 0.5)
+        d = np.hypot(a * np.cos(phi) - x, b * np.sin(phi) - y)
+        best = np.minimum(best, d)
+    return best
 
 
 @functools.lru_cache(maxsize=2)
@@ -133,7 +144,13 @@ def ellipse_map(H: int = 2048, W: int = 2048, resolution: float = 0.05,
     walls blurred with a Gaussian (reflect) and clamped to [0, 1]."""
     res = np.float32(resolution)
     ys, xs = np.meshgrid(np.arange(H) * float(res), np.arange(W) * float(res), indexing="ij")
-    d = _ellipse_distance(xs, ys, center[0], center[1], semi_axes[0], semi_axes[1])
+    a, b = semi_axes
+    # A point at scaled-ellipse coordinate r lies at least |r - 1| * min(a, b) from the curve,
+    # so only the band |r - 1| <= (half_width + 1) / min(a, b) needs the distance solve.
+    r = np.hypot((xs - center[0]) / a, (ys - center[1]) / b)
+    band = np.abs(r - 1.0) <= (half_width + 1.0) / min(a, b)
+    d = np.full(xs.shape, np.inf)
+    d[band] = _ellipse_distance(xs[band], ys[band], center[0], center[1], a, b)
     mask = (d > half_width).astype(np.float64)
     data = _blur_clamp(mask, blur_sigma_cells)
     data.setflags(write=False)

@@ -1,0 +1,113 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, it exports every
+entry point include/mppi.h declares, the binding names match, and argument validation
+rejects bad input before any device work.  No compute call is made here."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = Path(__file__).resolve().parent.parent
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1707_02342_amd import mppi
+    if not mppi.LIB_PATH.exists():
+        from paper_1707_02342_amd import build
+        build.build()
+    mppi.lib()
+    return mppi
+
+
+def header_functions():
+    text = (ROOT / "include" / "mppi.h").read_text()
+    return sorted(set(re.findall(r"\b(mppi_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(M):
+    names = header_functions()
+    assert len(names) >= 15
+    L = M.lib()
+    for n in names:
+        assert hasattr(L, n), f"libmppi.so does not export {n}"
+    assert sorted(M.EXPORTED) == names
+    for n in names:
+        assert callable(getattr(M, n)), f"binding lacks {n}"
+
+
+def test_struct_layout_matches_header(M):
+    # int32 K, T; float dt, lambda, gamma, sigma2[2], u_lo[2], u_hi[2]; int32 sg_window, sg_order,
+    # precision, schedule; uint64 seed; uint32 instance  -> 15*4 + pad 4 + 8 + 4 + pad 4 = 80
+    assert C.sizeof(M.mppi_config) == 80
+    assert M.mppi_config.seed.offset == 64
+    assert C.sizeof(M.mppi_cost) == 36
+
+
+def _cfg(M, **kw):
+    c = M.make_config(synth.c1_problem())
+    for k, v in kw.items():
+        if k in ("sigma2", "u_lo", "u_hi"):
+            getattr(c, k)[:] = v
+        else:
+            setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("field,value", [
+    ("K", 0), ("K", -3), ("K", (1 << 22) + 1), ("T", 0), ("T", 257), ("dt", 0.0), ("dt", float("nan")),
+    ("lam", 0.0), ("lam", -1.0), ("lam", float("inf")), ("gamma", float("nan")),
+    ("sigma2", (0.0, 0.3)), ("sigma2", (0.3, -1.0)), ("sigma2", (float("inf"), 0.3)),
+    ("u_lo", (1.5, -1.0)), ("sg_window", 2), ("sg_window", 0), ("sg_window", 31),
+    ("sg_order", 1), ("precision", 7), ("schedule", 9),
+])
+def test_create_rejects_invalid_config(M, field, value):
+    cfg = _cfg(M, **{field: value})
+    out = C.c_void_p()
+    st = M.lib().mppi_create(C.byref(cfg), C.byref(M.make_cost(synth.c1_problem().cost)), 0, None, C.byref(out))
+    assert st == M.MPPI_E_INVAL
+    assert out.value is None
+    assert M.mppi_last_error(None) != ""
+
+
+def test_create_rejects_null_and_bad_cost(M):
+    out = C.c_void_p()
+    cfg = _cfg(M)
+    assert M.lib().mppi_create(None, None, 0, None, C.byref(out)) == M.MPPI_E_INVAL
+    cost = M.make_cost(synth.c1_problem().cost)
+    cost.w_map = float("nan")
+    assert M.lib().mppi_create(C.byref(cfg), C.byref(cost), 0, None, C.byref(out)) == M.MPPI_E_INVAL
+    assert M.lib().mppi_create(C.byref(cfg), C.byref(M.make_cost(synth.c1_problem().cost)), 0, None, None) \
+        == M.MPPI_E_INVAL
+
+
+def test_null_context_calls_are_rejected(M):
+    L = M.lib()
+    buf = np.zeros(16, np.float32)
+    p = buf.ctypes.data_as(C.POINTER(C.c_float))
+    assert L.mppi_iterate(None, p, None) == M.MPPI_E_INVAL
+    assert L.mppi_get_controls(None, p) == M.MPPI_E_INVAL
+    assert L.mppi_shift(None, p) == M.MPPI_E_INVAL
+    assert L.mppi_set_controls(None, p) == M.MPPI_E_INVAL
+    L.mppi_destroy(None)            # NULL-safe
+
+
+def test_valid_config_without_gpu_reports_device_error(M):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    out = C.c_void_p()
+    cfg = _cfg(M)
+    st = M.lib().mppi_create(C.byref(cfg), C.byref(M.make_cost(synth.c1_problem().cost)), 0, None, C.byref(out))
+    assert st == M.MPPI_E_DEVICE
+    assert "device" in M.mppi_last_error(None).lower()
+
+
+def test_binding_fails_loudly_without_library(M, monkeypatch, tmp_path):
+    monkeypatch.setattr(M, "_lib", None)
+    monkeypatch.setattr(M, "LIB_PATH", tmp_path / "missing.so")
+    with pytest.raises(ImportError):
+        M.lib()
