@@ -178,6 +178,24 @@ mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
 mppi_status mppi_set_timing(mppi_ctx* ctx, int32_t enable);
 mppi_status mppi_get_timing(mppi_ctx* ctx, double times_ms[2], int64_t counts[2]);
 
+/* Differentiation form.  The free-energy objective of Eq. FreeEnergy estimated with
+ * this iteration's K samples,
+ *   J = -lambda log((1/K) sum_k exp(-S_k/lambda)) = rho - lambda log(eta~/K),
+ * at the context's U and network, with the perturbations of iteration `iter` (the
+ * counter is not advanced and U is not changed).  The forward pass stores every
+ * sample's full state each `ckpt_every` steps (1..16) for the backward pass.
+ * Synchronises.  J_out and costs_out ([K]) may be NULL.  Requires h = 32.
+ * INVAL: ckpt_every outside [1, 16] or h != 32.  NONFINITE: no finite cost. */
+mppi_status mppi_objective(mppi_ctx* ctx, const float x0[7], uint32_t iter, int32_t ckpt_every,
+                           double* J_out, float* costs_out);
+
+/* Gradient of the last mppi_objective's J with respect to U (dJdU, [T][2]) and the
+ * network parameters (dJdtheta, packed like mppi_set_dynamics, 1412 floats), by an
+ * adjoint rollout that re-runs each checkpointed segment.  Either output may be NULL.
+ * Synchronises.  STATE: no objective evaluated since the last change of U, the
+ * network, the map or the last mppi_iterate. */
+mppi_status mppi_objective_backward(mppi_ctx* ctx, float* dJdU, float* dJdtheta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -166,6 +166,39 @@ __device__ __forceinline__ float state_cost(const CostArgs& c, const float* __re
   return cost;
 }
 
+// Gradient of the smooth part of c(x) with respect to (p_x, p_y, v_x, v_y): the
+// bilinear map's slope (zero where the lookup is clamped to the edge), the speed
+// term and the slip term; the impulse indicators are piecewise constant and
+// contribute nothing.
+__device__ __forceinline__ void state_cost_grad(const CostArgs& c, const float* __restrict__ map,
+                                                float px, float py, float vx, float vy, float& gpx,
+                                                float& gpy, float& gvx, float& gvy) {
+  float gx = (px - c.ox) / c.res;
+  float gy = (py - c.oy) / c.res;
+  gx = fminf(fmaxf(gx, -1.0f), (float)c.W);
+  gy = fminf(fmaxf(gy, -1.0f), (float)c.H);
+  const float fj = floorf(gx), fi = floorf(gy);
+  const int j0 = (int)fj, i0 = (int)fi;
+  const float fx = gx - fj, fy = gy - fi;
+  const int ja = min(max(j0, 0), c.W - 1), jb = min(max(j0 + 1, 0), c.W - 1);
+  const int ia = min(max(i0, 0), c.H - 1), ib = min(max(i0 + 1, 0), c.H - 1);
+  const float m00 = map[(size_t)ia * c.W + ja];
+  const float m01 = map[(size_t)ia * c.W + jb];
+  const float m10 = map[(size_t)ib * c.W + ja];
+  const float m11 = map[(size_t)ib * c.W + jb];
+  gpx = c.w_map * (((1.0f - fy) * (m01 - m00) + fy * (m11 - m10)) / c.res);
+  gpy = c.w_map * (((1.0f - fx) * (m10 - m00) + fx * (m11 - m01)) / c.res);
+  gvx = 2.0f * c.w_speed * (vx - c.v_des);
+  gvy = 0.0f;
+  const float den = vx * vx + vy * vy;
+  if (den > 0.0f) {
+    const float zeta = -atan2f(vy, fabsf(vx));
+    const float sgn = vx > 0.0f ? 1.0f : (vx < 0.0f ? -1.0f : 0.0f);
+    gvx += 2.0f * c.w_slip * zeta * (vy * sgn / den);
+    gvy += 2.0f * c.w_slip * zeta * (-fabsf(vx) / den);
+  }
+}
+
 __device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
 
 // Compensated accumulator: the value is hi + lo.  add() folds in the rounding error

@@ -50,6 +50,14 @@ __global__ __launch_bounds__(kMergeBlock) void merge_update_kernel(MergeArgs a, 
   }
   __syncthreads();
   const int w = a.sg_window;
+  if (!a.update_U) {
+    if (threadIdx.x == 0) {
+      *a.status = 0;
+      a.stats[0] = rho;
+      a.stats[1] = eta;
+    }
+    return;
+  }
   for (int o = threadIdx.x; o < 2 * a.T; o += kMergeBlock) {
     float upd;
     if (w == 1) {

@@ -30,74 +30,9 @@
 //
 // The network arithmetic of phase B is exactly the FP32 network of the lane
 // schedule with a different summation order.
-#include "kernels_common.hip.h"
+#include "wave_common.hip.h"
 
 namespace mppi {
-
-constexpr int kWaveBlock = 256;
-constexpr int kWaveSlots = 8;        // samples per block
-constexpr int kWaveNT = kTMax / 32;  // chunks of 32 steps
-
-__device__ __forceinline__ float as_f(uint32_t v) { return __builtin_bit_cast(float, v); }
-__device__ __forceinline__ uint32_t as_u(float v) { return __builtin_bit_cast(uint32_t, v); }
-
-// acc += src[dpp lane] * w, as one v_fmac_f32 with a DPP source operand.  The first
-// use after src was written is preceded by two wait states (VALU write -> DPP read).
-#define FMAC_DPP(acc, src, w, ctrl) \
-  asm volatile("v_fmac_f32_dpp %0, %1, %2 " ctrl " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(w))
-#define FMAC_DPP_FIRST(acc, src, w, ctrl)                                                        \
-  asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 " ctrl " row_mask:0xf bank_mask:0xf" : "+v"(acc) \
-      : "v"(src), "v"(w))
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return as_f((uint32_t)__builtin_amdgcn_mov_dpp((int)as_u(v), CTRL, 0xf, 0xf, true));
-}
-
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
-}
-
-constexpr int kRowRor = 0x120;        // row_ror:s = 0x120 + s
-constexpr int kQuadXor1 = 0xB1;       // quad_perm:[1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;       // quad_perm:[2,3,0,1]
-
-// Column (0..15) whose value lane `col` reads through row_ror:S.
-template <int S>
-__device__ __forceinline__ int ror_src(int col) {
-  return dpp_i<kRowRor + S>(col);
-}
-
-// Exchange between the two 16-lane rows of each 32-lane half: returns the pair
-// (new first operand, new second operand) of v_permlane16_swap.
-__device__ __forceinline__ void swap_rows(float& a, float& b) {
-  auto r = __builtin_amdgcn_permlane16_swap(as_u(a), as_u(b), false, false);
-  a = as_f(r[0]);
-  b = as_f(r[1]);
-}
-
-// Sum of v over the sample's two rows, the same bits in both rows.
-__device__ __forceinline__ float add_rows(float v) {
-  float x = v, y = v;
-  swap_rows(x, y);
-  return x + y;
-}
-
-__device__ __forceinline__ float scan32_incl(float v, int c32) {
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const float o = __shfl_up(v, d, 32);
-    if (c32 >= d) v += o;
-  }
-  return v;
-}
-
-__device__ __forceinline__ float sum32(float v) {
-#pragma unroll
-  for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
-  return v;
-}
 
 template <int HID>
 __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a) {
@@ -180,6 +115,8 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   }
   Acc xd{x0v[3 + comp], 0.0f};
   if (c32 < 4) sX[slot * T4 * 4 + c32] = x0v[3 + c32];
+  if (a.ckpt && valid && c32 < kStateDim)
+    a.ckpt[(size_t)k * (T / a.ckpt_every + 1) * kCkptStride + c32] = x0v[c32];
   __syncthreads();
 
   // ---- B: serial chain of the dynamic states ---------------------------------------
@@ -203,7 +140,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     float Q = __builtin_fmaf(wQ[0], h1, bQ);
     float P2 = wP[1] * dpp_f<kRowRor + 1>(h1);
     float Q2 = wQ[1] * dpp_f<kRowRor + 1>(h1);
-    FMAC_DPP(P, h1, wP[2], "row_ror:2");
+    FMAC_DPP_FIRST(P, h1, wP[2], "row_ror:2");
     FMAC_DPP(Q, h1, wQ[2], "row_ror:2");
     FMAC_DPP(P2, h1, wP[3], "row_ror:3");
     FMAC_DPP(Q2, h1, wQ[3], "row_ror:3");
@@ -276,6 +213,11 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       const float ipx = scan32_incl(dpx, c32);
       const float ipy = scan32_incl(dpy, c32);
       const float px1 = pxb + ipx, py1 = pyb + ipy, th1 = thb + ith;
+      if (act && a.ckpt && ((t + 1) % a.ckpt_every) == 0 && valid) {
+        float* cp = a.ckpt + ((size_t)k * (T / a.ckpt_every + 1) + (t + 1) / a.ckpt_every) * kCkptStride;
+        cp[0] = px1; cp[1] = py1; cp[2] = th1;
+        cp[3] = xn.x; cp[4] = xn.y; cp[5] = xn.z; cp[6] = xn.w;
+      }
       if (act) {
         Sacc.add(state_cost(a.cost, a.map, a.decay, px1, py1, xn.y, xn.z, t + 1));
         Sacc.add(a.gcs0 * (sU[2 * t] * ea[i]) + a.gcs1 * (sU[2 * t + 1] * eb[i]));

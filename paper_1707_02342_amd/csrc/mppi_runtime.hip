@@ -28,6 +28,10 @@ template <int HID>
 __global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
                              float, float, float);
 __global__ void noise_kernel(NoiseKey, int, int, float*);
+__global__ void adjoint_wave_kernel(AdjointArgs);
+__global__ void adjoint_reduce_kernel(const float*, int, int, const float*, float, float, float*);
+size_t adjoint_smem_bytes(int T, int ckpt_every);
+constexpr int kNP32Host = 1412;
 constexpr int kLaneBlockHost = 256;
 constexpr int kWaveSamplesPerBlock = 8;   // 4 waves x 2 samples of 32 lanes
 constexpr int kWaveBlockThreads = 256;
@@ -74,6 +78,13 @@ struct mppi_ctx {
   float* d_hist_u = nullptr;
   float* d_hist_x = nullptr;
   int hist_cap = 0;
+  float* d_ckpt = nullptr;    // objective checkpoints [K][n_ckpt][8]
+  float* d_gpart = nullptr;   // adjoint per-block partials
+  float* d_gout = nullptr;    // reduced gradient [1412 + 2T]
+  int ckpt_cap = 0;           // n_ckpt the checkpoint buffer holds
+  bool objective_ready = false;
+  int obj_ckpt_every = 0;
+  uint32_t obj_iter = 0;
   int part_cap = 0;          // partial rows allocated
   uint32_t iter = 0;
   int schedule = MPPI_SCHED_LANE;
@@ -227,6 +238,8 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   a.params = c->d_params;
   a.decay = c->d_decay;
   a.x0_dev = x0_dev;
+  a.ckpt = nullptr;
+  a.ckpt_every = 1;
   a.S = c->d_S;
   a.part = c->d_part;
   for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
@@ -269,6 +282,7 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   const int sched = c->schedule;
   const int G = blocks_for(c, sched);
   if (G > c->part_cap) return fail(c, MPPI_E_INVAL, "internal: %d partial blocks > capacity %d", G, c->part_cap);
+  c->objective_ready = false;
   RolloutArgs a = rollout_args(c, x0_host, x0_dev);
   PendingTiming pt{};
   if (c->timing) {
@@ -298,6 +312,7 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   m.G = G;
   m.T = c->cfg.T;
   m.sg_window = c->cfg.sg_window;
+  m.update_U = 1;
   m.inv_lambda = 1.0f / c->cfg.lambda;
   hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(512), 0, c->stream, m, c->d_scale);
   HIP_TRY(c, hipGetLastError());
@@ -347,7 +362,8 @@ mppi_status launch_plant(mppi_ctx* c, const float* x_in_dev, const float* u_dev,
 
 void free_all(mppi_ctx* c) {
   float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_part, &c->d_scale,
-                    &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x};
+                    &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x,
+                    &c->d_ckpt, &c->d_gpart, &c->d_gout};
   for (float** b : bufs) {
     if (*b) (void)hipFree(*b);
     *b = nullptr;
@@ -457,6 +473,7 @@ mppi_status mppi_set_costmap(mppi_ctx* c, const float* map, int32_t H, int32_t W
     if (!c->d_map) HIP_TRY(c, hipMalloc(&c->d_map, sizeof(float) * (size_t)H * W));
     HIP_TRY(c, hipMemcpyAsync(c->d_map, map, sizeof(float) * (size_t)H * W, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->objective_ready = false;
     c->H = H;
     c->W = W;
     c->ox = origin_x;
@@ -490,6 +507,7 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     if (!c->d_params) HIP_TRY(c, hipMalloc(&c->d_params, sizeof(float) * n));
     HIP_TRY(c, hipMemcpyAsync(c->d_params, params, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->objective_ready = false;
     c->hidden = h;
     c->have_dyn = true;
     if (c->cfg.schedule == MPPI_SCHED_AUTO)
@@ -507,6 +525,7 @@ mppi_status mppi_set_controls(mppi_ctx* c, const float* U) {
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipMemcpyAsync(c->d_U, U, sizeof(float) * 2 * c->cfg.T, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->objective_ready = false;
     return MPPI_OK;
   });
 }
@@ -688,6 +707,110 @@ mppi_status mppi_get_timing(mppi_ctx* c, double times_ms[2], int64_t counts[2]) 
     times_ms[1] = c->t_ms[1];
     counts[0] = c->t_cnt[0];
     counts[1] = c->t_cnt[1];
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_t ckpt_every,
+                           double* J_out, float* costs_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x0) return fail(c, MPPI_E_INVAL, "x0 is NULL");
+    for (int i = 0; i < kStateDim; ++i)
+      if (!finite(x0[i])) return fail(c, MPPI_E_INVAL, "x0[%d] is not finite", i);
+    if (ckpt_every < 1 || ckpt_every > 16) return fail(c, MPPI_E_INVAL, "ckpt_every=%d outside [1, 16]", ckpt_every);
+    if (!c->have_map || !c->have_dyn) return fail(c, MPPI_E_STATE, "set the cost map and the dynamics first");
+    if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "the objective gradient supports h = 32 only");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int K = c->cfg.K, T = c->cfg.T;
+    const int n_ckpt = T / ckpt_every + 1;
+    if (n_ckpt > c->ckpt_cap) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      if (c->d_ckpt) HIP_TRY(c, hipFree(c->d_ckpt));
+      c->d_ckpt = nullptr;
+      HIP_TRY(c, hipMalloc(&c->d_ckpt, sizeof(float) * (size_t)K * n_ckpt * kCkptStride));
+      c->ckpt_cap = n_ckpt;
+    }
+    const int G = blocks_for(c, MPPI_SCHED_WAVE);
+    const uint32_t saved_iter = c->iter;
+    c->iter = iter;
+    RolloutArgs a = rollout_args(c, x0, nullptr);
+    c->iter = saved_iter;
+    a.ckpt = c->d_ckpt;
+    a.ckpt_every = ckpt_every;
+    hipLaunchKernelGGL(rollout_wave_kernel<32>, dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+    MergeArgs m{};
+    m.part = c->d_part;
+    m.sg = c->d_sg;
+    m.U = c->d_U;
+    m.stats = c->d_stats;
+    m.status = c->d_status;
+    m.G = G;
+    m.T = T;
+    m.sg_window = c->cfg.sg_window;
+    m.update_U = 0;
+    m.inv_lambda = 1.0f / c->cfg.lambda;
+    hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(512), 0, c->stream, m, c->d_scale);
+    HIP_TRY(c, hipGetLastError());
+    float st2[2];
+    HIP_TRY(c, hipMemcpyAsync(st2, c->d_stats, sizeof(float) * 2, hipMemcpyDeviceToHost, c->stream));
+    if (costs_out) HIP_TRY(c, hipMemcpyAsync(costs_out, c->d_S, sizeof(float) * K, hipMemcpyDeviceToHost, c->stream));
+    mppi_status st = read_status(c);
+    if (st != MPPI_OK) return st;
+    if (J_out) *J_out = (double)st2[0] - (double)c->cfg.lambda * std::log((double)st2[1] / (double)K);
+    c->objective_ready = true;
+    c->obj_ckpt_every = ckpt_every;
+    c->obj_iter = iter;
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!c->objective_ready) return fail(c, MPPI_E_STATE, "evaluate mppi_objective first");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int K = c->cfg.K, T = c->cfg.T, C = c->obj_ckpt_every;
+    const int G = blocks_for(c, MPPI_SCHED_WAVE);
+    const size_t stride = (size_t)kNP32Host + 2 * T;
+    if (!c->d_gpart) {
+      HIP_TRY(c, hipMalloc(&c->d_gpart, sizeof(float) * (size_t)c->part_cap * stride));
+      HIP_TRY(c, hipMalloc(&c->d_gout, sizeof(float) * stride));
+    }
+    AdjointArgs a{};
+    RolloutArgs r = rollout_args(c, nullptr, nullptr);
+    a.U = c->d_U;
+    a.map = c->d_map;
+    a.params = c->d_params;
+    a.decay = c->d_decay;
+    a.S = c->d_S;
+    a.stats = c->d_stats;
+    a.ckpt = c->d_ckpt;
+    a.gpart = c->d_gpart;
+    a.K = K;
+    a.T = T;
+    a.ckpt_every = C;
+    a.n_ckpt = T / C + 1;
+    a.dt = c->cfg.dt;
+    a.inv_lambda = 1.0f / c->cfg.lambda;
+    a.u_lo0 = c->cfg.u_lo[0];
+    a.u_lo1 = c->cfg.u_lo[1];
+    a.u_hi0 = c->cfg.u_hi[0];
+    a.u_hi1 = c->cfg.u_hi[1];
+    a.nk = r.nk;
+    a.nk.iter = c->obj_iter;
+    a.cost = r.cost;
+    hipLaunchKernelGGL(adjoint_wave_kernel, dim3(G), dim3(kWaveBlockThreads), adjoint_smem_bytes(T, C), c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, c->stream,
+                       c->d_gpart, G, T, c->d_stats, r.gcs0, r.gcs1, c->d_gout);
+    HIP_TRY(c, hipGetLastError());
+    std::vector<float> out(stride);
+    HIP_TRY(c, hipMemcpyAsync(out.data(), c->d_gout, sizeof(float) * stride, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (dJdtheta) std::memcpy(dJdtheta, out.data(), sizeof(float) * kNP32Host);
+    if (dJdU) std::memcpy(dJdU, out.data() + kNP32Host, sizeof(float) * 2 * T);
     return MPPI_OK;
   });
 }

@@ -38,6 +38,8 @@ struct RolloutArgs {
   const float* x0_dev;     // nullable: read x0 from here instead of x0[]
   float* S;                // [K] trajectory costs
   float* part;             // [G][2 + 2T] per-block (rho_g, eta_g, N_g[T][2])
+  float* ckpt;             // nullable: [K][n_ckpt][8] full states every ckpt_every steps
+  int ckpt_every;
   float x0[kStateDim];
   int K, T;
   float dt;
@@ -57,7 +59,28 @@ struct MergeArgs {
   int* status;             // 0 or MPPI_E_NONFINITE for this iteration
   int G, T;
   int sg_window;
+  int update_U;            // 0: weights and Delta only (objective evaluation)
   float inv_lambda;
+};
+
+constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)
+
+// Adjoint of the free-energy objective J = rho - lambda log(eta~/K) through every
+// sample's rollout (one launch over all samples).
+struct AdjointArgs {
+  const float* U;
+  const float* map;
+  const float* params;
+  const float* decay;
+  const float* S;          // [K] costs of the forward pass
+  const float* stats;      // rho, eta~ of the forward pass
+  const float* ckpt;       // [K][n_ckpt][8]
+  float* gpart;            // [G][P + 2T] per-block gradient partials
+  int K, T, ckpt_every, n_ckpt;
+  float dt, inv_lambda;
+  float u_lo0, u_lo1, u_hi0, u_hi1;
+  NoiseKey nk;
+  CostArgs cost;
 };
 
 }  // namespace mppi

@@ -29,7 +29,7 @@ EXPORTED = [
     "mppi_set_controls", "mppi_iterate", "mppi_iterate_device", "mppi_get_controls", "mppi_shift",
     "mppi_plant_step", "mppi_run_receding", "mppi_get_stats", "mppi_get_noise",
     "mppi_get_iteration", "mppi_set_iteration", "mppi_get_schedule", "mppi_set_timing",
-    "mppi_get_timing",
+    "mppi_get_timing", "mppi_objective", "mppi_objective_backward",
 ]
 
 
@@ -86,6 +86,8 @@ def lib() -> C.CDLL:
         L.mppi_get_schedule.argtypes = [vp, C.POINTER(C.c_int32)]
         L.mppi_set_timing.argtypes = [vp, C.c_int32]
         L.mppi_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.mppi_objective.argtypes = [vp, fp, C.c_uint32, C.c_int32, C.POINTER(C.c_double), fp]
+        L.mppi_objective_backward.argtypes = [vp, fp, fp]
         for name in EXPORTED:
             if name not in ("mppi_destroy", "mppi_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -225,6 +227,21 @@ def mppi_get_timing(ctx):
     return (t[0], t[1]), (n[0], n[1])
 
 
+def mppi_objective(ctx, x0, it: int, ckpt_every: int = 10, K: Optional[int] = None):
+    x = _f32(x0)
+    J = C.c_double()
+    S = np.zeros(K, dtype=np.float32) if K else None
+    _check(ctx, lib().mppi_objective(ctx, _fp(x), it, ckpt_every, C.byref(J), _fp(S)))
+    return J.value, S
+
+
+def mppi_objective_backward(ctx, T: int, n_params: int = 1412):
+    gU = np.zeros((T, 2), dtype=np.float32)
+    gth = np.zeros(n_params, dtype=np.float32)
+    _check(ctx, lib().mppi_objective_backward(ctx, _fp(gU), _fp(gth)))
+    return gU, gth
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrapper
 # ---------------------------------------------------------------------------
@@ -327,3 +344,12 @@ class Controller:
     @property
     def schedule(self) -> int:
         return mppi_get_schedule(self.ctx)
+
+    def set_dynamics(self, params):
+        mppi_set_dynamics(self.ctx, self.hidden, params)
+
+    def objective(self, x0, it: int, ckpt_every: int = 10, want_costs: bool = False):
+        return mppi_objective(self.ctx, x0, it, ckpt_every, self.K if want_costs else None)
+
+    def objective_backward(self):
+        return mppi_objective_backward(self.ctx, self.T)
