@@ -132,7 +132,7 @@ def main():
                                "2048x2048 elliptical track map, SGF window 9",
                    "K": K, "T": T, "hidden": prob.hidden, "schedule": ctl.schedule},
         "latency_us": {"device_per_iteration": dev_ms * 1e3 / args.steps,
-                       "rollout_kernel": roll_ms * 1e3, "update_kernel": t_merge / max(n_merge, 1) * 1e3,
+                       "rollout_kernel": roll_ms * 1e3,
                        "host_p50": float(np.percentile(lat, 50)), "host_p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,

@@ -171,10 +171,12 @@ mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iter);
 /* Rollout schedule actually used (MPPI_SCHED_LANE or MPPI_SCHED_WAVE). */
 mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
 
-/* Per-kernel device time, measured with HIP events recorded on the context's
- * stream around every launch once enabled.  times_ms[0] = rollout kernel,
- * times_ms[1] = weights/update kernel, summed since the last reset; counts[0..1]
- * = launches.  Synchronises. */
+/* Device time of the iteration kernel, measured with HIP events recorded on the
+ * context's stream around every launch once enabled.  times_ms[0] = the rollout
+ * kernel (which also forms the weights and updates U in its last block), summed
+ * since the last reset; times_ms[1] is the time between the kernel's end event and
+ * a second event right after it (launch-gap probe, normally ~0); counts = launches.
+ * Synchronises. */
 mppi_status mppi_set_timing(mppi_ctx* ctx, int32_t enable);
 mppi_status mppi_get_timing(mppi_ctx* ctx, double times_ms[2], int64_t counts[2]);
 

@@ -151,6 +151,66 @@ __device__ __forceinline__ float costmap_at(const CostArgs& c, const float* __re
   return (1.0f - fy) * top + fy * bot;
 }
 
+// Exact sum and its rounding error (Knuth's two-sum).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Grid coordinate (p - o) / res of a position given as hi + lo, split into an integer
+// cell and a fraction in [0, 1) that keeps the low part: the quotient's rounding
+// remainder is exact (fma), so the fraction is good to ~1e-7 of a cell even where
+// the coordinate itself needs all 24 bits.  Clamped to [-1, n] like costmap_at.
+__device__ __forceinline__ void grid_coord(float ph, float pl, float o, float res, int n, int& i0,
+                                           float& f) {
+  float d, dl;
+  two_sum(ph, -o, d, dl);
+  dl = dl + pl;
+  float q = d / res;
+  const float rem = __builtin_fmaf(-q, res, d);
+  float ql = (rem + dl) / res;
+  if (!(q >= -1.0f)) { q = -1.0f; ql = 0.0f; }
+  if (!(q <= (float)n)) { q = (float)n; ql = 0.0f; }
+  const float fl = floorf(q);
+  i0 = (int)fl;
+  f = (q - fl) + ql;
+  if (f < 0.0f) { f += 1.0f; i0 -= 1; }
+  if (f >= 1.0f) { f -= 1.0f; i0 += 1; }
+}
+
+__device__ __forceinline__ float costmap_at2(const CostArgs& c, const float* __restrict__ map,
+                                             float pxh, float pxl, float pyh, float pyl) {
+  int j0, i0;
+  float fx, fy;
+  grid_coord(pxh, pxl, c.ox, c.res, c.W, j0, fx);
+  grid_coord(pyh, pyl, c.oy, c.res, c.H, i0, fy);
+  const int ja = min(max(j0, 0), c.W - 1), jb = min(max(j0 + 1, 0), c.W - 1);
+  const int ia = min(max(i0, 0), c.H - 1), ib = min(max(i0 + 1, 0), c.H - 1);
+  const float m00 = map[(size_t)ia * c.W + ja];
+  const float m01 = map[(size_t)ia * c.W + jb];
+  const float m10 = map[(size_t)ib * c.W + ja];
+  const float m11 = map[(size_t)ib * c.W + jb];
+  const float top = (1.0f - fx) * m00 + fx * m01;
+  const float bot = (1.0f - fx) * m10 + fx * m11;
+  return (1.0f - fy) * top + fy * bot;
+}
+
+// c(x, t) with the position as hi + lo pairs (see grid_coord).
+__device__ __forceinline__ float state_cost2(const CostArgs& c, const float* __restrict__ map,
+                                             const float* __restrict__ decay, float pxh, float pxl,
+                                             float pyh, float pyl, float vx, float vy, int t) {
+  const float h = costmap_at2(c, map, pxh, pxl, pyh, pyl);
+  float cost = c.w_map * h;
+  if (h > c.map_thresh) cost += c.crash_cost * decay[t];
+  const float dv = vx - c.v_des;
+  cost += c.w_speed * (dv * dv);
+  const float zeta = -atan2f(vy, fabsf(vx));
+  cost += c.w_slip * (zeta * zeta);
+  if (fabsf(zeta) > c.slip_thresh) cost += c.slip_cost;
+  return cost;
+}
+
 // c(x, t) on the post-step state: track (+ decaying impulse), speed, side slip.
 __device__ __forceinline__ float state_cost(const CostArgs& c, const float* __restrict__ map,
                                             const float* __restrict__ decay, float px, float py,

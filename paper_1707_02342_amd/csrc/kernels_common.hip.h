@@ -59,4 +59,127 @@ __device__ __forceinline__ float rel_weight(float S, float rho, float inv_lambda
   return (S < kInf && rho < kInf) ? expf(-(S - rho) * inv_lambda) : 0.0f;
 }
 
+constexpr int kMergeGroup = 16;
+constexpr int kStatusNonfinite = 5;
+
+// Merge n <= 16 partial rows (rho_g, eta_g, N_g[2T]) into one relative to
+// rho = min_g rho_g: eta = sum_g s_g eta_g, N = sum_g s_g N_g, s_g = exp(-(rho_g - rho)/lambda)
+// (s_g = 0 for a row without finite samples).  Called by the whole block; each thread
+// loads the n rows of its outputs at once, and sums them in row order.  The result
+// row goes to out_row (global) and/or out_lds.
+template <int NT>
+__device__ void merge_rows(const float* rows, int n, int stride, int T2, float inv_lambda,
+                           float* out_row, float* out_lds, float* s_small /* [2 * 16 + 2] */,
+                           float& rho_out, float& eta_out) {
+  const int tid = threadIdx.x;
+  if (tid < n) {
+    s_small[tid] = __builtin_nontemporal_load(rows + (size_t)tid * stride);
+    s_small[16 + tid] = __builtin_nontemporal_load(rows + (size_t)tid * stride + 1);
+  }
+  __syncthreads();
+  float rho = kInf;
+  for (int g = 0; g < n; ++g) rho = fminf(rho, s_small[g]);
+  __syncthreads();
+  if (tid < n) {
+    const float eg = s_small[16 + tid];
+    s_small[tid] = (eg > 0.0f) ? expf(-(s_small[tid] - rho) * inv_lambda) : 0.0f;
+  }
+  __syncthreads();
+  float eta = 0.0f;
+  for (int g = 0; g < n; ++g) eta = __builtin_fmaf(s_small[g], s_small[16 + g], eta);
+  for (int o = tid; o < T2; o += NT) {
+    float v[kMergeGroup];
+#pragma unroll
+    for (int g = 0; g < kMergeGroup; ++g)
+      v[g] = g < n ? __builtin_nontemporal_load(rows + (size_t)g * stride + 2 + o) : 0.0f;
+    float acc = 0.0f;
+#pragma unroll
+    for (int g = 0; g < kMergeGroup; ++g)
+      if (g < n) acc = __builtin_fmaf(s_small[g], v[g], acc);
+    if (out_row) out_row[2 + o] = acc;
+    if (out_lds) out_lds[o] = acc;
+  }
+  if (tid == 0 && out_row) {
+    out_row[0] = rho;
+    out_row[1] = eta;
+  }
+  rho_out = rho;
+  eta_out = eta;
+}
+
+// Called by every rollout block after writing its partial row.  Blocks arrive in
+// groups of 16; the last to arrive in a group merges the group's rows, and the last
+// group merger merges the group rows and applies Algorithm 2's normalisation, the
+// Savitzky-Golay smoothing and the update U <- U + SG * Delta.  Device-scope fences
+// order the rows written on one XCD before their reads on another.
+template <int NT>
+__device__ void finish_iteration(const RolloutArgs& a, float* lds /* >= 2T floats */) {
+  __shared__ unsigned s_flag;
+  __shared__ float s_small[2 * kMergeGroup + 2];
+  const int tid = threadIdx.x;
+  const int T2 = 2 * a.T;
+  const int stride = 2 + T2;
+  const int ngrp = (a.G + kMergeGroup - 1) / kMergeGroup;
+  const int grp = blockIdx.x / kMergeGroup;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const int n_in = min(kMergeGroup, a.G - grp * kMergeGroup);
+    s_flag = (atomicAdd(a.cnt + grp, 1u) == (unsigned)(n_in - 1)) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  float rho, eta;
+  const int n_in = min(kMergeGroup, a.G - grp * kMergeGroup);
+  merge_rows<NT>(a.part + (size_t)grp * kMergeGroup * stride, n_in, stride, T2, a.inv_lambda,
+                 a.part2 + (size_t)grp * stride, nullptr, s_small, rho, eta);
+  if (tid == 0) a.cnt[grp] = 0u;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_flag = (atomicAdd(a.cnt + ngrp, 1u) == (unsigned)(ngrp - 1)) ? 1u : 0u;
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, nullptr, lds, s_small, rho, eta);
+  if (tid == 0) a.cnt[ngrp] = 0u;
+  if (!(rho < kInf) || !(eta > 0.0f)) {
+    for (int o = tid; o < T2; o += NT) a.stats[2 + o] = 0.0f;
+    if (tid == 0) {
+      *a.status = kStatusNonfinite;
+      a.stats[0] = rho;
+      a.stats[1] = 0.0f;
+    }
+    return;
+  }
+  const float inv_eta = 1.0f / eta;
+  for (int o = tid; o < T2; o += NT) {
+    const float d = lds[o] * inv_eta;
+    lds[o] = d;
+    a.stats[2 + o] = d;
+  }
+  __syncthreads();
+  if (a.update_U) {
+    const int w = a.sg_window;
+    for (int o = tid; o < T2; o += NT) {
+      float upd;
+      if (w == 1) {
+        upd = lds[o];
+      } else {
+        const int t = o >> 1, c = o & 1;
+        const int lo = min(max(t - w / 2, 0), a.T - w);
+        const float* row = a.sg + (size_t)t * w;
+        upd = 0.0f;
+        for (int j = 0; j < w; ++j) upd = __builtin_fmaf(row[j], lds[2 * (lo + j) + c], upd);
+      }
+      a.Uout[o] = a.Uout[o] + upd;
+    }
+  }
+  if (tid == 0) {
+    *a.status = 0;
+    a.stats[0] = rho;
+    a.stats[1] = eta;
+  }
+}
+
 }  // namespace mppi

@@ -123,7 +123,8 @@ __global__ __launch_bounds__(kLaneBlock) void rollout_lane_kernel(RolloutArgs a)
       for (int i = 0; i < 4; ++i) x[3 + i].add(a.dt * f[i]);
 #pragma unroll
       for (int i = 0; i < kStateDim; ++i) ok = ok && finite_f(x[i].hi);
-      S.add(state_cost(a.cost, a.map, a.decay, x[0].value(), x[1].value(), x[4].value(), x[5].value(), t + 1));
+      S.add(state_cost2(a.cost, a.map, a.decay, x[0].hi, x[0].lo, x[1].hi, x[1].lo, x[4].value(),
+                        x[5].value(), t + 1));
       S.add(a.gcs0 * (u0 * e0) + a.gcs1 * (u1 * e1));
     }
     Sv = S.value();
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(kLaneBlock) void rollout_lane_kernel(RolloutArgs a)
     a.S[k] = Sv;
   }
   lane_block_partial(a, Sv, valid, k, red, scratch);
+  finish_iteration<kLaneBlock>(a, red);
 }
 
 template __global__ void rollout_lane_kernel<32>(RolloutArgs);

@@ -1,82 +1,8 @@
-// Weights, update, shift, plant step and the stand-alone noise generator.
-//
-// merge_update_kernel: Algorithm 2 and the update line of Algorithm 1 from the
-// rollout blocks' partials.  One workgroup: rho = min_g rho_g; per-block scale
-// s_g = exp(-(rho_g - rho)/lambda); eta~ = sum_g s_g eta_g; Delta_t = sum_g s_g N_g[t] / eta~;
-// U_t += sum_j SG[t][j] Delta_j.  If no sample had a finite cost the status is
-// NONFINITE and U is left unchanged (the shift of Section III-D-1 guarantees a
-// non-zero weight otherwise).
+// Shift, plant step and the stand-alone noise generator.  (Algorithm 2's weights and
+// the update of U run at the end of the rollout kernels, see finish_iteration.)
 #include "kernels_common.hip.h"
 
 namespace mppi {
-
-constexpr int kMergeBlock = 512;
-constexpr int kMergeWaves = kMergeBlock / 64;
-constexpr int kNonfinite = 5;
-
-__global__ __launch_bounds__(kMergeBlock) void merge_update_kernel(MergeArgs a, float* scale) {
-  __shared__ float scratch[kMergeWaves];
-  __shared__ float s_delta[2 * kTMax];
-  const int stride = 2 + 2 * a.T;
-  float m = kInf;
-  for (int g = threadIdx.x; g < a.G; g += kMergeBlock) m = fminf(m, a.part[(size_t)g * stride]);
-  const float rho = block_min<kMergeWaves>(m, scratch);
-  float es = 0.0f;
-  for (int g = threadIdx.x; g < a.G; g += kMergeBlock) {
-    const float rg = a.part[(size_t)g * stride];
-    const float eg = a.part[(size_t)g * stride + 1];
-    const float sc = (eg > 0.0f) ? expf(-(rg - rho) * a.inv_lambda) : 0.0f;
-    scale[g] = sc;
-    es = __builtin_fmaf(sc, eg, es);
-  }
-  const float eta = block_sum<kMergeWaves>(es, scratch);
-  if (!(rho < kInf) || !(eta > 0.0f)) {
-    if (threadIdx.x == 0) {
-      *a.status = kNonfinite;
-      a.stats[0] = rho;
-      a.stats[1] = 0.0f;
-    }
-    for (int o = threadIdx.x; o < 2 * a.T; o += kMergeBlock) a.stats[2 + o] = 0.0f;
-    return;
-  }
-  __syncthreads();   // scale[] written by other threads
-  const float inv_eta = 1.0f / eta;
-  for (int o = threadIdx.x; o < 2 * a.T; o += kMergeBlock) {
-    float acc = 0.0f;
-    for (int g = 0; g < a.G; ++g) acc = __builtin_fmaf(scale[g], a.part[(size_t)g * stride + 2 + o], acc);
-    const float d = acc * inv_eta;
-    s_delta[o] = d;
-    a.stats[2 + o] = d;
-  }
-  __syncthreads();
-  const int w = a.sg_window;
-  if (!a.update_U) {
-    if (threadIdx.x == 0) {
-      *a.status = 0;
-      a.stats[0] = rho;
-      a.stats[1] = eta;
-    }
-    return;
-  }
-  for (int o = threadIdx.x; o < 2 * a.T; o += kMergeBlock) {
-    float upd;
-    if (w == 1) {
-      upd = s_delta[o];
-    } else {
-      const int t = o >> 1, c = o & 1;
-      const int lo = min(max(t - w / 2, 0), a.T - w);
-      const float* row = a.sg + (size_t)t * w;
-      upd = 0.0f;
-      for (int j = 0; j < w; ++j) upd = __builtin_fmaf(row[j], s_delta[2 * (lo + j) + c], upd);
-    }
-    a.U[o] = a.U[o] + upd;
-  }
-  if (threadIdx.x == 0) {
-    *a.status = 0;
-    a.stats[0] = rho;
-    a.stats[1] = eta;
-  }
-}
 
 // Algorithm 1's last block: u0_out = u_0; u_{t-1} <- u_t; u_{T-1} <- Initialize = (0,0).
 __global__ __launch_bounds__(512) void shift_kernel(float* U, int T, float* u0_out) {

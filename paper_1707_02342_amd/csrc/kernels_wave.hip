@@ -101,14 +101,23 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   for (int i = 0; i < kStateDim; ++i) x0v[i] = a.x0_dev ? a.x0_dev[i] : a.x0[i];
 
   // ---- A: noise ---------------------------------------------------------------------
+  // (draws for steps past T use a clamped step index and are discarded; keeping the
+  // chunks free of branches lets the independent draws interleave)
   float ea[kWaveNT], eb[kWaveNT];
+  const int NT = (T + 31) >> 5;
+#pragma unroll
+  for (int i = 0; i < kWaveNT; ++i) {
+    ea[i] = 0.0f;
+    eb[i] = 0.0f;
+    if (i < NT) {
+      const int t = min(32 * i + c32, T - 1);
+      draw_eps((uint32_t)t, (uint32_t)k, a.nk, ea[i], eb[i]);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < kWaveNT; ++i) {
     const int t = 32 * i + c32;
-    ea[i] = 0.0f;
-    eb[i] = 0.0f;
-    if (t < T) {
-      draw_eps((uint32_t)t, (uint32_t)k, a.nk, ea[i], eb[i]);
+    if (i < NT && t < T) {
       myE[2 * t] = ea[i];
       myE[2 * t + 1] = eb[i];
     }
@@ -120,9 +129,14 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   __syncthreads();
 
   // ---- B: serial chain of the dynamic states ---------------------------------------
+  {
+  float2 u = *reinterpret_cast<const float2*>(sU);
+  float2 e = *reinterpret_cast<const float2*>(myE);
   for (int t = 0; t < T; ++t) {
-    const float2 u = *reinterpret_cast<const float2*>(sU + 2 * t);
-    const float2 e = *reinterpret_cast<const float2*>(myE + 2 * t);
+    // next step's control and noise are read one step ahead (LDS latency off the chain)
+    const int tn = min(t + 1, T - 1);
+    const float2 u_next = *reinterpret_cast<const float2*>(sU + 2 * tn);
+    const float2 e_next = *reinterpret_cast<const float2*>(myE + 2 * tn);
     const float vc0 = fminf(fmaxf(u.x + e.x, a.u_lo0), a.u_hi0);
     const float vc1 = fminf(fmaxf(u.y + e.y, a.u_lo1), a.u_hi1);
     // layer 1
@@ -185,51 +199,111 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     f = add_rows(f) + b3c;
     xd.add(a.dt * f);
     if (c32 < 4) sX[slot * T4 * 4 + (t + 1) * 4 + c32] = xd.value();
+    u = u_next;
+    e = e_next;
+  }
   }
   __syncthreads();
 
   // ---- C: kinematics and cost, parallel over t ---------------------------------------
-  float thb = x0v[2], pxb = x0v[0], pyb = x0v[1];
+  // Lane c owns the contiguous steps [c*npl, (c+1)*npl).  theta(t) = theta_0 + dt sum_{s<t}
+  // theta_dot(s) and p(t+1) = p_0 + dt sum_{s<=t} R(theta(s)) v(s) are formed as
+  // compensated lane sums plus compensated exclusive scans across the 32 lanes.
+  const int npl = (T + 31) >> 5;
+  const int tb = c32 * npl;
+  float th_h = 0.0f, th_l = 0.0f;
+  for (int q = 0; q < npl; ++q) {
+    const int t = tb + q;
+    if (t < T) {
+      float s_, e_;
+      two_sum(th_h, a.dt * myX[t].w, s_, e_);
+      th_h = s_;
+      th_l += e_;
+    }
+  }
+  scan32_excl2(th_h, th_l, c32);
+  {
+    float s_, e_;
+    two_sum(x0v[2], th_h, s_, e_);
+    th_h = s_;
+    th_l = th_l + e_;
+  }
+  // theta at the lane's first step; walk the steps for the position increments
+  float dpx[kWaveNT], dpy[kWaveNT];
+  float px_h = 0.0f, px_l = 0.0f, py_h = 0.0f, py_l = 0.0f;
+  {
+    float th = th_h, thl = th_l;
+#pragma unroll
+    for (int q = 0; q < kWaveNT; ++q) {
+      dpx[q] = 0.0f;
+      dpy[q] = 0.0f;
+      const int t = tb + q;
+      if (q < npl && t < T) {
+        const float4 xs = myX[t];
+        float sn, cs;
+        sincosf(th + thl, &sn, &cs);
+        dpx[q] = a.dt * (cs * xs.y - sn * xs.z);
+        dpy[q] = a.dt * (sn * xs.y + cs * xs.z);
+        float s_, e_;
+        two_sum(px_h, dpx[q], s_, e_);
+        px_h = s_;
+        px_l += e_;
+        two_sum(py_h, dpy[q], s_, e_);
+        py_h = s_;
+        py_l += e_;
+        two_sum(th, a.dt * xs.w, s_, e_);
+        th = s_;
+        thl += e_;
+      }
+    }
+  }
+  scan32_excl2(px_h, px_l, c32);
+  scan32_excl2(py_h, py_l, c32);
+  {
+    float s_, e_;
+    two_sum(x0v[0], px_h, s_, e_);
+    px_h = s_;
+    px_l += e_;
+    two_sum(x0v[1], py_h, s_, e_);
+    py_h = s_;
+    py_l += e_;
+  }
   Acc Sacc{0.0f, 0.0f};
   bool ok = true;
-  const int NT = (T + 31) >> 5;
+  {
+    float th = th_h, thl = th_l;
 #pragma unroll
-  for (int i = 0; i < kWaveNT; ++i) {
-    if (i < NT) {
-      const int t = 32 * i + c32;
-      const bool act = t < T;
-      const int tt = act ? t : 0;
-      const float4 xs = myX[tt];
-      const float4 xn = myX[tt + 1];
-      const float dth = act ? a.dt * xs.w : 0.0f;
-      const float ith = scan32_incl(dth, c32);
-      float eth = __shfl_up(ith, 1, 32);
-      if (c32 == 0) eth = 0.0f;
-      const float th = thb + eth;
-      float sn, cs;
-      sincosf(th, &sn, &cs);
-      const float dpx = act ? a.dt * (cs * xs.y - sn * xs.z) : 0.0f;
-      const float dpy = act ? a.dt * (sn * xs.y + cs * xs.z) : 0.0f;
-      const float ipx = scan32_incl(dpx, c32);
-      const float ipy = scan32_incl(dpy, c32);
-      const float px1 = pxb + ipx, py1 = pyb + ipy, th1 = thb + ith;
-      if (act && a.ckpt && ((t + 1) % a.ckpt_every) == 0 && valid) {
-        float* cp = a.ckpt + ((size_t)k * (T / a.ckpt_every + 1) + (t + 1) / a.ckpt_every) * kCkptStride;
-        cp[0] = px1; cp[1] = py1; cp[2] = th1;
-        cp[3] = xn.x; cp[4] = xn.y; cp[5] = xn.z; cp[6] = xn.w;
-      }
-      if (act) {
-        Sacc.add(state_cost(a.cost, a.map, a.decay, px1, py1, xn.y, xn.z, t + 1));
-        Sacc.add(a.gcs0 * (sU[2 * t] * ea[i]) + a.gcs1 * (sU[2 * t + 1] * eb[i]));
+    for (int q = 0; q < kWaveNT; ++q) {
+      const int t = tb + q;
+      if (q < npl && t < T) {
+        const float4 xs = myX[t];
+        const float4 xn = myX[t + 1];
+        float s_, e_;
+        two_sum(px_h, dpx[q], s_, e_);
+        px_h = s_;
+        px_l += e_;
+        two_sum(py_h, dpy[q], s_, e_);
+        py_h = s_;
+        py_l += e_;
+        two_sum(th, a.dt * xs.w, s_, e_);
+        th = s_;
+        thl += e_;
+        const float px1 = px_h + px_l, py1 = py_h + py_l, th1 = th + thl;
+        if (a.ckpt && ((t + 1) % a.ckpt_every) == 0 && valid) {
+          float* cp = a.ckpt + ((size_t)k * (T / a.ckpt_every + 1) + (t + 1) / a.ckpt_every) * kCkptStride;
+          cp[0] = px1; cp[1] = py1; cp[2] = th1;
+          cp[3] = xn.x; cp[4] = xn.y; cp[5] = xn.z; cp[6] = xn.w;
+        }
+        Sacc.add(state_cost2(a.cost, a.map, a.decay, px_h, px_l, py_h, py_l, xn.y, xn.z, t + 1));
+        Sacc.add(a.gcs0 * (sU[2 * t] * myE[2 * t]) + a.gcs1 * (sU[2 * t + 1] * myE[2 * t + 1]));
         ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1) && finite_f(xn.x) &&
              finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
       }
-      thb += __shfl(ith, 31, 32);
-      pxb += __shfl(ipx, 31, 32);
-      pyb += __shfl(ipy, 31, 32);
     }
   }
-  float S = sum32(Sacc.value());
+  float S_h = Sacc.hi, S_l = Sacc.lo;
+  sum32_2(S_h, S_l);
+  float S = S_h + S_l;
   int okc = ok ? 1 : 0;
 #pragma unroll
   for (int m = 16; m >= 1; m >>= 1) okc &= __shfl_xor(okc, m, 32);
@@ -267,6 +341,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     out[0] = rho;
     out[1] = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
   }
+  finish_iteration<kWaveBlock>(a, red);
 }
 
 template __global__ void rollout_wave_kernel<32>(RolloutArgs);

@@ -2,7 +2,7 @@
 //
 // The context owns every device buffer, binds one HIP stream, validates every
 // argument before anything is enqueued, and launches the rollout kernel (one
-// of two schedules) followed by the merge/update kernel for each iteration.
+// of two schedules) per iteration; its last block forms the weights and updates U.
 // No C++ exception escapes: every entry point catches and maps to a status.
 #include <hip/hip_runtime.h>
 
@@ -22,7 +22,6 @@ namespace mppi {
 template <int HID> __global__ void rollout_lane_kernel(RolloutArgs);
 template <int HID> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T);
-__global__ void merge_update_kernel(MergeArgs, float*);
 __global__ void shift_kernel(float*, int, float*);
 template <int HID>
 __global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
@@ -69,7 +68,8 @@ struct mppi_ctx {
   float* d_decay = nullptr;
   float* d_S = nullptr;
   float* d_part = nullptr;
-  float* d_scale = nullptr;
+  float* d_part2 = nullptr;
+  unsigned* d_cnt = nullptr;
   float* d_stats = nullptr;
   float* d_sg = nullptr;
   float* d_x = nullptr;      // [7] device-resident state for the receding loop
@@ -240,6 +240,15 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   a.x0_dev = x0_dev;
   a.ckpt = nullptr;
   a.ckpt_every = 1;
+  a.part2 = c->d_part2;
+  a.cnt = c->d_cnt;
+  a.sg = c->d_sg;
+  a.Uout = c->d_U;
+  a.stats = c->d_stats;
+  a.status = c->d_status;
+  a.G = 0;
+  a.sg_window = c->cfg.sg_window;
+  a.update_U = 1;
   a.S = c->d_S;
   a.part = c->d_part;
   for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
@@ -284,6 +293,7 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   if (G > c->part_cap) return fail(c, MPPI_E_INVAL, "internal: %d partial blocks > capacity %d", G, c->part_cap);
   c->objective_ready = false;
   RolloutArgs a = rollout_args(c, x0_host, x0_dev);
+  a.G = G;
   PendingTiming pt{};
   if (c->timing) {
     pt.e0 = take_event(c);
@@ -302,21 +312,8 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
     hipLaunchKernelGGL(rollout_lane_kernel<64>, dim3(G), dim3(kLaneBlockHost), 0, c->stream, a);
   }
   HIP_TRY(c, hipGetLastError());
-  if (c->timing) HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
-  MergeArgs m{};
-  m.part = c->d_part;
-  m.sg = c->d_sg;
-  m.U = c->d_U;
-  m.stats = c->d_stats;
-  m.status = c->d_status;
-  m.G = G;
-  m.T = c->cfg.T;
-  m.sg_window = c->cfg.sg_window;
-  m.update_U = 1;
-  m.inv_lambda = 1.0f / c->cfg.lambda;
-  hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(512), 0, c->stream, m, c->d_scale);
-  HIP_TRY(c, hipGetLastError());
   if (c->timing) {
+    HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
     HIP_TRY(c, hipEventRecord(pt.e2, c->stream));
     c->pending.push_back(pt);
     if (c->pending.size() >= 512) {
@@ -361,7 +358,7 @@ mppi_status launch_plant(mppi_ctx* c, const float* x_in_dev, const float* u_dev,
 }
 
 void free_all(mppi_ctx* c) {
-  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_part, &c->d_scale,
+  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_part, &c->d_part2,
                     &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x,
                     &c->d_ckpt, &c->d_gpart, &c->d_gout};
   for (float** b : bufs) {
@@ -370,6 +367,8 @@ void free_all(mppi_ctx* c) {
   }
   if (c->d_status) (void)hipFree(c->d_status);
   c->d_status = nullptr;
+  if (c->d_cnt) (void)hipFree(c->d_cnt);
+  c->d_cnt = nullptr;
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
@@ -418,7 +417,10 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
-    HIP_TRY(c, hipMalloc(&c->d_scale, sizeof(float) * (size_t)c->part_cap));
+    const int ngrp_cap = (c->part_cap + 15) / 16;
+    HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)ngrp_cap * (2 + 2 * T)));
+    HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(unsigned) * (ngrp_cap + 1)));
+    HIP_TRY(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (ngrp_cap + 1), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_stats, sizeof(float) * (2 + 2 * T)));
     HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(float) * (2 + 2 * T), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_status, sizeof(int)));
@@ -738,20 +740,9 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
     c->iter = saved_iter;
     a.ckpt = c->d_ckpt;
     a.ckpt_every = ckpt_every;
+    a.G = G;
+    a.update_U = 0;
     hipLaunchKernelGGL(rollout_wave_kernel<32>, dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), c->stream, a);
-    HIP_TRY(c, hipGetLastError());
-    MergeArgs m{};
-    m.part = c->d_part;
-    m.sg = c->d_sg;
-    m.U = c->d_U;
-    m.stats = c->d_stats;
-    m.status = c->d_status;
-    m.G = G;
-    m.T = T;
-    m.sg_window = c->cfg.sg_window;
-    m.update_U = 0;
-    m.inv_lambda = 1.0f / c->cfg.lambda;
-    hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(512), 0, c->stream, m, c->d_scale);
     HIP_TRY(c, hipGetLastError());
     float st2[2];
     HIP_TRY(c, hipMemcpyAsync(st2, c->d_stats, sizeof(float) * 2, hipMemcpyDeviceToHost, c->stream));

@@ -38,6 +38,15 @@ struct RolloutArgs {
   const float* x0_dev;     // nullable: read x0 from here instead of x0[]
   float* S;                // [K] trajectory costs
   float* part;             // [G][2 + 2T] per-block (rho_g, eta_g, N_g[T][2])
+  float* part2;            // [ceil(G/16)][2 + 2T] per-group merges
+  unsigned* cnt;           // [ceil(G/16) + 1] arrival counters, zero between launches
+  const float* sg;         // [T][sg_window] smoothing rows (null when window == 1)
+  float* Uout;             // [T][2], updated in place by the last block
+  float* stats;            // [2 + 2T]: rho, eta~, Delta[T][2]
+  int* status;             // 0 or MPPI_E_NONFINITE for this iteration
+  int G;                   // blocks of this launch
+  int sg_window;
+  int update_U;            // 0: weights and Delta only (objective evaluation)
   float* ckpt;             // nullable: [K][n_ckpt][8] full states every ckpt_every steps
   int ckpt_every;
   float x0[kStateDim];
@@ -48,19 +57,6 @@ struct RolloutArgs {
   float u_lo0, u_lo1, u_hi0, u_hi1;
   NoiseKey nk;
   CostArgs cost;
-};
-
-// Merge of the per-block partials, Savitzky-Golay smoothing and the update of U.
-struct MergeArgs {
-  const float* part;       // [G][2 + 2T]
-  const float* sg;         // [T][sg_window] smoothing rows (null when window == 1)
-  float* U;                // [T][2], updated in place
-  float* stats;            // [2 + 2T]: rho, eta~, Delta[T][2]
-  int* status;             // 0 or MPPI_E_NONFINITE for this iteration
-  int G, T;
-  int sg_window;
-  int update_U;            // 0: weights and Delta only (objective evaluation)
-  float inv_lambda;
 };
 
 constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)

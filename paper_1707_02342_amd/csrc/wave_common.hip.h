@@ -66,6 +66,38 @@ __device__ __forceinline__ float scan32_incl(float v, int c32) {
   return v;
 }
 
+// Compensated exclusive scan of (hi, lo) pairs over the 32 lanes of a half-wave.
+__device__ __forceinline__ void scan32_excl2(float& hi, float& lo, int c32) {
+#pragma unroll
+  for (int d = 1; d < 32; d <<= 1) {
+    const float oh = __shfl_up(hi, d, 32);
+    const float ol = __shfl_up(lo, d, 32);
+    if (c32 >= d) {
+      float s_, e_;
+      two_sum(hi, oh, s_, e_);
+      hi = s_;
+      lo = lo + (ol + e_);
+    }
+  }
+  const float ph = __shfl_up(hi, 1, 32);
+  const float pl = __shfl_up(lo, 1, 32);
+  hi = c32 == 0 ? 0.0f : ph;
+  lo = c32 == 0 ? 0.0f : pl;
+}
+
+// Compensated sum of (hi, lo) over the 32 lanes, the same bits in every lane.
+__device__ __forceinline__ void sum32_2(float& hi, float& lo) {
+#pragma unroll
+  for (int m = 16; m >= 1; m >>= 1) {
+    const float oh = __shfl_xor(hi, m, 32);
+    const float ol = __shfl_xor(lo, m, 32);
+    float s_, e_;
+    two_sum(hi, oh, s_, e_);
+    hi = s_;
+    lo = (lo + ol) + e_;
+  }
+}
+
 __device__ __forceinline__ float sum32(float v) {
 #pragma unroll
   for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
