@@ -198,6 +198,39 @@ mppi_status mppi_objective(mppi_ctx* ctx, const float x0[7], uint32_t iter, int3
  * network, the map or the last mppi_iterate. */
 mppi_status mppi_objective_backward(mppi_ctx* ctx, float* dJdU, float* dJdtheta);
 
+/* Batched form: n independent MPPI problems (instances) that share one cost map,
+ * one cost and one FP32 6-32-32-4 network, each with its own K_i, T_i, x0, U and
+ * iteration counter, advanced together by one persistent kernel launch per
+ * mppi_batch_iterate (replayed from a HIP graph).  Instance i draws its noise with
+ * Philox counter word 4 = cfg->instance + i, so it reproduces, bit for bit, a
+ * single-problem context with K_i, T_i and that instance word.  cfg->K and cfg->T
+ * are ignored.  The first iterate times several launch schedules (grid size and
+ * work order) on the real problem and keeps the fastest; U and the counters are
+ * restored afterwards and every schedule gives the same results.  With a NULL
+ * stream the batch creates its own (graph capture needs a non-null stream).
+ * INVAL: n outside [1, 65536], an instance's K/T invalid (as in mppi_config), or
+ * a precision other than FP32. */
+typedef struct mppi_batch mppi_batch;
+mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int32_t n, const int32_t* K,
+                              const int32_t* T, int device, void* hip_stream, mppi_batch** out);
+void mppi_batch_destroy(mppi_batch* b);
+const char* mppi_batch_last_error(const mppi_batch* b);
+mppi_status mppi_batch_set_costmap(mppi_batch* b, const float* map, int32_t H, int32_t W, float origin_x,
+                                   float origin_y, float resolution);
+/* dims must be {6, 32, 32, 4}. */
+mppi_status mppi_batch_set_dynamics(mppi_batch* b, const int32_t dims[4], const float* params);
+/* Instance i's nominal controls ([T_i][2]); every instance starts at 0. */
+mppi_status mppi_batch_set_controls(mppi_batch* b, int32_t i, const float* U);
+/* One iteration of every instance from x0 ([n][7], host).  Enqueued. */
+mppi_status mppi_batch_iterate(mppi_batch* b, const float* x0);
+/* Instance i's controls ([T_i][2]) / costs of its last iteration ([K_i]).  Synchronise. */
+mppi_status mppi_batch_get_controls(mppi_batch* b, int32_t i, float* U_out);
+mppi_status mppi_batch_get_costs(mppi_batch* b, int32_t i, float* S_out);
+/* The schedule the autotuner chose: persistent grid size, work order (0 = by
+ * instance, 1 = longest horizon first) and its measured time per launch. */
+mppi_status mppi_batch_get_schedule(mppi_batch* b, int32_t* grid, int32_t* order, double* tuned_us);
+mppi_status mppi_batch_synchronize(mppi_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,79 +107,74 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
   eta_out = eta;
 }
 
-// Called by every rollout block after writing its partial row.  Blocks arrive in
-// groups of 16; the last to arrive in a group merges the group's rows, and the last
-// group merger merges the group rows and applies Algorithm 2's normalisation, the
-// Savitzky-Golay smoothing and the update U <- U + SG * Delta.  Device-scope fences
-// order the rows written on one XCD before their reads on another.
+// Called by every rollout block after writing its partial row (tile = the block's
+// index among the launch's blocks of this problem).  Blocks arrive in groups of 16;
+// the last to arrive in a group merges the group's rows, and the last group merger
+// merges the group rows and applies Algorithm 2's normalisation, the Savitzky-Golay
+// smoothing and the update U <- U + SG * Delta.  Device-scope fences order the rows
+// written on one XCD before their reads on another.  Every decision is uniform over
+// the block, so all barriers are reached by all threads.
 template <int NT>
-__device__ void finish_iteration(const RolloutArgs& a, float* lds /* >= 2T floats */) {
+__device__ void finish_iteration(const RolloutArgs& a, int tile, float* lds /* >= 2T floats */) {
   __shared__ unsigned s_flag;
   __shared__ float s_small[2 * kMergeGroup + 2];
   const int tid = threadIdx.x;
   const int T2 = 2 * a.T;
   const int stride = 2 + T2;
   const int ngrp = (a.G + kMergeGroup - 1) / kMergeGroup;
-  const int grp = blockIdx.x / kMergeGroup;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const int n_in = min(kMergeGroup, a.G - grp * kMergeGroup);
-    s_flag = (atomicAdd(a.cnt + grp, 1u) == (unsigned)(n_in - 1)) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
-  float rho, eta;
+  const int grp = tile / kMergeGroup;
   const int n_in = min(kMergeGroup, a.G - grp * kMergeGroup);
-  merge_rows<NT>(a.part + (size_t)grp * kMergeGroup * stride, n_in, stride, T2, a.inv_lambda,
-                 a.part2 + (size_t)grp * stride, nullptr, s_small, rho, eta);
-  if (tid == 0) a.cnt[grp] = 0u;
   __threadfence();
   __syncthreads();
-  if (tid == 0) s_flag = (atomicAdd(a.cnt + ngrp, 1u) == (unsigned)(ngrp - 1)) ? 1u : 0u;
+  if (tid == 0) s_flag = (atomicAdd(a.cnt + grp, 1u) == (unsigned)(n_in - 1)) ? 1u : 0u;
   __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
-  merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, nullptr, lds, s_small, rho, eta);
-  if (tid == 0) a.cnt[ngrp] = 0u;
-  if (!(rho < kInf) || !(eta > 0.0f)) {
-    for (int o = tid; o < T2; o += NT) a.stats[2 + o] = 0.0f;
-    if (tid == 0) {
-      *a.status = kStatusNonfinite;
-      a.stats[0] = rho;
-      a.stats[1] = 0.0f;
-    }
-    return;
-  }
-  const float inv_eta = 1.0f / eta;
-  for (int o = tid; o < T2; o += NT) {
-    const float d = lds[o] * inv_eta;
-    lds[o] = d;
-    a.stats[2 + o] = d;
-  }
-  __syncthreads();
-  if (a.update_U) {
-    const int w = a.sg_window;
-    for (int o = tid; o < T2; o += NT) {
-      float upd;
-      if (w == 1) {
-        upd = lds[o];
-      } else {
-        const int t = o >> 1, c = o & 1;
-        const int lo = min(max(t - w / 2, 0), a.T - w);
-        const float* row = a.sg + (size_t)t * w;
-        upd = 0.0f;
-        for (int j = 0; j < w; ++j) upd = __builtin_fmaf(row[j], lds[2 * (lo + j) + c], upd);
+  if (s_flag) {
+    __threadfence();
+    float rho, eta;
+    merge_rows<NT>(a.part + (size_t)grp * kMergeGroup * stride, n_in, stride, T2, a.inv_lambda,
+                   a.part2 + (size_t)grp * stride, nullptr, s_small, rho, eta);
+    if (tid == 0) a.cnt[grp] = 0u;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_flag = (atomicAdd(a.cnt + ngrp, 1u) == (unsigned)(ngrp - 1)) ? 1u : 0u;
+    __syncthreads();
+    if (s_flag) {
+      __threadfence();
+      merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, nullptr, lds, s_small, rho, eta);
+      if (tid == 0) a.cnt[ngrp] = 0u;
+      const bool fin = (rho < kInf) && (eta > 0.0f);
+      const float inv_eta = fin ? 1.0f / eta : 0.0f;
+      for (int o = tid; o < T2; o += NT) {
+        const float d = lds[o] * inv_eta;
+        lds[o] = d;
+        a.stats[2 + o] = d;
       }
-      a.Uout[o] = a.Uout[o] + upd;
+      __syncthreads();
+      if (fin && a.update_U) {
+        const int w = a.sg_window;
+        for (int o = tid; o < T2; o += NT) {
+          float upd;
+          if (w == 1) {
+            upd = lds[o];
+          } else {
+            const int t = o >> 1, c = o & 1;
+            const int lo = min(max(t - w / 2, 0), a.T - w);
+            const float* row = a.sg + (size_t)t * w;
+            upd = 0.0f;
+            for (int j = 0; j < w; ++j) upd = __builtin_fmaf(row[j], lds[2 * (lo + j) + c], upd);
+          }
+          a.Uout[o] = a.Uout[o] + upd;
+        }
+      }
+      if (tid == 0) {
+        *a.status = fin ? 0 : kStatusNonfinite;
+        a.stats[0] = rho;
+        a.stats[1] = fin ? eta : 0.0f;
+        if (a.iter_dev) *a.iter_dev = *a.iter_dev + 1u;
+      }
     }
   }
-  if (tid == 0) {
-    *a.status = 0;
-    a.stats[0] = rho;
-    a.stats[1] = eta;
-  }
+  __syncthreads();
 }
 
 }  // namespace mppi

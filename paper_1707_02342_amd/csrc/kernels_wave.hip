@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     out[0] = rho;
     out[1] = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
   }
-  finish_iteration<kWaveBlock>(a, red);
+  finish_iteration<kWaveBlock>(a, blockIdx.x, red);
 }
 
 template __global__ void rollout_wave_kernel<32>(RolloutArgs);

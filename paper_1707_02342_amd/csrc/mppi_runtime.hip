@@ -19,7 +19,7 @@
 #include "mppi_types.h"
 
 namespace mppi {
-template <int HID> __global__ void rollout_lane_kernel(RolloutArgs);
+hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
 template <int HID> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T);
 __global__ void shift_kernel(float*, int, float*);
@@ -306,10 +306,8 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
     if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
     hipLaunchKernelGGL(rollout_wave_kernel<32>, dim3(G), dim3(kWaveBlockThreads),
                        wave_smem_bytes(c->cfg.T), c->stream, a);
-  } else if (c->hidden == 32) {
-    hipLaunchKernelGGL(rollout_lane_kernel<32>, dim3(G), dim3(kLaneBlockHost), 0, c->stream, a);
   } else {
-    hipLaunchKernelGGL(rollout_lane_kernel<64>, dim3(G), dim3(kLaneBlockHost), 0, c->stream, a);
+    HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
   }
   HIP_TRY(c, hipGetLastError());
   if (c->timing) {
@@ -493,8 +491,8 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     const int h = dims[1];
     if (dims[0] != 6 || dims[3] != 4 || dims[1] != dims[2] || (h != 32 && h != 64))
       return fail(c, MPPI_E_INVAL, "dims must be {6, h, h, 4} with h = 32 or 64");
-    if (c->cfg.precision != MPPI_PREC_FP32)
-      return fail(c, MPPI_E_INVAL, "this build runs the FP32 network only");
+    if (c->cfg.precision != MPPI_PREC_FP32 && c->cfg.schedule == MPPI_SCHED_WAVE)
+      return fail(c, MPPI_E_INVAL, "the wave schedule runs the FP32 network only");
     if (c->cfg.schedule == MPPI_SCHED_WAVE && h != 32)
       return fail(c, MPPI_E_INVAL, "the wave schedule supports h = 32 only");
     const size_t n = (size_t)6 * h + h + (size_t)h * h + h + 4 * (size_t)h + 4;
@@ -513,7 +511,8 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     c->hidden = h;
     c->have_dyn = true;
     if (c->cfg.schedule == MPPI_SCHED_AUTO)
-      c->schedule = (h == 32 && c->cfg.K <= kWaveAutoMaxK) ? MPPI_SCHED_WAVE : MPPI_SCHED_LANE;
+      c->schedule = (h == 32 && c->cfg.precision == MPPI_PREC_FP32 && c->cfg.K <= kWaveAutoMaxK)
+                        ? MPPI_SCHED_WAVE : MPPI_SCHED_LANE;
     return MPPI_OK;
   });
 }
@@ -804,6 +803,454 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
     if (dJdU) std::memcpy(dJdU, out.data() + kNP32Host, sizeof(float) * 2 * T);
     return MPPI_OK;
   });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form: many independent MPPI problems in one persistent launch
+// ===========================================================================
+namespace mppi {
+__global__ void rollout_batch_kernel(const RolloutArgs*, const int2*, int);
+}
+
+struct mppi_batch {
+  mppi_config cfg{};
+  mppi_cost cost{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n = 0;
+  std::vector<int> K, T, G, tile0;       // per instance: samples, horizon, tiles, first item
+  std::vector<size_t> Uoff, Soff, poff, p2off, coff, soff, sgoff;
+  float* d_U = nullptr;
+  float* d_S = nullptr;
+  float* d_part = nullptr;
+  float* d_part2 = nullptr;
+  unsigned* d_cnt = nullptr;
+  float* d_stats = nullptr;
+  int* d_status = nullptr;
+  float* d_sg = nullptr;
+  float* d_decay = nullptr;
+  float* d_x0 = nullptr;
+  unsigned* d_iter = nullptr;
+  float* d_map = nullptr;
+  float* d_params = nullptr;
+  RolloutArgs* d_args = nullptr;
+  int2* d_items = nullptr;
+  int n_items = 0;
+  int H = 0, W = 0;
+  float ox = 0, oy = 0, res = 1;
+  bool have_map = false, have_dyn = false, ready = false;
+  int grid = 0, order = 0;
+  double tuned_us = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool own_stream = false;
+  std::string err;
+};
+
+namespace {
+
+mppi_status bfail(mppi_batch* b, mppi_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf; else g_create_error = buf;
+  return st;
+}
+
+#define BHIP_TRY(b, expr)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return bfail((b), e_ == hipErrorOutOfMemory ? MPPI_E_NOMEM : MPPI_E_DEVICE, "%s: %s",  \
+                   #expr, hipGetErrorString(e_));                                            \
+  } while (0)
+
+void batch_free(mppi_batch* b) {
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  b->stream = nullptr;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  void* bufs[] = {b->d_U, b->d_S, b->d_part, b->d_part2, b->d_cnt, b->d_stats, b->d_status, b->d_sg,
+                  b->d_decay, b->d_x0, b->d_iter, b->d_map, b->d_params, b->d_args, b->d_items};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+}
+
+// Per-instance launch arguments (device pointers into the batch's shared buffers).
+std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
+  std::vector<RolloutArgs> v(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    RolloutArgs a{};
+    a.U = b->d_U + b->Uoff[i];
+    a.map = b->d_map;
+    a.params = b->d_params;
+    a.decay = b->d_decay;
+    a.x0_dev = b->d_x0 + 7 * (size_t)i;
+    a.S = b->d_S + b->Soff[i];
+    a.part = b->d_part + b->poff[i];
+    a.part2 = b->d_part2 + b->p2off[i];
+    a.cnt = b->d_cnt + b->coff[i];
+    a.sg = b->cfg.sg_window > 1 ? b->d_sg + b->sgoff[i] : nullptr;
+    a.Uout = b->d_U + b->Uoff[i];
+    a.stats = b->d_stats + b->soff[i];
+    a.status = b->d_status + i;
+    a.G = b->G[i];
+    a.sg_window = b->cfg.sg_window;
+    a.update_U = 1;
+    a.iter_dev = b->d_iter + i;
+    a.ckpt = nullptr;
+    a.ckpt_every = 1;
+    a.K = b->K[i];
+    a.T = b->T[i];
+    a.dt = b->cfg.dt;
+    a.inv_lambda = 1.0f / b->cfg.lambda;
+    a.gcs0 = b->cfg.gamma / b->cfg.sigma2[0];
+    a.gcs1 = b->cfg.gamma / b->cfg.sigma2[1];
+    a.u_lo0 = b->cfg.u_lo[0];
+    a.u_lo1 = b->cfg.u_lo[1];
+    a.u_hi0 = b->cfg.u_hi[0];
+    a.u_hi1 = b->cfg.u_hi[1];
+    a.nk.key_lo = (uint32_t)b->cfg.seed;
+    a.nk.key_hi = (uint32_t)(b->cfg.seed >> 32);
+    a.nk.iter = 0;  // read from iter_dev by the kernel
+    a.nk.instance = b->cfg.instance + (uint32_t)i;
+    a.nk.sig0 = std::sqrt(b->cfg.sigma2[0]);
+    a.nk.sig1 = std::sqrt(b->cfg.sigma2[1]);
+    a.cost.H = b->H;
+    a.cost.W = b->W;
+    a.cost.ox = b->ox;
+    a.cost.oy = b->oy;
+    a.cost.res = b->res;
+    a.cost.w_map = b->cost.w_map;
+    a.cost.w_speed = b->cost.w_speed;
+    a.cost.w_slip = b->cost.w_slip;
+    a.cost.v_des = b->cost.v_des;
+    a.cost.crash_cost = b->cost.crash_cost;
+    a.cost.map_thresh = b->cost.map_thresh;
+    a.cost.slip_cost = b->cost.slip_cost;
+    a.cost.slip_thresh = b->cost.slip_thresh;
+    v[i] = a;
+  }
+  return v;
+}
+
+// Work items in the given order: 0 = instance by instance, 1 = longest horizon first
+// (then largest K), so that the long tiles start early in the persistent loop.
+std::vector<int2> batch_items(const mppi_batch* b, int order) {
+  std::vector<int> idx(b->n);
+  for (int i = 0; i < b->n; ++i) idx[i] = i;
+  if (order == 1)
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+      return b->T[x] != b->T[y] ? b->T[x] > b->T[y] : b->K[x] > b->K[y];
+    });
+  std::vector<int2> items;
+  items.reserve(b->n_items);
+  if (order == 1) {
+    // interleave tiles of equal-length instances so that one instance's tiles spread out
+    for (int i : idx)
+      for (int t = 0; t < b->G[i]; ++t) items.push_back(make_int2(i, t));
+  } else {
+    for (int i = 0; i < b->n; ++i)
+      for (int t = 0; t < b->G[i]; ++t) items.push_back(make_int2(i, t));
+  }
+  return items;
+}
+
+mppi_status batch_launch(mppi_batch* b, int grid) {
+  hipLaunchKernelGGL(rollout_batch_kernel, dim3(grid), dim3(kLaneBlockHost), 0, b->stream,
+                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items);
+  BHIP_TRY(b, hipGetLastError());
+  return MPPI_OK;
+}
+
+// Times each (grid, order) candidate on the real problem, keeps the fastest, and
+// restores U and the iteration counters so tuning leaves no trace in the results.
+mppi_status batch_autotune(mppi_batch* b) {
+  int ncu = 0;
+  BHIP_TRY(b, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device));
+  const size_t nU = b->Uoff.back();
+  std::vector<float> U0(nU);
+  std::vector<unsigned> it0(b->n);
+  BHIP_TRY(b, hipMemcpyAsync(U0.data(), b->d_U, sizeof(float) * nU, hipMemcpyDeviceToHost, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(it0.data(), b->d_iter, sizeof(unsigned) * b->n, hipMemcpyDeviceToHost, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  hipEvent_t e0, e1;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  BHIP_TRY(b, hipEventCreate(&e1));
+  double best = 1e30;
+  int best_grid = b->n_items, best_order = 0;
+  const int grids[] = {ncu, 2 * ncu, 4 * ncu, 8 * ncu, b->n_items};
+  for (int order = 0; order < 2; ++order) {
+    std::vector<int2> items = batch_items(b, order);
+    BHIP_TRY(b, hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+    for (int gsz : grids) {
+      const int grid = std::max(1, std::min(gsz, b->n_items));
+      mppi_status st = batch_launch(b, grid);   // warm-up
+      if (st != MPPI_OK) return st;
+      BHIP_TRY(b, hipEventRecord(e0, b->stream));
+      for (int r = 0; r < 2; ++r) {
+        st = batch_launch(b, grid);
+        if (st != MPPI_OK) return st;
+      }
+      BHIP_TRY(b, hipEventRecord(e1, b->stream));
+      BHIP_TRY(b, hipEventSynchronize(e1));
+      float ms = 0;
+      BHIP_TRY(b, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_grid = grid;
+        best_order = order;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::vector<int2> items = batch_items(b, best_order);
+  BHIP_TRY(b, hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->d_U, U0.data(), sizeof(float) * nU, hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->d_iter, it0.data(), sizeof(unsigned) * b->n, hipMemcpyHostToDevice));
+  b->grid = best_grid;
+  b->order = best_order;
+  b->tuned_us = best * 1e3 / 2.0;
+  return MPPI_OK;
+}
+
+mppi_status batch_prepare(mppi_batch* b) {
+  if (b->ready) return MPPI_OK;
+  if (!b->have_map || !b->have_dyn) return bfail(b, MPPI_E_STATE, "set the cost map and the dynamics first");
+  std::vector<RolloutArgs> args = batch_args(b);
+  BHIP_TRY(b, hipMemcpy(b->d_args, args.data(), sizeof(RolloutArgs) * args.size(), hipMemcpyHostToDevice));
+  mppi_status st = batch_autotune(b);
+  if (st != MPPI_OK) return st;
+  // capture the chosen launch once; every iteration replays it
+  BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(rollout_batch_kernel, dim3(b->grid), dim3(kLaneBlockHost), 0, b->stream,
+                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items);
+  hipError_t le = hipGetLastError();
+  hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
+  if (le != hipSuccess) return bfail(b, MPPI_E_DEVICE, "capture launch: %s", hipGetErrorString(le));
+  if (ce != hipSuccess) return bfail(b, MPPI_E_DEVICE, "end capture: %s", hipGetErrorString(ce));
+  BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->ready = true;
+  return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mppi_batch_last_error(const mppi_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int32_t n, const int32_t* K,
+                              const int32_t* T, int device, void* hip_stream, mppi_batch** out) {
+  g_create_error.clear();
+  if (!out) return bfail(nullptr, MPPI_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !K || !T || n < 1 || n > 65536) return bfail(nullptr, MPPI_E_INVAL, "need 1..65536 instances with K and T");
+  int sgmax = 0;
+  for (int i = 0; i < n; ++i) {
+    mppi_config c = *cfg;
+    c.K = K[i];
+    c.T = T[i];
+    c.schedule = MPPI_SCHED_LANE;
+    if (validate_config(&c) != MPPI_OK) {
+      g_create_error = "instance " + std::to_string(i) + ": " + g_create_error;
+      return MPPI_E_INVAL;
+    }
+    sgmax = std::max(sgmax, T[i] * cfg->sg_window);
+  }
+  if (cfg->precision != MPPI_PREC_FP32) return bfail(nullptr, MPPI_E_INVAL, "the batched form runs the FP32 network");
+  mppi_status st = validate_cost(cost);
+  if (st != MPPI_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return bfail(nullptr, MPPI_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return bfail(nullptr, MPPI_E_INVAL, "device %d outside [0, %d)", device, ndev);
+  mppi_batch* b = new (std::nothrow) mppi_batch();
+  if (!b) return bfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
+  b->cfg = *cfg;
+  b->cost = *cost;
+  b->device = device;
+  b->stream = (hipStream_t)hip_stream;
+  b->n = n;
+  auto body = [&]() -> mppi_status {
+    BHIP_TRY(b, hipSetDevice(device));
+    if (!b->stream) {   // graph capture needs a stream other than the null stream
+      BHIP_TRY(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+      b->own_stream = true;
+    }
+    size_t u = 0, s = 0, p = 0, p2 = 0, cn = 0, so = 0, sg = 0;
+    int items = 0, Tmax = 0;
+    for (int i = 0; i < n; ++i) {
+      const int g = (K[i] + kLaneBlockHost - 1) / kLaneBlockHost;
+      const int ng = (g + 15) / 16;
+      b->K.push_back(K[i]);
+      b->T.push_back(T[i]);
+      b->G.push_back(g);
+      b->tile0.push_back(items);
+      b->Uoff.push_back(u);
+      b->Soff.push_back(s);
+      b->poff.push_back(p);
+      b->p2off.push_back(p2);
+      b->coff.push_back(cn);
+      b->soff.push_back(so);
+      b->sgoff.push_back(sg);
+      u += 2 * (size_t)T[i];
+      s += K[i];
+      p += (size_t)g * (2 + 2 * T[i]);
+      p2 += (size_t)ng * (2 + 2 * T[i]);
+      cn += ng + 1;
+      so += 2 + 2 * (size_t)T[i];
+      if (cfg->sg_window > 1) sg += (size_t)T[i] * cfg->sg_window;
+      items += g;
+      Tmax = std::max(Tmax, T[i]);
+    }
+    b->Uoff.push_back(u);
+    b->n_items = items;
+    BHIP_TRY(b, hipMalloc(&b->d_U, sizeof(float) * u));
+    BHIP_TRY(b, hipMemset(b->d_U, 0, sizeof(float) * u));
+    BHIP_TRY(b, hipMalloc(&b->d_S, sizeof(float) * s));
+    BHIP_TRY(b, hipMalloc(&b->d_part, sizeof(float) * p));
+    BHIP_TRY(b, hipMalloc(&b->d_part2, sizeof(float) * p2));
+    BHIP_TRY(b, hipMalloc(&b->d_cnt, sizeof(unsigned) * cn));
+    BHIP_TRY(b, hipMemset(b->d_cnt, 0, sizeof(unsigned) * cn));
+    BHIP_TRY(b, hipMalloc(&b->d_stats, sizeof(float) * so));
+    BHIP_TRY(b, hipMemset(b->d_stats, 0, sizeof(float) * so));
+    BHIP_TRY(b, hipMalloc(&b->d_status, sizeof(int) * n));
+    BHIP_TRY(b, hipMemset(b->d_status, 0, sizeof(int) * n));
+    BHIP_TRY(b, hipMalloc(&b->d_x0, sizeof(float) * 7 * n));
+    BHIP_TRY(b, hipMemset(b->d_x0, 0, sizeof(float) * 7 * n));
+    BHIP_TRY(b, hipMalloc(&b->d_iter, sizeof(unsigned) * n));
+    BHIP_TRY(b, hipMemset(b->d_iter, 0, sizeof(unsigned) * n));
+    BHIP_TRY(b, hipMalloc(&b->d_args, sizeof(RolloutArgs) * n));
+    BHIP_TRY(b, hipMalloc(&b->d_items, sizeof(int2) * items));
+    std::vector<float> decay(Tmax + 1);
+    for (int t = 0; t <= Tmax; ++t) decay[t] = (float)std::pow((double)cost->crash_decay, (double)t);
+    BHIP_TRY(b, hipMalloc(&b->d_decay, sizeof(float) * (Tmax + 1)));
+    BHIP_TRY(b, hipMemcpy(b->d_decay, decay.data(), sizeof(float) * (Tmax + 1), hipMemcpyHostToDevice));
+    if (cfg->sg_window > 1) {
+      BHIP_TRY(b, hipMalloc(&b->d_sg, sizeof(float) * sg));
+      for (int i = 0; i < n; ++i) {
+        std::vector<float> rows = savgol_rows(T[i], cfg->sg_window, cfg->sg_order);
+        BHIP_TRY(b, hipMemcpy(b->d_sg + b->sgoff[i], rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice));
+      }
+    }
+    return MPPI_OK;
+  };
+  try {
+    st = body();
+  } catch (...) {
+    st = bfail(b, MPPI_E_NOMEM, "host allocation failed");
+  }
+  if (st != MPPI_OK) {
+    g_create_error = b->err;
+    batch_free(b);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return MPPI_OK;
+}
+
+void mppi_batch_destroy(mppi_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_free(b);
+  delete b;
+}
+
+mppi_status mppi_batch_set_costmap(mppi_batch* b, const float* map, int32_t H, int32_t W, float origin_x,
+                                   float origin_y, float resolution) {
+  if (!b) return MPPI_E_INVAL;
+  if (!map || H < 2 || W < 2 || (int64_t)H * W > (int64_t)1 << 30 || !finite(origin_x) || !finite(origin_y) ||
+      !finite(resolution) || !(resolution > 0))
+    return bfail(b, MPPI_E_INVAL, "bad cost map");
+  BHIP_TRY(b, hipSetDevice(b->device));
+  if (b->d_map) BHIP_TRY(b, hipFree(b->d_map));
+  BHIP_TRY(b, hipMalloc(&b->d_map, sizeof(float) * (size_t)H * W));
+  BHIP_TRY(b, hipMemcpy(b->d_map, map, sizeof(float) * (size_t)H * W, hipMemcpyHostToDevice));
+  b->H = H;
+  b->W = W;
+  b->ox = origin_x;
+  b->oy = origin_y;
+  b->res = resolution;
+  b->have_map = true;
+  b->ready = false;
+  return MPPI_OK;
+}
+
+mppi_status mppi_batch_set_dynamics(mppi_batch* b, const int32_t dims[4], const float* params) {
+  if (!b) return MPPI_E_INVAL;
+  if (!dims || !params || dims[0] != 6 || dims[1] != 32 || dims[2] != 32 || dims[3] != 4)
+    return bfail(b, MPPI_E_INVAL, "the batched form runs the {6, 32, 32, 4} network");
+  for (int i = 0; i < kNP32Host; ++i)
+    if (!finite(params[i])) return bfail(b, MPPI_E_INVAL, "parameter %d is not finite", i);
+  BHIP_TRY(b, hipSetDevice(b->device));
+  if (!b->d_params) BHIP_TRY(b, hipMalloc(&b->d_params, sizeof(float) * kNP32Host));
+  BHIP_TRY(b, hipMemcpy(b->d_params, params, sizeof(float) * kNP32Host, hipMemcpyHostToDevice));
+  b->have_dyn = true;
+  b->ready = false;
+  return MPPI_OK;
+}
+
+mppi_status mppi_batch_set_controls(mppi_batch* b, int32_t i, const float* U) {
+  if (!b || !U || i < 0 || i >= b->n) return b ? bfail(b, MPPI_E_INVAL, "bad instance or U") : MPPI_E_INVAL;
+  BHIP_TRY(b, hipSetDevice(b->device));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_U + b->Uoff[i], U, sizeof(float) * 2 * b->T[i], hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return MPPI_OK;
+}
+
+mppi_status mppi_batch_iterate(mppi_batch* b, const float* x0) {
+  if (!b) return MPPI_E_INVAL;
+  if (!x0) return bfail(b, MPPI_E_INVAL, "x0 is NULL");
+  for (int i = 0; i < 7 * b->n; ++i)
+    if (!finite(x0[i])) return bfail(b, MPPI_E_INVAL, "x0[%d] is not finite", i);
+  BHIP_TRY(b, hipSetDevice(b->device));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_x0, x0, sizeof(float) * 7 * b->n, hipMemcpyHostToDevice, b->stream));
+  mppi_status st = batch_prepare(b);
+  if (st != MPPI_OK) return st;
+  BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+  return MPPI_OK;
+}
+
+mppi_status mppi_batch_get_controls(mppi_batch* b, int32_t i, float* U_out) {
+  if (!b || !U_out || i < 0 || i >= b->n) return b ? bfail(b, MPPI_E_INVAL, "bad instance or U_out") : MPPI_E_INVAL;
+  BHIP_TRY(b, hipSetDevice(b->device));
+  int st = 0;
+  BHIP_TRY(b, hipMemcpyAsync(U_out, b->d_U + b->Uoff[i], sizeof(float) * 2 * b->T[i], hipMemcpyDeviceToHost, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(&st, b->d_status + i, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return st == MPPI_E_NONFINITE ? bfail(b, MPPI_E_NONFINITE, "instance %d: no finite cost", i) : MPPI_OK;
+}
+
+mppi_status mppi_batch_get_costs(mppi_batch* b, int32_t i, float* S_out) {
+  if (!b || !S_out || i < 0 || i >= b->n) return b ? bfail(b, MPPI_E_INVAL, "bad instance or S_out") : MPPI_E_INVAL;
+  BHIP_TRY(b, hipSetDevice(b->device));
+  BHIP_TRY(b, hipMemcpyAsync(S_out, b->d_S + b->Soff[i], sizeof(float) * b->K[i], hipMemcpyDeviceToHost, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return MPPI_OK;
+}
+
+mppi_status mppi_batch_get_schedule(mppi_batch* b, int32_t* grid, int32_t* order, double* tuned_us) {
+  if (!b) return MPPI_E_INVAL;
+  if (grid) *grid = b->grid;
+  if (order) *order = b->order;
+  if (tuned_us) *tuned_us = b->tuned_us;
+  return b->ready ? MPPI_OK : bfail(b, MPPI_E_STATE, "no iteration has run yet");
+}
+
+mppi_status mppi_batch_synchronize(mppi_batch* b) {
+  if (!b) return MPPI_E_INVAL;
+  BHIP_TRY(b, hipSetDevice(b->device));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return MPPI_OK;
 }
 
 }  // extern "C"

@@ -47,6 +47,7 @@ struct RolloutArgs {
   int G;                   // blocks of this launch
   int sg_window;
   int update_U;            // 0: weights and Delta only (objective evaluation)
+  unsigned* iter_dev;      // nullable: iteration counter advanced by the final merge
   float* ckpt;             // nullable: [K][n_ckpt][8] full states every ckpt_every steps
   int ckpt_every;
   float x0[kStateDim];

@@ -30,6 +30,10 @@ EXPORTED = [
     "mppi_plant_step", "mppi_run_receding", "mppi_get_stats", "mppi_get_noise",
     "mppi_get_iteration", "mppi_set_iteration", "mppi_get_schedule", "mppi_set_timing",
     "mppi_get_timing", "mppi_objective", "mppi_objective_backward",
+    "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error", "mppi_batch_set_costmap",
+    "mppi_batch_set_dynamics", "mppi_batch_set_controls", "mppi_batch_iterate",
+    "mppi_batch_get_controls", "mppi_batch_get_costs", "mppi_batch_get_schedule",
+    "mppi_batch_synchronize",
 ]
 
 
@@ -88,8 +92,23 @@ def lib() -> C.CDLL:
         L.mppi_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.mppi_objective.argtypes = [vp, fp, C.c_uint32, C.c_int32, C.POINTER(C.c_double), fp]
         L.mppi_objective_backward.argtypes = [vp, fp, fp]
+        i32p = C.POINTER(C.c_int32)
+        L.mppi_batch_create.argtypes = [C.POINTER(mppi_config), C.POINTER(mppi_cost), C.c_int32, i32p, i32p,
+                                        C.c_int, vp, C.POINTER(vp)]
+        L.mppi_batch_destroy.argtypes = [vp]
+        L.mppi_batch_destroy.restype = None
+        L.mppi_batch_last_error.argtypes = [vp]
+        L.mppi_batch_last_error.restype = C.c_char_p
+        L.mppi_batch_set_costmap.argtypes = [vp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float]
+        L.mppi_batch_set_dynamics.argtypes = [vp, i32p, fp]
+        L.mppi_batch_set_controls.argtypes = [vp, C.c_int32, fp]
+        L.mppi_batch_iterate.argtypes = [vp, fp]
+        L.mppi_batch_get_controls.argtypes = [vp, C.c_int32, fp]
+        L.mppi_batch_get_costs.argtypes = [vp, C.c_int32, fp]
+        L.mppi_batch_get_schedule.argtypes = [vp, i32p, i32p, C.POINTER(C.c_double)]
+        L.mppi_batch_synchronize.argtypes = [vp]
         for name in EXPORTED:
-            if name not in ("mppi_destroy", "mppi_last_error"):
+            if name not in ("mppi_destroy", "mppi_last_error", "mppi_batch_destroy", "mppi_batch_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -240,6 +259,124 @@ def mppi_objective_backward(ctx, T: int, n_params: int = 1412):
     gth = np.zeros(n_params, dtype=np.float32)
     _check(ctx, lib().mppi_objective_backward(ctx, _fp(gU), _fp(gth)))
     return gU, gth
+
+
+def mppi_batch_last_error(b) -> str:
+    r = lib().mppi_batch_last_error(b)
+    return r.decode() if r else ""
+
+
+def _bcheck(b, st: int, allow=(MPPI_OK,)) -> int:
+    if st not in allow:
+        raise MppiError(st, mppi_batch_last_error(b))
+    return st
+
+
+def mppi_batch_create(cfg: mppi_config, cost: mppi_cost, Ks, Ts, device: int = 0, stream: int = 0):
+    K = np.ascontiguousarray(Ks, dtype=np.int32)
+    T = np.ascontiguousarray(Ts, dtype=np.int32)
+    out = C.c_void_p()
+    st = lib().mppi_batch_create(C.byref(cfg), C.byref(cost), K.size, K.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 T.ctypes.data_as(C.POINTER(C.c_int32)), device, C.c_void_p(stream or None),
+                                 C.byref(out))
+    if st != MPPI_OK:
+        raise MppiError(st, mppi_batch_last_error(None))
+    return out
+
+
+def mppi_batch_destroy(b) -> None:
+    lib().mppi_batch_destroy(b)
+
+
+def mppi_batch_set_costmap(b, data, origin_x, origin_y, resolution) -> None:
+    m = _f32(data)
+    _bcheck(b, lib().mppi_batch_set_costmap(b, _fp(m), m.shape[0], m.shape[1], origin_x, origin_y, resolution))
+
+
+def mppi_batch_set_dynamics(b, params) -> None:
+    dims = (C.c_int32 * 4)(6, 32, 32, 4)
+    p = _f32(params)
+    _bcheck(b, lib().mppi_batch_set_dynamics(b, dims, _fp(p)))
+
+
+def mppi_batch_set_controls(b, i: int, U) -> None:
+    u = _f32(U)
+    _bcheck(b, lib().mppi_batch_set_controls(b, i, _fp(u)))
+
+
+def mppi_batch_iterate(b, x0) -> None:
+    x = _f32(x0)
+    _bcheck(b, lib().mppi_batch_iterate(b, _fp(x)))
+
+
+def mppi_batch_get_controls(b, i: int, T: int):
+    U = np.zeros((T, 2), dtype=np.float32)
+    st = _bcheck(b, lib().mppi_batch_get_controls(b, i, _fp(U)), allow=(MPPI_OK, MPPI_E_NONFINITE))
+    return U, st
+
+
+def mppi_batch_get_costs(b, i: int, K: int):
+    S = np.zeros(K, dtype=np.float32)
+    _bcheck(b, lib().mppi_batch_get_costs(b, i, _fp(S)))
+    return S
+
+
+def mppi_batch_get_schedule(b):
+    g, o, t = C.c_int32(), C.c_int32(), C.c_double()
+    _bcheck(b, lib().mppi_batch_get_schedule(b, C.byref(g), C.byref(o), C.byref(t)))
+    return g.value, o.value, t.value
+
+
+def mppi_batch_synchronize(b) -> None:
+    _bcheck(b, lib().mppi_batch_synchronize(b))
+
+
+class Batch:
+    """Many MPPI problems advanced by one persistent launch (see mppi_batch_create)."""
+
+    def __init__(self, base_prob, Ks, Ts, cmap, params, device: int = 0, stream: Optional[int] = None):
+        self.Ks = [int(k) for k in Ks]
+        self.Ts = [int(t) for t in Ts]
+        self.b = mppi_batch_create(make_config(base_prob), make_cost(base_prob.cost), self.Ks, self.Ts, device,
+                                   0 if stream is None else stream)
+        try:
+            mppi_batch_set_costmap(self.b, cmap.data, cmap.origin_x, cmap.origin_y, cmap.resolution)
+            mppi_batch_set_dynamics(self.b, params)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "b", None):
+            mppi_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def iterate(self, x0):
+        mppi_batch_iterate(self.b, x0)
+
+    def controls(self, i: int):
+        return mppi_batch_get_controls(self.b, i, self.Ts[i])[0]
+
+    def costs(self, i: int):
+        return mppi_batch_get_costs(self.b, i, self.Ks[i])
+
+    def set_controls(self, i: int, U):
+        mppi_batch_set_controls(self.b, i, U)
+
+    def schedule(self):
+        return mppi_batch_get_schedule(self.b)
+
+    def synchronize(self):
+        mppi_batch_synchronize(self.b)
 
 
 # ---------------------------------------------------------------------------
