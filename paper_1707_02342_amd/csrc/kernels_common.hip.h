@@ -3,7 +3,7 @@
 // Each rollout block ends by summarising its samples as
 //   rho_g = min_k S_k,  eta_g = sum_k exp(-(S_k - rho_g)/lambda),
 //   N_g[t] = sum_k exp(-(S_k - rho_g)/lambda) eps_{k,t}
-// so that the merge kernel can form Algorithm 2's weights and the weighted
+// so that the last block to finish can form Algorithm 2's weights and the weighted
 // perturbation sum exactly: rho = min_g rho_g, eta~ = sum_g e^{-(rho_g-rho)/lambda} eta_g,
 // Delta_t = sum_g e^{-(rho_g-rho)/lambda} N_g[t] / eta~.  All sums run in a fixed
 // order, so results are reproducible run to run.
@@ -59,45 +59,63 @@ __device__ __forceinline__ float rel_weight(float S, float rho, float inv_lambda
   return (S < kInf && rho < kInf) ? expf(-(S - rho) * inv_lambda) : 0.0f;
 }
 
-constexpr int kMergeGroup = 16;
+constexpr int kMergeChunk = 64;
 constexpr int kStatusNonfinite = 5;
 
-// Merge n <= 16 partial rows (rho_g, eta_g, N_g[2T]) into one relative to
-// rho = min_g rho_g: eta = sum_g s_g eta_g, N = sum_g s_g N_g, s_g = exp(-(rho_g - rho)/lambda)
-// (s_g = 0 for a row without finite samples).  Called by the whole block; each thread
-// loads the n rows of its outputs at once, and sums them in row order.  The result
-// row goes to out_row (global) and/or out_lds.
+// Merge n partial rows (rho_g, eta_g, N_g[2T]) into one relative to rho = min_g rho_g:
+// eta = sum_g s_g eta_g, N = sum_g s_g N_g, s_g = exp(-(rho_g - rho)/lambda) (s_g = 0 for
+// a row without finite samples).  Called by the whole block.  Rows are taken in chunks
+// of kMergeChunk whose scales are staged in LDS; every sum runs in row order, so the
+// result does not depend on NT or on the chunking.  The result row goes to out_row
+// (global) and/or out_lds.  T2 <= 2 * kTMax.
 template <int NT>
 __device__ void merge_rows(const float* rows, int n, int stride, int T2, float inv_lambda,
-                           float* out_row, float* out_lds, float* s_small /* [2 * 16 + 2] */,
+                           float* out_row, float* out_lds, float* s_small /* [2 * kMergeChunk] */,
                            float& rho_out, float& eta_out) {
+  constexpr int kOut = (2 * kTMax + NT - 1) / NT;
   const int tid = threadIdx.x;
-  if (tid < n) {
-    s_small[tid] = __builtin_nontemporal_load(rows + (size_t)tid * stride);
-    s_small[16 + tid] = __builtin_nontemporal_load(rows + (size_t)tid * stride + 1);
-  }
-  __syncthreads();
-  float rho = kInf;
-  for (int g = 0; g < n; ++g) rho = fminf(rho, s_small[g]);
-  __syncthreads();
-  if (tid < n) {
-    const float eg = s_small[16 + tid];
-    s_small[tid] = (eg > 0.0f) ? expf(-(s_small[tid] - rho) * inv_lambda) : 0.0f;
-  }
-  __syncthreads();
+  float r = kInf;
+  for (int g = tid; g < n; g += NT) r = fminf(r, __builtin_nontemporal_load(rows + (size_t)g * stride));
+  const float rho = block_min<NT / 64>(r, s_small);
   float eta = 0.0f;
-  for (int g = 0; g < n; ++g) eta = __builtin_fmaf(s_small[g], s_small[16 + g], eta);
-  for (int o = tid; o < T2; o += NT) {
-    float v[kMergeGroup];
+  float acc[kOut];
 #pragma unroll
-    for (int g = 0; g < kMergeGroup; ++g)
-      v[g] = g < n ? __builtin_nontemporal_load(rows + (size_t)g * stride + 2 + o) : 0.0f;
-    float acc = 0.0f;
+  for (int j = 0; j < kOut; ++j) acc[j] = 0.0f;
+  for (int c0 = 0; c0 < n; c0 += kMergeChunk) {
+    const int m = min(kMergeChunk, n - c0);
+    if (tid < m) {
+      const float* row = rows + (size_t)(c0 + tid) * stride;
+      const float eg = __builtin_nontemporal_load(row + 1);
+      s_small[tid] = (eg > 0.0f) ? expf(-(__builtin_nontemporal_load(row) - rho) * inv_lambda) : 0.0f;
+      s_small[kMergeChunk + tid] = eg;
+    }
+    __syncthreads();
+    for (int g = 0; g < m; ++g) eta = __builtin_fmaf(s_small[g], s_small[kMergeChunk + g], eta);
 #pragma unroll
-    for (int g = 0; g < kMergeGroup; ++g)
-      if (g < n) acc = __builtin_fmaf(s_small[g], v[g], acc);
-    if (out_row) out_row[2 + o] = acc;
-    if (out_lds) out_lds[o] = acc;
+    for (int j = 0; j < kOut; ++j) {
+      const int o = tid + j * NT;
+      if (o < T2) {
+        const float* col = rows + (size_t)c0 * stride + 2 + o;
+        int g = 0;
+        for (; g + 16 <= m; g += 16) {
+          float v[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(col + (size_t)(g + i) * stride);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[j] = __builtin_fmaf(s_small[g + i], v[i], acc[j]);
+        }
+        for (; g < m; ++g) acc[j] = __builtin_fmaf(s_small[g], __builtin_nontemporal_load(col + (size_t)g * stride), acc[j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < kOut; ++j) {
+    const int o = tid + j * NT;
+    if (o < T2) {
+      if (out_row) out_row[2 + o] = acc[j];
+      if (out_lds) out_lds[o] = acc[j];
+    }
   }
   if (tid == 0 && out_row) {
     out_row[0] = rho;
@@ -108,8 +126,8 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
 }
 
 // Called by every rollout block after writing its partial row (tile = the block's
-// index among the launch's blocks of this problem).  Blocks arrive in groups of 16;
-// the last to arrive in a group merges the group's rows, and the last group merger
+// index among the launch's blocks of this problem).  Blocks arrive in groups of
+// merge_group_size(G); the last to arrive in a group merges the group's rows, and the last group merger
 // merges the group rows and applies Algorithm 2's normalisation, the Savitzky-Golay
 // smoothing and the update U <- U + SG * Delta.  Device-scope fences order the rows
 // written on one XCD before their reads on another.  Every decision is uniform over
@@ -117,13 +135,14 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
 template <int NT>
 __device__ void finish_iteration(const RolloutArgs& a, int tile, float* lds /* >= 2T floats */) {
   __shared__ unsigned s_flag;
-  __shared__ float s_small[2 * kMergeGroup + 2];
+  __shared__ float s_small[2 * kMergeChunk];
   const int tid = threadIdx.x;
   const int T2 = 2 * a.T;
   const int stride = 2 + T2;
-  const int ngrp = (a.G + kMergeGroup - 1) / kMergeGroup;
-  const int grp = tile / kMergeGroup;
-  const int n_in = min(kMergeGroup, a.G - grp * kMergeGroup);
+  const int gsz = merge_group_size(a.G);
+  const int ngrp = (a.G + gsz - 1) / gsz;
+  const int grp = tile / gsz;
+  const int n_in = min(gsz, a.G - grp * gsz);
   __threadfence();
   __syncthreads();
   if (tid == 0) s_flag = (atomicAdd(a.cnt + grp, 1u) == (unsigned)(n_in - 1)) ? 1u : 0u;
@@ -131,7 +150,7 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float* lds /* >
   if (s_flag) {
     __threadfence();
     float rho, eta;
-    merge_rows<NT>(a.part + (size_t)grp * kMergeGroup * stride, n_in, stride, T2, a.inv_lambda,
+    merge_rows<NT>(a.part + (size_t)grp * gsz * stride, n_in, stride, T2, a.inv_lambda,
                    a.part2 + (size_t)grp * stride, nullptr, s_small, rho, eta);
     if (tid == 0) a.cnt[grp] = 0u;
     __threadfence();

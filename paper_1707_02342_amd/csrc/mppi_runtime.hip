@@ -415,7 +415,8 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
-    const int ngrp_cap = (c->part_cap + 15) / 16;
+    const int ngrp_cap = std::max(merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
+                                  merge_groups(blocks_for(c, MPPI_SCHED_WAVE)));
     HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)ngrp_cap * (2 + 2 * T)));
     HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(unsigned) * (ngrp_cap + 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (ngrp_cap + 1), c->stream));
@@ -1088,7 +1089,7 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     int items = 0, Tmax = 0;
     for (int i = 0; i < n; ++i) {
       const int g = (K[i] + kLaneBlockHost - 1) / kLaneBlockHost;
-      const int ng = (g + 15) / 16;
+      const int ng = merge_groups(g);
       b->K.push_back(K[i]);
       b->T.push_back(T[i]);
       b->G.push_back(g);

@@ -2,6 +2,7 @@
 // Passed by value as kernel arguments (no constant-memory uploads per call).
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace mppi {
@@ -11,6 +12,20 @@ constexpr int kCtrlDim = 2;
 constexpr int kNetIn = 6;
 constexpr int kNetOut = 4;
 constexpr int kTMax = 256;
+
+// The per-block partial rows of one launch (G blocks) are merged in two levels:
+// groups of merge_group_size(G) consecutive blocks, then the merge_groups(G) group
+// rows.  16 up to 256 blocks, ceil(sqrt(G)) beyond, so neither level grows faster
+// than sqrt(G).
+__host__ __device__ inline int merge_group_size(int G) {
+  int s = 16;
+  while (s * s < G) ++s;
+  return s;
+}
+__host__ __device__ inline int merge_groups(int G) {
+  const int s = merge_group_size(G);
+  return (G + s - 1) / s;
+}
 
 // Philox key and counter words that are fixed within one iteration, plus the
 // noise standard deviations sqrt(Sigma_ii) (FP32, correctly rounded on the host).
@@ -38,8 +53,8 @@ struct RolloutArgs {
   const float* x0_dev;     // nullable: read x0 from here instead of x0[]
   float* S;                // [K] trajectory costs
   float* part;             // [G][2 + 2T] per-block (rho_g, eta_g, N_g[T][2])
-  float* part2;            // [ceil(G/16)][2 + 2T] per-group merges
-  unsigned* cnt;           // [ceil(G/16) + 1] arrival counters, zero between launches
+  float* part2;            // [merge_groups(G)][2 + 2T] per-group merges
+  unsigned* cnt;           // [merge_groups(G) + 1] arrival counters, zero between launches
   const float* sg;         // [T][sg_window] smoothing rows (null when window == 1)
   float* Uout;             // [T][2], updated in place by the last block
   float* stats;            // [2 + 2T]: rho, eta~, Delta[T][2]

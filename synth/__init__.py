@@ -174,6 +174,27 @@ def affine_map(a: float, b: float, c: float, H: int = 64, W: int = 64, resolutio
                    float(np.float32(resolution)))
 
 
+def split_nan_map(x_max: np.ndarray, y_center: float, value: float = 0.25, resolution: float = 0.002,
+                  size: int = 2048):
+    """A constant map whose columns beyond a boundary are NaN, placed so that about half of
+    the samples, given the largest x each reaches (x_max, from a rollout), read a NaN cell
+    and the others do not.  The boundary grid line sits in the middle of the widest gap
+    between consecutive sorted x_max values in their middle third, and 1000 cells from
+    the map's left edge; lookups at x >= boundary touch the NaN column.  Returns the map
+    and the width of that gap."""
+    xs = np.sort(np.asarray(x_max, np.float64))
+    lo, hi = len(xs) // 3, max(len(xs) * 2 // 3, len(xs) // 3 + 1)
+    gaps = xs[lo + 1:hi + 1] - xs[lo:hi]
+    i = lo + int(np.argmax(gaps))
+    boundary = 0.5 * (xs[i] + xs[i + 1])
+    res = float(np.float32(resolution))
+    ox = float(np.float32(boundary - 1000 * res))
+    oy = float(np.float32(y_center - 0.5 * size * res))
+    data = np.full((size, size), value, dtype=np.float32)
+    data[:, 1001:] = np.nan
+    return CostMap(data, ox, oy, res), float(xs[i + 1] - xs[i])
+
+
 # ----------------------------------------------------------------------------
 # Problem parameters
 # ----------------------------------------------------------------------------

@@ -79,7 +79,14 @@ def test_precision_form_error_vs_fp64(M, orc, prec, seed):
                                             "dU_max": float(dU), "dU_max_rounded_weights": float(dU_r)})
     assert st == M.MPPI_OK
     assert rel.max() < (0.05 if prec == 1 else 0.01)
-    assert dU < 0.1
+    # U is reported, not gated: at lambda = 1 the weights sit on a handful of samples, and a
+    # relative cost error of 1e-3..1e-2 can hand the weight to another sample.  The update
+    # itself (FP32 weights, sum, smoothing) must reproduce the oracle's FP64 update applied
+    # to the GPU's own costs and the same noise.
+    st2, w, _, _ = orc.weights(S.astype(np.float64), prob.lam)
+    eps = orc.noise(op, 0).astype(np.float64)
+    U_iso = np.tensordot(w, eps, axes=(0, 0))
+    assert np.abs(U - U_iso).max() <= 1e-5
 
 
 def test_precision_form_lanes_are_independent(M, orc):
@@ -92,16 +99,15 @@ def test_precision_form_lanes_are_independent(M, orc):
     with M.Controller(synth.with_(base, K=300), synth.ring_map(), params, precision=1) as c:
         S300, _ = c.iterate(synth.C1_X0, want_costs=True)
     np.testing.assert_array_equal(S300, S320[:300])
-    # a map with a NaN region that part of the samples reach
-    data = synth.ring_map().data.copy()
+    # a map with a NaN region that about half of the samples reach
     op = orc.OracleProblem(base, synth.ring_map(), params)
     x0 = np.array([20.8, 12.8, 0.0, 0.0, 6.0, 0.0, 0.0], np.float32)
     _, tr = orc.rollout(op, x0, np.zeros((17, 2), np.float32), orc.noise(op, 0), traj=True)
-    col = int(np.percentile(tr[:, :, 0].max(axis=1), 50) / 0.1) + 1
-    data[:, col:] = np.nan
-    with M.Controller(base, synth.CostMap(data, 0.0, 0.0, 0.1), params, precision=1) as c:
+    cmap, _ = synth.split_nan_map(tr[:, :, 0].max(axis=1), 12.8)
+    good = synth.CostMap(np.full_like(cmap.data, 0.25), cmap.origin_x, cmap.origin_y, cmap.resolution)
+    with M.Controller(base, cmap, params, precision=1) as c:
         Snan, st = c.iterate(x0, want_costs=True)
-    with M.Controller(base, synth.ring_map(), params, precision=1) as c:
+    with M.Controller(base, good, params, precision=1) as c:
         Sok, _ = c.iterate(x0, want_costs=True)
     fin = np.isfinite(Snan)
     assert fin.any() and (~fin).any()

@@ -172,6 +172,17 @@ def test_ragged_shapes(M, orc, schedule, K, T):
                      synth.random_controls(T, K), schedule)
 
 
+@pytest.mark.parametrize("schedule,K", [(2, 2049), (2, 4100), (2, 32768), (1, 65537), (1, 70000)])
+def test_many_blocks(M, orc, schedule, K):
+    """Launches of more than 256 blocks: the partial rows are merged in groups of
+    ceil(sqrt(G)) blocks (wave: 8 samples per block, lane: 256)."""
+    T = 12
+    prob = synth.with_(synth.c1_problem(seed=K), K=K, T=T)
+    _say("many blocks", schedule, K)
+    _check_iteration(M, orc, prob, synth.ring_map(), synth.mlp_params(32, 0), synth.C1_X0,
+                     synth.random_controls(T, 5), schedule)
+
+
 @pytest.mark.parametrize("schedule", _schedules())
 def test_sgf_and_impulses_small(M, orc, schedule):
     """The paper-shaped cost (impulses, slip) with window-9 smoothing on a small K."""
@@ -285,18 +296,16 @@ def test_all_nonfinite_leaves_controls(M, orc):
 
 def test_partial_nonfinite_samples_get_zero_weight(M, orc):
     """A map that is NaN beyond a column boundary: samples that reach it get S = inf and
-    weight 0.  The boundary is put at the median of the samples' largest x reached, so
-    about half of the samples touch it."""
+    weight 0.  The boundary is put in a wide gap between the samples' largest x values
+    near their median, so about half of the samples touch it and none is close to it."""
     prob = synth.with_(synth.c1_problem(seed=3), K=256, T=30)
-    base = synth.ring_map()
+    params = synth.mlp_params(32, 0)
     x0 = np.array([20.8, 12.8, 0.0, 0.0, 6.0, 0.0, 0.0], np.float32)
-    op = _orc(orc, prob, base, synth.mlp_params(32, 0))
+    op = _orc(orc, prob, synth.ring_map(), params)
     _, tr = orc.rollout(op, x0, np.zeros((30, 2), np.float32), orc.noise(op, 0), traj=True)
-    col = int(np.percentile(tr[:, :, 0].max(axis=1), 50) / base.resolution) + 1
-    data = base.data.copy()
-    data[:, col:] = np.nan
-    cmap = synth.CostMap(data, 0.0, 0.0, base.resolution)
-    S, U = _check_iteration(M, orc, prob, cmap, synth.mlp_params(32, 0), x0, np.zeros((30, 2), np.float32), 1)
+    cmap, gap = synth.split_nan_map(tr[:, :, 0].max(axis=1), 12.8)
+    assert gap > 1e-4, gap
+    S, U = _check_iteration(M, orc, prob, cmap, params, x0, np.zeros((30, 2), np.float32), 1)
     assert np.isinf(S).any() and np.isfinite(S).any()
 
 
