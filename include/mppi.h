@@ -174,9 +174,9 @@ mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
 /* Device time of the iteration kernel, measured with HIP events recorded on the
  * context's stream around every launch once enabled.  times_ms[0] = the rollout
  * kernel (which also forms the weights and updates U in its last block), summed
- * since the last reset; times_ms[1] is the time between the kernel's end event and
- * a second event right after it (launch-gap probe, normally ~0); counts = launches.
- * Synchronises. */
+ * since timing was last enabled, counts[0] = launches; times_ms[1] and counts[1]
+ * are 0 (reserved).  The events add stream markers between launches, so measure
+ * throughput with timing off.  mppi_get_timing synchronises. */
 mppi_status mppi_set_timing(mppi_ctx* ctx, int32_t enable);
 mppi_status mppi_get_timing(mppi_ctx* ctx, double times_ms[2], int64_t counts[2]);
 

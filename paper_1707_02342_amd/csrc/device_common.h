@@ -179,21 +179,46 @@ __device__ __forceinline__ void grid_coord(float ph, float pl, float o, float re
   if (f >= 1.0f) { f -= 1.0f; i0 += 1; }
 }
 
-__device__ __forceinline__ float costmap_at2(const CostArgs& c, const float* __restrict__ map,
-                                             float pxh, float pxl, float pyh, float pyl) {
+// Cell indices (row-major offsets of the four corners, clamped to the edge) and
+// fractions of the bilinear lookup at a hi + lo position.
+__device__ __forceinline__ void map_taps(const CostArgs& c, float pxh, float pxl, float pyh, float pyl,
+                                         int idx[4], float& fx, float& fy) {
   int j0, i0;
-  float fx, fy;
   grid_coord(pxh, pxl, c.ox, c.res, c.W, j0, fx);
   grid_coord(pyh, pyl, c.oy, c.res, c.H, i0, fy);
   const int ja = min(max(j0, 0), c.W - 1), jb = min(max(j0 + 1, 0), c.W - 1);
   const int ia = min(max(i0, 0), c.H - 1), ib = min(max(i0 + 1, 0), c.H - 1);
-  const float m00 = map[(size_t)ia * c.W + ja];
-  const float m01 = map[(size_t)ia * c.W + jb];
-  const float m10 = map[(size_t)ib * c.W + ja];
-  const float m11 = map[(size_t)ib * c.W + jb];
-  const float top = (1.0f - fx) * m00 + fx * m01;
-  const float bot = (1.0f - fx) * m10 + fx * m11;
+  idx[0] = ia * c.W + ja;
+  idx[1] = ia * c.W + jb;
+  idx[2] = ib * c.W + ja;
+  idx[3] = ib * c.W + jb;
+}
+
+__device__ __forceinline__ float bilerp(const float m[4], float fx, float fy) {
+  const float top = (1.0f - fx) * m[0] + fx * m[1];
+  const float bot = (1.0f - fx) * m[2] + fx * m[3];
   return (1.0f - fy) * top + fy * bot;
+}
+
+__device__ __forceinline__ float costmap_at2(const CostArgs& c, const float* __restrict__ map,
+                                             float pxh, float pxl, float pyh, float pyl) {
+  int idx[4];
+  float fx, fy;
+  map_taps(c, pxh, pxl, pyh, pyl, idx, fx, fy);
+  const float m[4] = {map[idx[0]], map[idx[1]], map[idx[2]], map[idx[3]]};
+  return bilerp(m, fx, fy);
+}
+
+// c(x, t) given the map value h at the post-step position and fl32(decay^t).
+__device__ __forceinline__ float state_cost_h(const CostArgs& c, float h, float decay_t, float vx, float vy) {
+  float cost = c.w_map * h;
+  if (h > c.map_thresh) cost += c.crash_cost * decay_t;
+  const float dv = vx - c.v_des;
+  cost += c.w_speed * (dv * dv);
+  const float zeta = -atan2f(vy, fabsf(vx));
+  cost += c.w_slip * (zeta * zeta);
+  if (fabsf(zeta) > c.slip_thresh) cost += c.slip_cost;
+  return cost;
 }
 
 // c(x, t) with the position as hi + lo pairs (see grid_coord).
@@ -201,14 +226,7 @@ __device__ __forceinline__ float state_cost2(const CostArgs& c, const float* __r
                                              const float* __restrict__ decay, float pxh, float pxl,
                                              float pyh, float pyl, float vx, float vy, int t) {
   const float h = costmap_at2(c, map, pxh, pxl, pyh, pyl);
-  float cost = c.w_map * h;
-  if (h > c.map_thresh) cost += c.crash_cost * decay[t];
-  const float dv = vx - c.v_des;
-  cost += c.w_speed * (dv * dv);
-  const float zeta = -atan2f(vy, fabsf(vx));
-  cost += c.w_slip * (zeta * zeta);
-  if (fabsf(zeta) > c.slip_thresh) cost += c.slip_cost;
-  return cost;
+  return state_cost_h(c, h, decay[t], vx, vy);
 }
 
 // c(x, t) on the post-step state: track (+ decaying impulse), speed, side slip.

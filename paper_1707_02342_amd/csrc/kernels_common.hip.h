@@ -66,74 +66,139 @@ constexpr int kStatusNonfinite = 5;
 // eta = sum_g s_g eta_g, N = sum_g s_g N_g, s_g = exp(-(rho_g - rho)/lambda) (s_g = 0 for
 // a row without finite samples).  Called by the whole block.  Rows are taken in chunks
 // of kMergeChunk whose scales are staged in LDS; every sum runs in row order, so the
-// result does not depend on NT or on the chunking.  The result row goes to out_row
-// (global) and/or out_lds.  T2 <= 2 * kTMax.
+// result does not depend on NT or on the chunking.  N goes to out_lds[2T] (visible to
+// the block after its next barrier), rho and eta to every thread.  T2 <= 2 * kTMax.
 template <int NT>
 __device__ void merge_rows(const float* rows, int n, int stride, int T2, float inv_lambda,
-                           float* out_row, float* out_lds, float* s_small /* [2 * kMergeChunk] */,
+                           float* out_lds, float* s_small /* [2 * kMergeChunk] */,
                            float& rho_out, float& eta_out) {
   constexpr int kOut = (2 * kTMax + NT - 1) / NT;
+  constexpr int kFast = 16;
+  static_assert(kMergeChunk >= kFast, "");
   const int tid = threadIdx.x;
-  float r = kInf;
-  for (int g = tid; g < n; g += NT) r = fminf(r, __builtin_nontemporal_load(rows + (size_t)g * stride));
-  const float rho = block_min<NT / 64>(r, s_small);
-  float eta = 0.0f;
   float acc[kOut];
 #pragma unroll
   for (int j = 0; j < kOut; ++j) acc[j] = 0.0f;
-  for (int c0 = 0; c0 < n; c0 += kMergeChunk) {
-    const int m = min(kMergeChunk, n - c0);
-    if (tid < m) {
-      const float* row = rows + (size_t)(c0 + tid) * stride;
-      const float eg = __builtin_nontemporal_load(row + 1);
-      s_small[tid] = (eg > 0.0f) ? expf(-(__builtin_nontemporal_load(row) - rho) * inv_lambda) : 0.0f;
-      s_small[kMergeChunk + tid] = eg;
+  float rho, eta = 0.0f;
+  if (n <= kFast) {
+    // one round trip: every load of the n rows is issued before the first use
+    float rg = kInf, eg = 0.0f;
+    if (tid < n) {
+      rg = __builtin_nontemporal_load(rows + (size_t)tid * stride);
+      eg = __builtin_nontemporal_load(rows + (size_t)tid * stride + 1);
     }
-    __syncthreads();
-    for (int g = 0; g < m; ++g) eta = __builtin_fmaf(s_small[g], s_small[kMergeChunk + g], eta);
+    float v[kOut][kFast];
 #pragma unroll
     for (int j = 0; j < kOut; ++j) {
       const int o = tid + j * NT;
-      if (o < T2) {
-        const float* col = rows + (size_t)c0 * stride + 2 + o;
-        int g = 0;
-        for (; g + 16 <= m; g += 16) {
-          float v[16];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(col + (size_t)(g + i) * stride);
-#pragma unroll
-          for (int i = 0; i < 16; ++i) acc[j] = __builtin_fmaf(s_small[g + i], v[i], acc[j]);
-        }
-        for (; g < m; ++g) acc[j] = __builtin_fmaf(s_small[g], __builtin_nontemporal_load(col + (size_t)g * stride), acc[j]);
-      }
+      for (int g = 0; g < kFast; ++g)
+        v[j][g] = (o < T2 && g < n) ? __builtin_nontemporal_load(rows + (size_t)g * stride + 2 + o) : 0.0f;
+    }
+    if (tid < n) {
+      s_small[tid] = rg;
+      s_small[kMergeChunk + tid] = eg;
     }
     __syncthreads();
+    rho = kInf;
+    for (int g = 0; g < n; ++g) rho = fminf(rho, s_small[g]);
+    __syncthreads();
+    if (tid < n) s_small[tid] = (eg > 0.0f) ? expf(-(rg - rho) * inv_lambda) : 0.0f;
+    __syncthreads();
+    for (int g = 0; g < n; ++g) eta = __builtin_fmaf(s_small[g], s_small[kMergeChunk + g], eta);
+#pragma unroll
+    for (int j = 0; j < kOut; ++j)
+#pragma unroll
+      for (int g = 0; g < kFast; ++g)
+        if (g < n) acc[j] = __builtin_fmaf(s_small[g], v[j][g], acc[j]);
+    __syncthreads();
+  } else {
+    float r = kInf;
+    for (int g = tid; g < n; g += NT) r = fminf(r, __builtin_nontemporal_load(rows + (size_t)g * stride));
+    rho = block_min<NT / 64>(r, s_small);
+    for (int c0 = 0; c0 < n; c0 += kMergeChunk) {
+      const int m = min(kMergeChunk, n - c0);
+      if (tid < m) {
+        const float* row = rows + (size_t)(c0 + tid) * stride;
+        const float eg = __builtin_nontemporal_load(row + 1);
+        s_small[tid] = (eg > 0.0f) ? expf(-(__builtin_nontemporal_load(row) - rho) * inv_lambda) : 0.0f;
+        s_small[kMergeChunk + tid] = eg;
+      }
+      __syncthreads();
+      for (int g = 0; g < m; ++g) eta = __builtin_fmaf(s_small[g], s_small[kMergeChunk + g], eta);
+#pragma unroll
+      for (int j = 0; j < kOut; ++j) {
+        const int o = tid + j * NT;
+        if (o < T2) {
+          const float* col = rows + (size_t)c0 * stride + 2 + o;
+          int g = 0;
+          for (; g + 16 <= m; g += 16) {
+            float v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(col + (size_t)(g + i) * stride);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[j] = __builtin_fmaf(s_small[g + i], v[i], acc[j]);
+          }
+          for (; g < m; ++g)
+            acc[j] = __builtin_fmaf(s_small[g], __builtin_nontemporal_load(col + (size_t)g * stride), acc[j]);
+        }
+      }
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int j = 0; j < kOut; ++j) {
     const int o = tid + j * NT;
-    if (o < T2) {
-      if (out_row) out_row[2 + o] = acc[j];
-      if (out_lds) out_lds[o] = acc[j];
-    }
-  }
-  if (tid == 0 && out_row) {
-    out_row[0] = rho;
-    out_row[1] = eta;
+    if (o < T2) out_lds[o] = acc[j];
   }
   rho_out = rho;
   eta_out = eta;
 }
 
-// Called by every rollout block after writing its partial row (tile = the block's
-// index among the launch's blocks of this problem).  Blocks arrive in groups of
-// merge_group_size(G); the last to arrive in a group merges the group's rows, and the last group merger
-// merges the group rows and applies Algorithm 2's normalisation, the Savitzky-Golay
-// smoothing and the update U <- U + SG * Delta.  Device-scope fences order the rows
-// written on one XCD before their reads on another.  Every decision is uniform over
-// the block, so all barriers are reached by all threads.
+// A store that writes through the XCD's L2 (device-scope relaxed atomic store).  Data
+// that other blocks read after a device-scope release is written this way, so the
+// release finds few dirty L2 lines to write back.
+__device__ __forceinline__ void store_through(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0 publishes a row (rho, eta, N[T2]) to global memory and counts its arrival
+// at *cnt; returns, in every thread after the barrier, whether this block was the
+// last of `expected` arrivals.  Only wave 0 writes global data that other blocks
+// read, so only wave 0 needs the device-scope release; the last arrival takes the
+// matching acquire.  (A full fence in every wave would also invalidate the XCD's L2
+// once per block.)  The row is written through L2, so the release has little to
+// write back.
 template <int NT>
-__device__ void finish_iteration(const RolloutArgs& a, int tile, float* lds /* >= 2T floats */) {
+__device__ bool publish_and_count(float* dst, float rho, float eta, const float* N_lds, int T2,
+                                  unsigned* cnt, unsigned expected, unsigned* s_flag) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+      store_through(dst, rho);
+      store_through(dst + 1, eta);
+    }
+    for (int o = lane; o < T2; o += 64) store_through(dst + 2 + o, N_lds[o]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) *s_flag = (atomicAdd(cnt, 1u) == expected - 1u) ? 1u : 0u;
+  }
+  __syncthreads();
+  const bool last = *s_flag != 0u;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+// Called by every rollout block with its partial row (rho_g, eta_g and N_g[2T] in
+// LDS; tile = the block's index among the launch's blocks of this problem).  Blocks
+// arrive in groups of merge_group_size(G); the last to arrive in a group merges the
+// group's rows, and the last group merger merges the group rows and applies
+// Algorithm 2's normalisation, the Savitzky-Golay smoothing and the update
+// U <- U + SG * Delta.  With a single group the second level is skipped (merging one
+// row with scale exp(0) = 1 would return it unchanged).  Every decision is uniform
+// over the block, so all barriers are reached by all threads.
+template <int NT>
+__device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
+                                 const float* N_lds /* [2T] */, float* lds /* >= 2T floats */) {
   __shared__ unsigned s_flag;
   __shared__ float s_small[2 * kMergeChunk];
   const int tid = threadIdx.x;
@@ -143,46 +208,77 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float* lds /* >
   const int ngrp = (a.G + gsz - 1) / gsz;
   const int grp = tile / gsz;
   const int n_in = min(gsz, a.G - grp * gsz);
-  __threadfence();
   __syncthreads();
-  if (tid == 0) s_flag = (atomicAdd(a.cnt + grp, 1u) == (unsigned)(n_in - 1)) ? 1u : 0u;
-  __syncthreads();
-  if (s_flag) {
-    __threadfence();
+  if (publish_and_count<NT>(a.part + (size_t)tile * stride, rho_b, eta_b, N_lds, T2, a.cnt + grp,
+                            (unsigned)n_in, &s_flag)) {
+    constexpr int kOut = (2 * kTMax + NT - 1) / NT;
+    constexpr int kTapReg = 16;
+    float u_old[kOut], taps[kOut][kTapReg];
+    const int w = a.sg_window;
+    // loads of the final stage, issued before the final merge's row loads so that
+    // both share one memory round trip
+    auto prefetch_final = [&]() {
+#pragma unroll
+      for (int j = 0; j < kOut; ++j) {
+        const int o = tid + j * NT;
+        u_old[j] = (o < T2) ? a.Uout[o] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < kTapReg; ++i)
+          taps[j][i] = (o < T2 && w > 1 && w <= kTapReg && i < w) ? a.sg[(size_t)(o >> 1) * w + i] : 0.0f;
+      }
+    };
     float rho, eta;
-    merge_rows<NT>(a.part + (size_t)grp * gsz * stride, n_in, stride, T2, a.inv_lambda,
-                   a.part2 + (size_t)grp * stride, nullptr, s_small, rho, eta);
+    bool final_merge = ngrp == 1;
+    if (final_merge) prefetch_final();
+    merge_rows<NT>(a.part + (size_t)grp * gsz * stride, n_in, stride, T2, a.inv_lambda, lds, s_small,
+                   rho, eta);
     if (tid == 0) a.cnt[grp] = 0u;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_flag = (atomicAdd(a.cnt + ngrp, 1u) == (unsigned)(ngrp - 1)) ? 1u : 0u;
-    __syncthreads();
-    if (s_flag) {
-      __threadfence();
-      merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, nullptr, lds, s_small, rho, eta);
-      if (tid == 0) a.cnt[ngrp] = 0u;
+    if (ngrp > 1) {
+      __syncthreads();
+      final_merge = publish_and_count<NT>(a.part2 + (size_t)grp * stride, rho, eta, lds, T2, a.cnt + ngrp,
+                                          (unsigned)ngrp, &s_flag);
+      if (final_merge) {
+        prefetch_final();
+        merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, lds, s_small, rho, eta);
+        if (tid == 0) a.cnt[ngrp] = 0u;
+      }
+    }
+    if (final_merge) {
       const bool fin = (rho < kInf) && (eta > 0.0f);
       const float inv_eta = fin ? 1.0f / eta : 0.0f;
-      for (int o = tid; o < T2; o += NT) {
-        const float d = lds[o] * inv_eta;
-        lds[o] = d;
-        a.stats[2 + o] = d;
+#pragma unroll
+      for (int j = 0; j < kOut; ++j) {
+        const int o = tid + j * NT;
+        if (o < T2) {
+          const float d = lds[o] * inv_eta;
+          lds[o] = d;
+          a.stats[2 + o] = d;
+        }
       }
       __syncthreads();
       if (fin && a.update_U) {
-        const int w = a.sg_window;
-        for (int o = tid; o < T2; o += NT) {
-          float upd;
-          if (w == 1) {
-            upd = lds[o];
-          } else {
-            const int t = o >> 1, c = o & 1;
-            const int lo = min(max(t - w / 2, 0), a.T - w);
-            const float* row = a.sg + (size_t)t * w;
-            upd = 0.0f;
-            for (int j = 0; j < w; ++j) upd = __builtin_fmaf(row[j], lds[2 * (lo + j) + c], upd);
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) {
+          const int o = tid + j * NT;
+          if (o < T2) {
+            float upd;
+            if (w == 1) {
+              upd = lds[o];
+            } else {
+              const int t = o >> 1, c = o & 1;
+              const int lo = min(max(t - w / 2, 0), a.T - w);
+              upd = 0.0f;
+              if (w <= kTapReg) {
+#pragma unroll
+                for (int i = 0; i < kTapReg; ++i)
+                  if (i < w) upd = __builtin_fmaf(taps[j][i], lds[2 * (lo + i) + c], upd);
+              } else {
+                const float* row = a.sg + (size_t)t * w;
+                for (int i = 0; i < w; ++i) upd = __builtin_fmaf(row[i], lds[2 * (lo + i) + c], upd);
+              }
+            }
+            a.Uout[o] = u_old[j] + upd;
           }
-          a.Uout[o] = a.Uout[o] + upd;
         }
       }
       if (tid == 0) {

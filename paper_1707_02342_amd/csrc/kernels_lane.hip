@@ -224,10 +224,12 @@ struct NetMfma {
 // Block partial and kernel
 // ---------------------------------------------------------------------------
 
-// Writes this block's (rho_g, eta_g, N_g[T][2]) by regenerating eps.
-__device__ __forceinline__ void lane_block_partial(const RolloutArgs& a, int tile, float S, bool valid,
-                                                   int k, float* red /* [kLaneWaves][2*kTMax] */,
-                                                   float* scratch) {
+// This block's (rho_g, eta_g, N_g[T][2]), N_g regenerating eps; N_g goes to N_lds
+// (complete after the block's next barrier).
+__device__ __forceinline__ void lane_block_partial(const RolloutArgs& a, float S, bool valid, int k,
+                                                   float* red /* [kLaneWaves][2*kTMax] */,
+                                                   float* scratch, float* N_lds, float& rho_out,
+                                                   float& eta_out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const float sv = valid ? S : kInf;
   const float rho = block_min<kLaneWaves>(sv, scratch);
@@ -244,18 +246,14 @@ __device__ __forceinline__ void lane_block_partial(const RolloutArgs& a, int til
     }
   }
   __syncthreads();
-  const int stride = 2 + 2 * a.T;
-  float* out = a.part + (size_t)tile * stride;
   for (int o = threadIdx.x; o < 2 * a.T; o += kLaneBlock) {
     float s = red[o];
 #pragma unroll
     for (int i = 1; i < kLaneWaves; ++i) s += red[i * 2 * kTMax + o];
-    out[2 + o] = s;
+    N_lds[o] = s;
   }
-  if (threadIdx.x == 0) {
-    out[0] = rho;
-    out[1] = eta;
-  }
+  rho_out = rho;
+  eta_out = eta;
 }
 
 // One tile of 256 samples of one problem (samples tile*256 ... tile*256 + 255).
@@ -304,9 +302,10 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   }
   float Sv = S.value();
   if (!ok || !finite_f(Sv)) Sv = kInf;
-  if (valid) a.S[k] = Sv;
-  lane_block_partial(a, tile, Sv, valid, k, red, scratch);
-  finish_iteration<kLaneBlock>(a, tile, red);
+  if (valid) store_through(a.S + k, Sv);   // read by the host only; kept out of L2
+  float rho, eta;
+  lane_block_partial(a, Sv, valid, k, red, scratch, sU, rho, eta);
+  finish_iteration<kLaneBlock>(a, tile, rho, eta, sU, red);
 }
 
 template <class Net>
@@ -325,13 +324,21 @@ __global__ __launch_bounds__(kLaneBlock) void rollout_lane_kernel(RolloutArgs a)
 // grid size and item order.
 __global__ __launch_bounds__(kLaneBlock) void rollout_batch_kernel(const RolloutArgs* __restrict__ inst,
                                                                  const int2* __restrict__ items,
-                                                                 int n_items) {
+                                                                 int n_items, const float* __restrict__ map,
+                                                                 const float* __restrict__ params,
+                                                                 const float* __restrict__ decay) {
   __shared__ float sU[2 * kTMax];
   __shared__ float red[kLaneWaves * 2 * kTMax];
   __shared__ float scratch[kLaneWaves];
   for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
     const int2 it = items[b];
     RolloutArgs a = inst[it.x];
+    // the shared inputs come from kernel arguments, so that the weights are read with
+    // scalar loads (through pointers loaded from memory they would be generic, loaded
+    // per lane and kept in registers)
+    a.map = map;
+    a.params = params;
+    a.decay = decay;
     a.nk.iter = *a.iter_dev;
     lane_rollout_tile<NetUniform<32>>(a, it.y, sU, red, scratch);
   }

@@ -34,7 +34,7 @@
 
 namespace mppi {
 
-template <int HID>
+template <int HID, int NQ>
 __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a) {
   static_assert(HID == 32, "the wave schedule maps 32 hidden units onto 32 lanes");
   extern __shared__ float smem[];
@@ -103,10 +103,10 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   // ---- A: noise ---------------------------------------------------------------------
   // (draws for steps past T use a clamped step index and are discarded; keeping the
   // chunks free of branches lets the independent draws interleave)
-  float ea[kWaveNT], eb[kWaveNT];
+  float ea[NQ], eb[NQ];
   const int NT = (T + 31) >> 5;
 #pragma unroll
-  for (int i = 0; i < kWaveNT; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     ea[i] = 0.0f;
     eb[i] = 0.0f;
     if (i < NT) {
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     }
   }
 #pragma unroll
-  for (int i = 0; i < kWaveNT; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     const int t = 32 * i + c32;
     if (i < NT && t < T) {
       myE[2 * t] = ea[i];
@@ -208,13 +208,16 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   // ---- C: kinematics and cost, parallel over t ---------------------------------------
   // Lane c owns the contiguous steps [c*npl, (c+1)*npl).  theta(t) = theta_0 + dt sum_{s<t}
   // theta_dot(s) and p(t+1) = p_0 + dt sum_{s<=t} R(theta(s)) v(s) are formed as
-  // compensated lane sums plus compensated exclusive scans across the 32 lanes.
-  const int npl = (T + 31) >> 5;
+  // compensated lane sums plus compensated exclusive scans across the 32 lanes.  The
+  // positions of all the lane's steps are formed first, then every map and decay load
+  // is issued before the first is used (one memory round trip), then the costs.
+  const int npl = NT;
   const int tb = c32 * npl;
   float th_h = 0.0f, th_l = 0.0f;
-  for (int q = 0; q < npl; ++q) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
     const int t = tb + q;
-    if (t < T) {
+    if (q < npl && t < T) {
       float s_, e_;
       two_sum(th_h, a.dt * myX[t].w, s_, e_);
       th_h = s_;
@@ -229,12 +232,12 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     th_l = th_l + e_;
   }
   // theta at the lane's first step; walk the steps for the position increments
-  float dpx[kWaveNT], dpy[kWaveNT];
+  float dpx[NQ], dpy[NQ];
   float px_h = 0.0f, px_l = 0.0f, py_h = 0.0f, py_l = 0.0f;
   {
     float th = th_h, thl = th_l;
 #pragma unroll
-    for (int q = 0; q < kWaveNT; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       dpx[q] = 0.0f;
       dpy[q] = 0.0f;
       const int t = tb + q;
@@ -268,16 +271,14 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     py_h = s_;
     py_l += e_;
   }
-  Acc Sacc{0.0f, 0.0f};
-  bool ok = true;
+  // post-step poses of the lane's steps (dead slots keep the last live pose)
+  float pxh[NQ], pxl[NQ], pyh[NQ], pyl[NQ], th1[NQ];
   {
     float th = th_h, thl = th_l;
 #pragma unroll
-    for (int q = 0; q < kWaveNT; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int t = tb + q;
       if (q < npl && t < T) {
-        const float4 xs = myX[t];
-        const float4 xn = myX[t + 1];
         float s_, e_;
         two_sum(px_h, dpx[q], s_, e_);
         px_h = s_;
@@ -285,20 +286,44 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
         two_sum(py_h, dpy[q], s_, e_);
         py_h = s_;
         py_l += e_;
-        two_sum(th, a.dt * xs.w, s_, e_);
+        two_sum(th, a.dt * myX[t].w, s_, e_);
         th = s_;
         thl += e_;
-        const float px1 = px_h + px_l, py1 = py_h + py_l, th1 = th + thl;
-        if (a.ckpt && ((t + 1) % a.ckpt_every) == 0 && valid) {
-          float* cp = a.ckpt + ((size_t)k * (T / a.ckpt_every + 1) + (t + 1) / a.ckpt_every) * kCkptStride;
-          cp[0] = px1; cp[1] = py1; cp[2] = th1;
-          cp[3] = xn.x; cp[4] = xn.y; cp[5] = xn.z; cp[6] = xn.w;
-        }
-        Sacc.add(state_cost2(a.cost, a.map, a.decay, px_h, px_l, py_h, py_l, xn.y, xn.z, t + 1));
-        Sacc.add(a.gcs0 * (sU[2 * t] * myE[2 * t]) + a.gcs1 * (sU[2 * t + 1] * myE[2 * t + 1]));
-        ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1) && finite_f(xn.x) &&
-             finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
       }
+      pxh[q] = px_h;
+      pxl[q] = px_l;
+      pyh[q] = py_h;
+      pyl[q] = py_l;
+      th1[q] = th + thl;
+    }
+  }
+  // all gathers at once (indices are clamped to the map, steps to [1, T])
+  float mv[NQ][4], fxv[NQ], fyv[NQ], dec[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    int idx[4];
+    map_taps(a.cost, pxh[q], pxl[q], pyh[q], pyl[q], idx, fxv[q], fyv[q]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mv[q][i] = a.map[idx[i]];
+    dec[q] = a.decay[min(tb + q, T - 1) + 1];
+  }
+  Acc Sacc{0.0f, 0.0f};
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int t = tb + q;
+    if (q < npl && t < T) {
+      const float4 xn = myX[t + 1];
+      const float px1 = pxh[q] + pxl[q], py1 = pyh[q] + pyl[q];
+      if (a.ckpt && ((t + 1) % a.ckpt_every) == 0 && valid) {
+        float* cp = a.ckpt + ((size_t)k * (T / a.ckpt_every + 1) + (t + 1) / a.ckpt_every) * kCkptStride;
+        cp[0] = px1; cp[1] = py1; cp[2] = th1[q];
+        cp[3] = xn.x; cp[4] = xn.y; cp[5] = xn.z; cp[6] = xn.w;
+      }
+      Sacc.add(state_cost_h(a.cost, bilerp(mv[q], fxv[q], fyv[q]), dec[q], xn.y, xn.z));
+      Sacc.add(a.gcs0 * (sU[2 * t] * myE[2 * t]) + a.gcs1 * (sU[2 * t + 1] * myE[2 * t + 1]));
+      ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1[q]) && finite_f(xn.x) &&
+           finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
     }
   }
   float S_h = Sacc.hi, S_l = Sacc.lo;
@@ -308,7 +333,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
 #pragma unroll
   for (int m = 16; m >= 1; m >>= 1) okc &= __shfl_xor(okc, m, 32);
   if (!valid || !okc || !finite_f(S)) S = kInf;
-  if (valid && c32 == 0) a.S[k] = S;
+  if (valid && c32 == 0) store_through(a.S + k, S);   // read by the host only; kept out of L2
 
   // ---- D: softmin partial of the block's samples ------------------------------------
   const float wmin = fminf(S, __shfl_xor(S, 32, 64));
@@ -320,7 +345,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   if (lane == 0) scratch[4 + wv] = epair;
   const int eStrideRed = eStride;
 #pragma unroll
-  for (int i = 0; i < kWaveNT; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     if (i < NT) {
       const int t = 32 * i + c32;
       const float n0 = e * ea[i], n1 = e * eb[i];
@@ -333,18 +358,15 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     }
   }
   __syncthreads();
-  const int stride = 2 + 2 * T;
-  float* out = a.part + (size_t)blockIdx.x * stride;
+  float* N_lds = sE;   // the noise rows are no longer read
   for (int o = threadIdx.x; o < 2 * T; o += kWaveBlock)
-    out[2 + o] = ((red[o] + red[eStrideRed + o]) + red[2 * eStrideRed + o]) + red[3 * eStrideRed + o];
-  if (threadIdx.x == 0) {
-    out[0] = rho;
-    out[1] = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
-  }
-  finish_iteration<kWaveBlock>(a, blockIdx.x, red);
+    N_lds[o] = ((red[o] + red[eStrideRed + o]) + red[2 * eStrideRed + o]) + red[3 * eStrideRed + o];
+  const float eta = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
+  finish_iteration<kWaveBlock>(a, blockIdx.x, rho, eta, N_lds, red);
 }
 
-template __global__ void rollout_wave_kernel<32>(RolloutArgs);
+template __global__ void rollout_wave_kernel<32, 4>(RolloutArgs);
+template __global__ void rollout_wave_kernel<32, 8>(RolloutArgs);
 
 // Dynamic LDS bytes the wave kernel needs for horizon T.
 size_t wave_smem_bytes(int T) {

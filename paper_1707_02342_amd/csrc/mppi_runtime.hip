@@ -20,7 +20,7 @@
 
 namespace mppi {
 hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
-template <int HID> __global__ void rollout_wave_kernel(RolloutArgs);
+template <int HID, int NQ> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T);
 __global__ void shift_kernel(float*, int, float*);
 template <int HID>
@@ -48,7 +48,7 @@ constexpr int32_t kMaxK = 1 << 22;
 constexpr int32_t kWaveAutoMaxK = 32768;
 
 struct PendingTiming {
-  hipEvent_t e0, e1, e2;
+  hipEvent_t e0, e1;
 };
 
 }  // namespace
@@ -209,17 +209,13 @@ hipEvent_t take_event(mppi_ctx* c) {
 
 mppi_status drain_timing(mppi_ctx* c) {
   for (auto& p : c->pending) {
-    HIP_TRY(c, hipEventSynchronize(p.e2));
-    float a = 0, b = 0;
+    HIP_TRY(c, hipEventSynchronize(p.e1));
+    float a = 0;
     HIP_TRY(c, hipEventElapsedTime(&a, p.e0, p.e1));
-    HIP_TRY(c, hipEventElapsedTime(&b, p.e1, p.e2));
     c->t_ms[0] += a;
-    c->t_ms[1] += b;
     c->t_cnt[0] += 1;
-    c->t_cnt[1] += 1;
     c->event_pool.push_back(p.e0);
     c->event_pool.push_back(p.e1);
-    c->event_pool.push_back(p.e2);
   }
   c->pending.clear();
   return MPPI_OK;
@@ -229,6 +225,15 @@ int blocks_for(const mppi_ctx* c, int sched) {
   const int K = c->cfg.K;
   if (sched == MPPI_SCHED_WAVE) return (K + kWaveSamplesPerBlock - 1) / kWaveSamplesPerBlock;
   return (K + kLaneBlockHost - 1) / kLaneBlockHost;
+}
+
+// The wave kernel keeps each lane's share of the steps (ceil(T/32) of them) in
+// registers; it is compiled for up to 4 (T <= 128) and up to 8 (T <= 256).
+void launch_wave(int G, int T, hipStream_t stream, const RolloutArgs& a) {
+  if (T <= 128)
+    hipLaunchKernelGGL((rollout_wave_kernel<32, 4>), dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), stream, a);
+  else
+    hipLaunchKernelGGL((rollout_wave_kernel<32, 8>), dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), stream, a);
 }
 
 RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x0_dev) {
@@ -298,21 +303,18 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   if (c->timing) {
     pt.e0 = take_event(c);
     pt.e1 = take_event(c);
-    pt.e2 = take_event(c);
-    if (!pt.e0 || !pt.e1 || !pt.e2) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
+    if (!pt.e0 || !pt.e1) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
     HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
   }
   if (sched == MPPI_SCHED_WAVE) {
     if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
-    hipLaunchKernelGGL(rollout_wave_kernel<32>, dim3(G), dim3(kWaveBlockThreads),
-                       wave_smem_bytes(c->cfg.T), c->stream, a);
+    launch_wave(G, c->cfg.T, c->stream, a);
   } else {
     HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
   }
   HIP_TRY(c, hipGetLastError());
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
-    HIP_TRY(c, hipEventRecord(pt.e2, c->stream));
     c->pending.push_back(pt);
     if (c->pending.size() >= 512) {
       mppi_status st = drain_timing(c);
@@ -370,7 +372,6 @@ void free_all(mppi_ctx* c) {
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
-    (void)hipEventDestroy(p.e2);
   }
   c->pending.clear();
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
@@ -742,7 +743,7 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
     a.ckpt_every = ckpt_every;
     a.G = G;
     a.update_U = 0;
-    hipLaunchKernelGGL(rollout_wave_kernel<32>, dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), c->stream, a);
+    launch_wave(G, T, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     float st2[2];
     HIP_TRY(c, hipMemcpyAsync(st2, c->d_stats, sizeof(float) * 2, hipMemcpyDeviceToHost, c->stream));
@@ -812,7 +813,7 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
 // Batched form: many independent MPPI problems in one persistent launch
 // ===========================================================================
 namespace mppi {
-__global__ void rollout_batch_kernel(const RolloutArgs*, const int2*, int);
+__global__ void rollout_batch_kernel(const RolloutArgs*, const int2*, int, const float*, const float*, const float*);
 }
 
 struct mppi_batch {
@@ -965,7 +966,8 @@ std::vector<int2> batch_items(const mppi_batch* b, int order) {
 
 mppi_status batch_launch(mppi_batch* b, int grid) {
   hipLaunchKernelGGL(rollout_batch_kernel, dim3(grid), dim3(kLaneBlockHost), 0, b->stream,
-                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items);
+                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
+                     (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
   BHIP_TRY(b, hipGetLastError());
   return MPPI_OK;
 }
@@ -1029,10 +1031,16 @@ mppi_status batch_prepare(mppi_batch* b) {
   BHIP_TRY(b, hipMemcpy(b->d_args, args.data(), sizeof(RolloutArgs) * args.size(), hipMemcpyHostToDevice));
   mppi_status st = batch_autotune(b);
   if (st != MPPI_OK) return st;
-  // capture the chosen launch once; every iteration replays it
+  // capture the chosen launch once; every iteration replays it (a new cost map or
+  // network re-captures, since their pointers are kernel arguments)
+  if (b->exec) BHIP_TRY(b, hipGraphExecDestroy(b->exec));
+  b->exec = nullptr;
+  if (b->graph) BHIP_TRY(b, hipGraphDestroy(b->graph));
+  b->graph = nullptr;
   BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipLaunchKernelGGL(rollout_batch_kernel, dim3(b->grid), dim3(kLaneBlockHost), 0, b->stream,
-                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items);
+                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
+                     (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
   hipError_t le = hipGetLastError();
   hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
   if (le != hipSuccess) return bfail(b, MPPI_E_DEVICE, "capture launch: %s", hipGetErrorString(le));

@@ -187,6 +187,35 @@ def test_batch_full_size_spot_checks(M, orc):
         assert rel.max() <= 1e-4   # second iteration starts from the GPU's own first update
 
 
+def test_batch_new_map_and_network_take_effect(M):
+    """The cost map and the network are kernel arguments of the captured launch: after
+    replacing them, the next iteration must use the new ones (re-captured graph)."""
+    base = synth.c2_problem(seed=11)
+    Ks, Ts = [256, 700, 300], [30, 25, 40]
+    x0s = np.stack([synth.ellipse_pose(p, 6.0) for p in (0.3, 2.0, 4.4)])
+    m1, m2 = synth.ellipse_map(), synth.ring_map()
+    p1, p2 = synth.mlp_params(32, 0), synth.mlp_params(32, 3)
+    with M.Batch(base, Ks, Ts, m1, p1) as b:
+        b.iterate(x0s)
+        M.mppi_batch_set_costmap(b.b, m2.data, m2.origin_x, m2.origin_y, m2.resolution)
+        M.mppi_batch_set_dynamics(b.b, p2)
+        b.iterate(x0s)
+        b.synchronize()
+        got = [(b.controls(i), b.costs(i)) for i in range(3)]
+    for i in range(3):
+        p = synth.with_(base, K=Ks[i], T=Ts[i], instance=i)
+        with M.Controller(p, m1, p1, schedule=1) as c:
+            c.iterate(x0s[i])
+            U1 = c.controls()
+        with M.Controller(p, m2, p2, schedule=1) as c:
+            c.set_controls(U1)
+            c.iteration = 1
+            S, _ = c.iterate(x0s[i], want_costs=True)
+            U = c.controls()
+        np.testing.assert_array_equal(got[i][0], U, err_msg=f"instance {i} controls")
+        np.testing.assert_array_equal(got[i][1], S, err_msg=f"instance {i} costs")
+
+
 def test_batch_rejects_bad_shapes(M):
     base = synth.c2_problem()
     cfg, cost = M.make_config(base), M.make_cost(base.cost)
