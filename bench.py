@@ -27,6 +27,11 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
+TRAFFIC_FILE = ROOT / "profiles" / "rollout_wave_k1920_t100_traffic.json"
+# the sources the benchmarked kernel (rollout_wave_kernel<32, 4>) is built from: stored
+# counter readings are used only while these files are unchanged
+KERNEL_SOURCES = ["kernels_wave.hip", "wave_common.hip.h", "kernels_common.hip.h", "device_common.h",
+                  "mppi_types.h"]
 NET_FLOP_PER_STEP = {32: 2 * (6 * 32 + 32 * 32 + 32 * 4), 64: 2 * (6 * 64 + 64 * 64 + 64 * 4)}
 
 
@@ -39,7 +44,94 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision/batched/differentiation forms")
+    ap.add_argument("--write-traffic", metavar="PMC_DIR",
+                    help="reduce rocprofv3 FETCH_SIZE/WRITE_SIZE runs under PMC_DIR to the stored traffic "
+                         "record under profiles/ and exit")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device-to-device copy five times (reference for the "
+                         "profiler's HBM byte counters) and exit")
     return ap.parse_args()
+
+
+COPY_BYTES = 256 << 20
+
+
+def calibrate_copy():
+    """Five copies of COPY_BYTES between two device buffers: a kernel whose HBM traffic
+    is known (COPY_BYTES read and COPY_BYTES written per launch), against which the
+    FETCH_SIZE and WRITE_SIZE counters are scaled."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update((ROOT / "paper_1707_02342_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the benchmarked kernel from the profiler's FETCH_SIZE and
+    WRITE_SIZE counters (scaled by a copy of known size), or None when the kernel's
+    sources changed after the counters were taken."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    rec = json.loads(TRAFFIC_FILE.read_text())
+    if rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def write_traffic(pmc_dir: str):
+    """Reduce four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the benchmark and
+    of --calibrate-copy, CSV output under pmc_dir/{FETCH_SIZE,WRITE_SIZE,FETCH_SIZE_copy,
+    WRITE_SIZE_copy}/) to per-launch HBM bytes of the rollout kernel."""
+    import csv
+    import glob
+
+    def per_dispatch(sub, match):
+        f = glob.glob(os.path.join(pmc_dir, sub, "*_counter_collection.csv"))[0]
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(f)) if match(r["Kernel_Name"])]
+        return float(np.median(vals)), len(vals)
+
+    is_roll = lambda n: "rollout_wave_kernel<32, 4>" in n
+    is_copy = lambda n: "copyBuffer" in n or "elementwise" in n
+    fetch, nf = per_dispatch("FETCH_SIZE", is_roll)
+    write, nw = per_dispatch("WRITE_SIZE", is_roll)
+    # the copy kernel's dispatches: the largest reading is the 256 MiB copy
+    def largest(sub):
+        f = glob.glob(os.path.join(pmc_dir, sub, "*_counter_collection.csv"))[0]
+        return max(float(r["Counter_Value"]) for r in csv.DictReader(open(f)) if is_copy(r["Kernel_Name"]))
+    kib = COPY_BYTES / 1024.0
+    fetch_scale = kib / largest("FETCH_SIZE_copy")
+    write_scale = kib / largest("WRITE_SIZE_copy")
+    rec = {"kernel": "rollout_wave_kernel<32, 4>",
+           "workload": "K=1920, T=100, 6-32-32-4 network, 2048x2048 map (bench.py default)",
+           "sources_sha256": kernel_sources_sha256(),
+           "fetch_size_kib_per_launch_median": fetch, "fetch_dispatches": nf, "fetch_scale": fetch_scale,
+           "write_size_kib_per_launch_median": write, "write_dispatches": nw, "write_scale": write_scale,
+           "traffic_bytes_per_launch": (fetch * fetch_scale + write * write_scale) * 1024.0,
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/FETCH_SIZE -o c2 -- "
+                        "python3 bench.py --steps 20 --warmup 5 --no-cpu --no-forms --latency-iters 5",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/WRITE_SIZE -o c2 -- "
+                        "python3 bench.py --steps 20 --warmup 5 --no-cpu --no-forms --latency-iters 5",
+                        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/FETCH_SIZE_copy -o copy -- "
+                        "python3 bench.py --calibrate-copy",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/WRITE_SIZE_copy -o copy -- "
+                        "python3 bench.py --calibrate-copy",
+                        "python3 bench.py --write-traffic <dir>"]}
+    TRAFFIC_FILE.parent.mkdir(exist_ok=True)
+    TRAFFIC_FILE.write_text(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec), flush=True)
 
 
 def cpu_baseline(prob, cmap, params, x0, budget_s: float):
@@ -63,12 +155,91 @@ def cpu_baseline(prob, cmap, params, x0, budget_s: float):
                       f"{el:.1f} s"}
 
 
+def _timed_iterations(ctl, x0, n, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        ctl.iterate(x0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n          # ms per iteration
+
+
+def measure_forms(M, stream, iters: int = 30):
+    """The three added forms on their own workloads (synthetic, seeded):
+    precision: K=16384, T=100, 6-64-64-4 network, one iteration in FP32 (lane schedule)
+      and with BF16 / FP16 matrix-core operands (FP32 accumulation);
+    batched: 512 instances (K_i in 512..4096, T_i in 50..150) advanced by one replayed
+      graph launch per iteration;
+    differentiation: K=4096, T=100, free-energy objective plus its adjoint gradient
+      with checkpoints every 10 steps."""
+    import torch
+    import synth
+    out = {}
+    prob = synth.c3_problem(K=16384, seed=0)
+    params = synth.mlp_params(64, 0)
+    cmap = synth.ring_map()
+    prec = {}
+    for name, p in (("fp32", M.MPPI_PREC_FP32), ("bf16", M.MPPI_PREC_BF16), ("fp16", M.MPPI_PREC_FP16)):
+        ctl = M.Controller(prob, cmap, params, stream=int(stream.cuda_stream), precision=p)
+        for _ in range(3):
+            ctl.iterate(synth.C1_X0)
+        ms = _timed_iterations(ctl, synth.C1_X0, iters, stream)
+        ctl.close()
+        prec[name] = {"ms_per_iteration": ms, "steps_per_s": prob.K * prob.T / (ms * 1e-3)}
+    prec["bf16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["bf16"]["ms_per_iteration"]
+    prec["fp16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["fp16"]["ms_per_iteration"]
+    prec["workload"] = "K=16384, T=100, 6-64-64-4 network, 256x256 ring map"
+    out["precision"] = prec
+
+    inst = synth.c4_instances(512, seed=0)
+    Ks, Ts = [b.K for b in inst], [b.T for b in inst]
+    x0s = np.stack([b.x0 for b in inst])
+    with M.Batch(synth.c2_problem(seed=0), Ks, Ts, synth.ellipse_map(), synth.mlp_params(32, 0)) as b:
+        b.iterate(x0s)              # autotunes and captures the launch
+        b.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            b.iterate(x0s)
+        b.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+        grid, order, tuned_us = b.schedule()
+    work = float(sum(k * t for k, t in zip(Ks, Ts)))
+    out["batched"] = {"ms_per_iteration": ms, "steps_per_s": work / (ms * 1e-3), "instances": len(Ks),
+                      "grid": grid, "order": order,
+                      "workload": "512 instances, K_i in {512..4096}, T_i in {50..150}, 2048x2048 map"}
+
+    prob = synth.c5_problem(seed=0)
+    U = synth.random_controls(prob.T, 0, scale=0.2)
+    with M.Controller(prob, synth.ring_map(), synth.mlp_params(32, 0), stream=int(stream.cuda_stream)) as c:
+        c.set_controls(U)
+        for _ in range(2):
+            c.objective(synth.C1_X0, 0, 10)
+            c.objective_backward()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            c.objective(synth.C1_X0, 0, 10)
+            c.objective_backward()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+    out["differentiation"] = {"ms_per_value_and_gradient": ms,
+                              "workload": "K=4096, T=100, checkpoints every 10 steps, 1612 gradient entries"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     import torch
     import synth
     from paper_1707_02342_amd import mppi as M
@@ -121,6 +292,7 @@ def main():
     roll_ms = t_roll / max(n_roll, 1)
     flop = NET_FLOP_PER_STEP[prob.hidden] * K * T
     achieved = flop / (roll_ms * 1e-3) / 1e12
+    traffic = stored_traffic() if ctl.schedule == M.MPPI_SCHED_WAVE else None
     out = {
         "metric": "MPPI rollout steps/sec (K×T per s) and iteration latency at K=1920,T=100",
         "value": value,
@@ -141,10 +313,12 @@ def main():
                        "rollout_kernel": roll_ms * 1e3,
                        "host_p50": float(np.percentile(lat, 50)), "host_p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "rollout", "flop_per_launch": flop},
     }
     ctl.close()
+    if not args.no_forms:
+        out["forms"] = measure_forms(M, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, cmap, params, x0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

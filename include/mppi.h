@@ -54,8 +54,12 @@ typedef enum {
 
 enum { MPPI_PREC_FP32 = 0, MPPI_PREC_BF16 = 1, MPPI_PREC_FP16 = 2 };
 
-/* Kernel schedule for the rollout (0 = pick automatically). */
-enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2 };
+/* Kernel schedule for the rollout (0 = pick automatically).  LANE: one sample per
+ * lane (any K; FP32, BF16 or FP16 network, h = 32 or 64).  WAVE: 32 lanes per sample,
+ * two samples per wavefront.  WIDE: 64 lanes (a whole wavefront) per sample.  WAVE and
+ * WIDE run the FP32 network with h = 32 and suit a few thousand samples, where one
+ * lane per sample leaves most of the device idle. */
+enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2, MPPI_SCHED_WIDE = 3 };
 
 #define MPPI_T_MAX 256
 #define MPPI_STATE_DIM 7
@@ -168,7 +172,7 @@ mppi_status mppi_get_noise(mppi_ctx* ctx, uint32_t iter, float* eps_out);
 mppi_status mppi_get_iteration(const mppi_ctx* ctx, uint32_t* iter);
 mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iter);
 
-/* Rollout schedule actually used (MPPI_SCHED_LANE or MPPI_SCHED_WAVE). */
+/* Rollout schedule actually used (MPPI_SCHED_LANE, _WAVE or _WIDE). */
 mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
 
 /* Device time of the iteration kernel, measured with HIP events recorded on the

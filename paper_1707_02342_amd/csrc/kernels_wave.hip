@@ -143,10 +143,14 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
     acc1 = __builtin_fmaf(w1[5], vc1, acc1);
     const float xh = xd.hi;
-    FMAC_DPP_FIRST(acc1, xh, w1[0], "quad_perm:[0,0,0,0]");
-    FMAC_DPP(acc1, xh, w1[1], "quad_perm:[1,1,1,1]");
-    FMAC_DPP(acc1, xh, w1[2], "quad_perm:[2,2,2,2]");
-    FMAC_DPP(acc1, xh, w1[3], "quad_perm:[3,3,3,3]");
+    // one asm block, so that no wait states are inserted between the four
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 quad_perm:[3,3,3,3] row_mask:0xf bank_mask:0xf"
+        : "+v"(acc1) : "v"(xh), "v"(w1[0]), "v"(w1[1]), "v"(w1[2]), "v"(w1[3]));
     const float h1 = tanh_f(acc1);
     // layer 2: four interleaved chains (P, Q for even and odd rotations) so that no
     // accumulator is read by the instruction right after the one that wrote it
@@ -154,34 +158,40 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     float Q = __builtin_fmaf(wQ[0], h1, bQ);
     float P2 = wP[1] * dpp_f<kRowRor + 1>(h1);
     float Q2 = wQ[1] * dpp_f<kRowRor + 1>(h1);
-    FMAC_DPP_FIRST(P, h1, wP[2], "row_ror:2");
-    FMAC_DPP(Q, h1, wQ[2], "row_ror:2");
-    FMAC_DPP(P2, h1, wP[3], "row_ror:3");
-    FMAC_DPP(Q2, h1, wQ[3], "row_ror:3");
-    FMAC_DPP(P, h1, wP[4], "row_ror:4");
-    FMAC_DPP(Q, h1, wQ[4], "row_ror:4");
-    FMAC_DPP(P2, h1, wP[5], "row_ror:5");
-    FMAC_DPP(Q2, h1, wQ[5], "row_ror:5");
-    FMAC_DPP(P, h1, wP[6], "row_ror:6");
-    FMAC_DPP(Q, h1, wQ[6], "row_ror:6");
-    FMAC_DPP(P2, h1, wP[7], "row_ror:7");
-    FMAC_DPP(Q2, h1, wQ[7], "row_ror:7");
-    FMAC_DPP(P, h1, wP[8], "row_ror:8");
-    FMAC_DPP(Q, h1, wQ[8], "row_ror:8");
-    FMAC_DPP(P2, h1, wP[9], "row_ror:9");
-    FMAC_DPP(Q2, h1, wQ[9], "row_ror:9");
-    FMAC_DPP(P, h1, wP[10], "row_ror:10");
-    FMAC_DPP(Q, h1, wQ[10], "row_ror:10");
-    FMAC_DPP(P2, h1, wP[11], "row_ror:11");
-    FMAC_DPP(Q2, h1, wQ[11], "row_ror:11");
-    FMAC_DPP(P, h1, wP[12], "row_ror:12");
-    FMAC_DPP(Q, h1, wQ[12], "row_ror:12");
-    FMAC_DPP(P2, h1, wP[13], "row_ror:13");
-    FMAC_DPP(Q2, h1, wQ[13], "row_ror:13");
-    FMAC_DPP(P, h1, wP[14], "row_ror:14");
-    FMAC_DPP(Q, h1, wQ[14], "row_ror:14");
-    FMAC_DPP(P2, h1, wP[15], "row_ror:15");
-    FMAC_DPP(Q2, h1, wQ[15], "row_ror:15");
+    // rotations 2..15 in one asm block (no wait states inserted between them); the
+    // DPP source h1 was written two instructions before (the nop covers the hazard)
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %4, %5 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %6 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %7 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %8 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %9 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %10 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %11 row_ror:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %12 row_ror:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %13 row_ror:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %14 row_ror:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %15 row_ror:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %16 row_ror:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %17 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %18 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %19 row_ror:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %20 row_ror:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %21 row_ror:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %22 row_ror:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %23 row_ror:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %24 row_ror:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %25 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %26 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %27 row_ror:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %28 row_ror:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %29 row_ror:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %30 row_ror:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %31 row_ror:15 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %32 row_ror:15 row_mask:0xf bank_mask:0xf"
+        : "+v"(P), "+v"(Q), "+v"(P2), "+v"(Q2)
+        : "v"(h1), "v"(wP[2]), "v"(wQ[2]), "v"(wP[3]), "v"(wQ[3]), "v"(wP[4]), "v"(wQ[4]), "v"(wP[5]), "v"(wQ[5]), "v"(wP[6]), "v"(wQ[6]), "v"(wP[7]), "v"(wQ[7]), "v"(wP[8]), "v"(wQ[8]), "v"(wP[9]), "v"(wQ[9]), "v"(wP[10]), "v"(wQ[10]), "v"(wP[11]), "v"(wQ[11]), "v"(wP[12]), "v"(wQ[12]), "v"(wP[13]), "v"(wQ[13]), "v"(wP[14]), "v"(wQ[14]), "v"(wP[15]), "v"(wQ[15]));
     P = P + P2;
     Q = Q + Q2;
     swap_rows(P, Q);                    // row 0: (P0, P1) -> out c;  row 1: (Q0, Q1) -> out 16+c

@@ -22,6 +22,8 @@ namespace mppi {
 hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
 template <int HID, int NQ> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T);
+size_t wide_smem_bytes(int T);
+template <int NQ> __global__ void rollout_wide_kernel(RolloutArgs);
 __global__ void shift_kernel(float*, int, float*);
 template <int HID>
 __global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
@@ -34,6 +36,8 @@ constexpr int kNP32Host = 1412;
 constexpr int kLaneBlockHost = 256;
 constexpr int kWaveSamplesPerBlock = 8;   // 4 waves x 2 samples of 32 lanes
 constexpr int kWaveBlockThreads = 256;
+constexpr int kWideSamplesPerBlock = 8;   // 8 waves x 1 sample of 64 lanes
+constexpr int kWideBlockThreads = 512;
 }  // namespace mppi
 
 using namespace mppi;
@@ -119,7 +123,11 @@ mppi_status fail(mppi_ctx* c, mppi_status st, const char* fmt, ...) {
 
 bool finite(float v) { return std::isfinite(v); }
 
-int sched_ok(int s) { return s == MPPI_SCHED_AUTO || s == MPPI_SCHED_LANE || s == MPPI_SCHED_WAVE; }
+int sched_ok(int s) {
+  return s == MPPI_SCHED_AUTO || s == MPPI_SCHED_LANE || s == MPPI_SCHED_WAVE || s == MPPI_SCHED_WIDE;
+}
+// The schedules that spread one sample over several lanes (FP32, h = 32 only).
+bool multi_lane(int s) { return s == MPPI_SCHED_WAVE || s == MPPI_SCHED_WIDE; }
 
 mppi_status validate_config(const mppi_config* c) {
   if (!c) return fail(nullptr, MPPI_E_INVAL, "config is NULL");
@@ -224,6 +232,7 @@ mppi_status drain_timing(mppi_ctx* c) {
 int blocks_for(const mppi_ctx* c, int sched) {
   const int K = c->cfg.K;
   if (sched == MPPI_SCHED_WAVE) return (K + kWaveSamplesPerBlock - 1) / kWaveSamplesPerBlock;
+  if (sched == MPPI_SCHED_WIDE) return (K + kWideSamplesPerBlock - 1) / kWideSamplesPerBlock;
   return (K + kLaneBlockHost - 1) / kLaneBlockHost;
 }
 
@@ -234,6 +243,15 @@ void launch_wave(int G, int T, hipStream_t stream, const RolloutArgs& a) {
     hipLaunchKernelGGL((rollout_wave_kernel<32, 4>), dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), stream, a);
   else
     hipLaunchKernelGGL((rollout_wave_kernel<32, 8>), dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), stream, a);
+}
+
+// The wide kernel keeps ceil(T/64) steps per lane in registers: up to 2 (T <= 128)
+// or up to 4 (T <= 256).
+void launch_wide(int G, int T, hipStream_t stream, const RolloutArgs& a) {
+  if (T <= 128)
+    hipLaunchKernelGGL((rollout_wide_kernel<2>), dim3(G), dim3(kWideBlockThreads), wide_smem_bytes(T), stream, a);
+  else
+    hipLaunchKernelGGL((rollout_wide_kernel<4>), dim3(G), dim3(kWideBlockThreads), wide_smem_bytes(T), stream, a);
 }
 
 RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x0_dev) {
@@ -309,6 +327,9 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   if (sched == MPPI_SCHED_WAVE) {
     if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
     launch_wave(G, c->cfg.T, c->stream, a);
+  } else if (sched == MPPI_SCHED_WIDE) {
+    if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wide schedule supports hidden 32 only");
+    launch_wide(G, c->cfg.T, c->stream, a);
   } else {
     HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
   }
@@ -411,13 +432,15 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     c->sig[0] = std::sqrt(cfg->sigma2[0]);
     c->sig[1] = std::sqrt(cfg->sigma2[1]);
     c->schedule = cfg->schedule;
-    c->part_cap = std::max(blocks_for(c, MPPI_SCHED_LANE), blocks_for(c, MPPI_SCHED_WAVE));
+    c->part_cap = std::max({blocks_for(c, MPPI_SCHED_LANE), blocks_for(c, MPPI_SCHED_WAVE),
+                            blocks_for(c, MPPI_SCHED_WIDE)});
     HIP_TRY(c, hipMalloc(&c->d_U, sizeof(float) * 2 * T));
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
-    const int ngrp_cap = std::max(merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
-                                  merge_groups(blocks_for(c, MPPI_SCHED_WAVE)));
+    const int ngrp_cap = std::max({merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
+                                   merge_groups(blocks_for(c, MPPI_SCHED_WAVE)),
+                                   merge_groups(blocks_for(c, MPPI_SCHED_WIDE))});
     HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)ngrp_cap * (2 + 2 * T)));
     HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(unsigned) * (ngrp_cap + 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (ngrp_cap + 1), c->stream));
@@ -493,10 +516,10 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     const int h = dims[1];
     if (dims[0] != 6 || dims[3] != 4 || dims[1] != dims[2] || (h != 32 && h != 64))
       return fail(c, MPPI_E_INVAL, "dims must be {6, h, h, 4} with h = 32 or 64");
-    if (c->cfg.precision != MPPI_PREC_FP32 && c->cfg.schedule == MPPI_SCHED_WAVE)
-      return fail(c, MPPI_E_INVAL, "the wave schedule runs the FP32 network only");
-    if (c->cfg.schedule == MPPI_SCHED_WAVE && h != 32)
-      return fail(c, MPPI_E_INVAL, "the wave schedule supports h = 32 only");
+    if (c->cfg.precision != MPPI_PREC_FP32 && multi_lane(c->cfg.schedule))
+      return fail(c, MPPI_E_INVAL, "the wave and wide schedules run the FP32 network only");
+    if (multi_lane(c->cfg.schedule) && h != 32)
+      return fail(c, MPPI_E_INVAL, "the wave and wide schedules support h = 32 only");
     const size_t n = (size_t)6 * h + h + (size_t)h * h + h + 4 * (size_t)h + 4;
     for (size_t i = 0; i < n; ++i)
       if (!finite(params[i])) return fail(c, MPPI_E_INVAL, "parameter %zu is not finite", i);

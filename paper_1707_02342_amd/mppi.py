@@ -17,7 +17,7 @@ LIB_PATH = PKG / "libmppi.so"
 
 MPPI_OK, MPPI_E_INVAL, MPPI_E_STATE, MPPI_E_NOMEM, MPPI_E_DEVICE, MPPI_E_NONFINITE = range(6)
 MPPI_PREC_FP32, MPPI_PREC_BF16, MPPI_PREC_FP16 = 0, 1, 2
-MPPI_SCHED_AUTO, MPPI_SCHED_LANE, MPPI_SCHED_WAVE = 0, 1, 2
+MPPI_SCHED_AUTO, MPPI_SCHED_LANE, MPPI_SCHED_WAVE, MPPI_SCHED_WIDE = 0, 1, 2, 3
 MPPI_T_MAX = 256
 
 STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_NOMEM",

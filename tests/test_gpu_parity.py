@@ -47,7 +47,7 @@ def _say(*a):
 
 
 def _schedules():
-    return [1, 2]
+    return [1, 2, 3]
 
 
 # ---------------------------------------------------------------------------
@@ -172,10 +172,10 @@ def test_ragged_shapes(M, orc, schedule, K, T):
                      synth.random_controls(T, K), schedule)
 
 
-@pytest.mark.parametrize("schedule,K", [(2, 2049), (2, 4100), (2, 32768), (1, 65537), (1, 70000)])
+@pytest.mark.parametrize("schedule,K", [(2, 2049), (2, 4100), (2, 32768), (3, 2049), (3, 4100), (1, 65537), (1, 70000)])
 def test_many_blocks(M, orc, schedule, K):
     """Launches of more than 256 blocks: the partial rows are merged in groups of
-    ceil(sqrt(G)) blocks (wave: 8 samples per block, lane: 256)."""
+    ceil(sqrt(G)) blocks (wave and wide: 8 samples per block, lane: 256)."""
     T = 12
     prob = synth.with_(synth.c1_problem(seed=K), K=K, T=T)
     _say("many blocks", schedule, K)
@@ -201,8 +201,8 @@ def test_paper_shaped_full_iteration(M, orc, schedule):
 
 @pytest.mark.parametrize("schedule", _schedules())
 def test_hidden64_fp32(M, orc, schedule):
-    if schedule == 2:
-        pytest.skip("wave schedule is h = 32 only")
+    if schedule in (2, 3):
+        pytest.skip("the wave and wide schedules are h = 32 only")
     prob = synth.with_(synth.c3_problem(K=1024), T=40)
     _check_iteration(M, orc, prob, synth.ring_map(), synth.mlp_params(64, 0), synth.C1_X0,
                      synth.random_controls(40, 9), schedule)
