@@ -1,16 +1,20 @@
 """Benchmark: MPPI rollout steps/s (K x T per second) and iteration latency on one MI355X.
 
-Workload: the paper-shaped configuration, K = 1920 samples, T = 100 steps, dt = 0.02,
-the 6-32-32-4 tanh network (1412 parameters, Xavier-uniform, seed 0), a 2048 x 2048
-elliptical track cost map at 0.05 m/cell, speed/slip/crash costs, lambda = 6.7,
-Savitzky-Golay window 9.  One step = one MPPI iteration (noise, rollouts, weights,
-weighted perturbation sum, smoothing, update) through the C ABI, warm-started from
-the previous iteration's controls; all inputs are resident in HBM before timing.
+Workload: the paper-shaped receding-horizon configuration, K = 1920 samples, T = 100
+steps, dt = 0.02, the 6-32-32-4 tanh network (1412 parameters, Xavier-uniform, seed 0),
+a 2048 x 2048 elliptical track cost map at 0.05 m/cell, speed/slip/crash costs,
+lambda = 6.7, Savitzky-Golay window 9; 100 warm-started iterations per Philox seed
+0..9 on a synthetic plant (the same network, noise-free).  One step = one control
+step: an MPPI iteration (noise, rollouts, weights, weighted perturbation sum,
+smoothing, update), the shift of U and the plant step, fused in one kernel launch
+and driven through the C ABI (mppi_run_receding); all inputs are resident in HBM
+before timing.
 
-Prints one JSON line with the throughput, the rollout kernel's roofline figures
-(algorithmic FLOP of the dynamics network per launch over the kernel's average
-duration, measured with HIP events on the library's stream) and the CPU oracle's
-throughput on a bounded sample of the same workload.
+Prints one JSON line with the throughput, launch and host latencies (eager and
+HIP-graph-replayed), the launch's roofline figures (algorithmic FLOP of the dynamics
+network over the launch's average duration, measured with HIP events on the
+library's stream), the precision / batched / differentiation forms, and the CPU
+oracle's throughput on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -38,12 +42,12 @@ NET_FLOP_PER_STEP = {32: 2 * (6 * 32 + 32 * 32 + 32 * 4), 64: 2 * (6 * 64 + 64 *
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000, help="receding-horizon steps (100 per seed in turn)")
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--schedule", type=int, default=0, help="0 auto, 1 lane, 2 wave")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision/batched/differentiation forms")
     ap.add_argument("--write-traffic", metavar="PMC_DIR",
                     help="reduce rocprofv3 FETCH_SIZE/WRITE_SIZE runs under PMC_DIR to the stored traffic "
@@ -247,23 +251,42 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    prob = synth.c2_problem(seed=0)
     cmap = synth.ellipse_map()
+    prob = synth.c2_problem(seed=0)
     params = synth.mlp_params(prob.hidden, 0)
     x0 = synth.C2_X0
-    ctl = M.Controller(prob, cmap, params, stream=int(stream.cuda_stream), schedule=args.schedule)
     K, T = prob.K, prob.T
+    sid = int(stream.cuda_stream)
+    # one controller per Philox seed 0..9 (U = 0, iteration 0); each timed block of up
+    # to 100 steps is a warm-started receding-horizon run of one seed from x0
+    ctls = [M.Controller(synth.c2_problem(seed=s), cmap, params, stream=sid, schedule=args.schedule)
+            for s in range(10)]
+    schedule = ctls[0].schedule
+    warm = M.Controller(synth.c2_problem(seed=99), cmap, params, stream=sid, schedule=args.schedule)
 
-    for _ in range(args.warmup):
-        ctl.iterate(x0)
+    def reset_all():
+        for c in ctls:
+            c.set_controls(np.zeros((T, 2), np.float32))
+            c.iteration = 0
+
+    def receding(n_steps):
+        done, blk = 0, 0
+        while done < n_steps:
+            n = min(100, n_steps - done)
+            M.mppi_run_receding(ctls[blk % 10].ctx, x0, n)
+            done += n
+            blk += 1
+
+    if args.warmup:
+        M.mppi_run_receding(warm.ctx, x0, args.warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    # timed region: K iterations back to back, no per-launch events
+    # timed region: `steps` receding-horizon control steps (iteration, shift and plant
+    # step fused in one launch each), no per-launch events
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
-        ctl.iterate(x0)
+    receding(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -271,28 +294,54 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = K * T * args.steps / wall
 
-    # the iteration kernel's average duration: HIP events around every launch on the
-    # library's stream, over a second pass of the same length (the events themselves
-    # add stream markers, so this pass is not the throughput one)
-    M.mppi_set_timing(ctl.ctx, True)
-    for _ in range(args.steps):
-        ctl.iterate(x0)
-    (t_roll, _), (n_roll, _) = M.mppi_get_timing(ctl.ctx)
-    M.mppi_set_timing(ctl.ctx, False)
+    # per-launch device time: HIP events around every launch on the library's stream,
+    # over the same steps again from the same start (the events add stream markers, so
+    # this pass is not the throughput one)
+    reset_all()
+    for c in ctls:
+        M.mppi_set_timing(c.ctx, True)
+    receding(args.steps)
+    samples = np.concatenate([M.mppi_get_timing_samples(c.ctx) for c in ctls])
+    for c in ctls:
+        M.mppi_set_timing(c.ctx, False)
+    t_roll, n_roll = float(samples.sum()), len(samples)
 
-    # host-observed latency: iterate + copy of U back to the host, one at a time
-    lat = []
+    # host-observed latency of a control step, state in -> u_0 on the host: eager
+    # (mppi_iterate + mppi_shift) and as a replayed HIP graph of mppi_step_device
+    c = ctls[0]
+    reset_all()
+    lat_eager = []
+    x = x0.copy()
     for _ in range(args.latency_iters):
         t1 = time.perf_counter()
-        ctl.iterate(x0)
-        ctl.controls()
-        lat.append((time.perf_counter() - t1) * 1e6)
-    lat = np.array(lat)
+        c.iterate(x)
+        u0 = c.shift()
+        lat_eager.append((time.perf_counter() - t1) * 1e6)
+        x = c.plant_step(x, u0)
+    reset_all()
+    gs = torch.cuda.Stream()
+    with M.Controller(prob, cmap, params, stream=int(gs.cuda_stream), schedule=args.schedule) as cg:
+        xd = torch.tensor(x0, device="cuda")
+        ud = torch.zeros(2, device="cuda")
+        with torch.cuda.stream(gs):
+            M.mppi_step_device(cg.ctx, xd.data_ptr(), ud.data_ptr())
+        gs.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=gs):
+            M.mppi_step_device(cg.ctx, xd.data_ptr(), ud.data_ptr())
+        lat_graph = []
+        for _ in range(args.latency_iters):
+            t1 = time.perf_counter()
+            g.replay()
+            ud.cpu()
+            lat_graph.append((time.perf_counter() - t1) * 1e6)
+        del g
+    lat_eager, lat_graph = np.array(lat_eager), np.array(lat_graph)
 
     roll_ms = t_roll / max(n_roll, 1)
     flop = NET_FLOP_PER_STEP[prob.hidden] * K * T
     achieved = flop / (roll_ms * 1e-3) / 1e12
-    traffic = stored_traffic() if ctl.schedule == M.MPPI_SCHED_WAVE else None
+    traffic = stored_traffic() if schedule == M.MPPI_SCHED_WAVE else None
     out = {
         "metric": "MPPI rollout steps/sec (K×T per s) and iteration latency at K=1920,T=100",
         "value": value,
@@ -306,17 +355,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "paper-shaped MPPI iteration: K=1920, T=100, 6-32-32-4 tanh network, "
-                               "2048x2048 elliptical track map, SGF window 9",
-                   "K": K, "T": T, "hidden": prob.hidden, "schedule": ctl.schedule},
-        "latency_us": {"device_per_iteration": dev_ms * 1e3 / args.steps,
-                       "rollout_kernel": roll_ms * 1e3,
-                       "host_p50": float(np.percentile(lat, 50)), "host_p99": float(np.percentile(lat, 99))},
+        "config": {"workload": "paper-shaped receding-horizon MPPI: K=1920, T=100, 6-32-32-4 tanh network, "
+                               "2048x2048 elliptical track map, SGF window 9, 100 warm-started iterations "
+                               "per Philox seed 0-9 on a synthetic plant; one step = iteration + shift + "
+                               "plant step (one launch)",
+                   "K": K, "T": T, "hidden": prob.hidden, "schedule": schedule},
+        "latency_us": {"step_device_back_to_back": dev_ms * 1e3 / args.steps,
+                       "launch_mean": roll_ms * 1e3,
+                       "launch_p50": float(np.percentile(samples, 50)) * 1e3,
+                       "launch_p99": float(np.percentile(samples, 99)) * 1e3,
+                       "host_eager_p50": float(np.percentile(lat_eager, 50)),
+                       "host_eager_p99": float(np.percentile(lat_eager, 99)),
+                       "host_graph_p50": float(np.percentile(lat_graph, 50)),
+                       "host_graph_p99": float(np.percentile(lat_graph, 99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "rollout", "flop_per_launch": flop},
+                     "kernel": "rollout (one receding step)", "flop_per_launch": flop},
     }
-    ctl.close()
+    for cc in ctls:
+        cc.close()
+    warm.close()
     if not args.no_forms:
         out["forms"] = measure_forms(M, stream)
     if not args.no_cpu:

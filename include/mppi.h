@@ -151,10 +151,23 @@ mppi_status mppi_shift(mppi_ctx* ctx, float u0_out[2]);
 mppi_status mppi_plant_step(mppi_ctx* ctx, const float x[7], const float u[2], float x_out[7]);
 
 /* n_iter receding-horizon steps entirely on the device: iterate from x, shift,
- * then x <- F(x, g(u_0)).  u_hist ([n_iter][2]) and x_hist ([n_iter+1][7], x_hist[0]
- * = x0) may be NULL.  Synchronises at the end only. */
+ * then x <- F(x, g(u_0)) (Algorithm 1 on a synthetic plant), one kernel launch per
+ * step (the last block of each launch applies the update, the shift and the plant
+ * step).  u_hist ([n_iter][2]) and x_hist ([n_iter+1][7], x_hist[0] = x0) may be NULL.
+ * The results equal the host-driven loop mppi_iterate / mppi_shift / mppi_plant_step
+ * bit for bit.  Synchronises at the end only. */
 mppi_status mppi_run_receding(mppi_ctx* ctx, const float x0[7], int32_t n_iter,
                               float* u_hist, float* x_hist);
+
+/* One receding-horizon control step on device data: iterate from the state in x_dev
+ * (device pointer, [7] floats), shift U (u_0 to u0_out_dev, a device pointer to [2]
+ * floats, or NULL) and advance x_dev in place by the noise-free plant step.  Enqueues
+ * one launch on the context's stream and returns: no synchronisation, no allocation
+ * and no host copy, so with timing off it can be captured in a HIP graph and
+ * replayed; each replay advances the device-side iteration counter.  x_dev must stay
+ * valid until the launch has run.  The iteration's status is read by the next
+ * synchronising call (mppi_get_controls, mppi_shift). */
+mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
 
 /* Diagnostics of the most recent iteration (synchronises): rho = min_k S_k,
  * eta~ = sum_k exp(-(S_k - rho)/lambda), and the unsmoothed update
@@ -168,8 +181,9 @@ mppi_status mppi_get_noise(mppi_ctx* ctx, uint32_t iter, float* eps_out);
 
 /* Iteration counter (the Philox counter's third word) for checkpoint/resume:
  * U (mppi_get_controls / mppi_set_controls), the seed and this counter
- * reproduce the next iteration bit for bit. */
-mppi_status mppi_get_iteration(const mppi_ctx* ctx, uint32_t* iter);
+ * reproduce the next iteration bit for bit.  The counter lives on the device (every
+ * iteration launch reads it and advances it); both calls synchronise. */
+mppi_status mppi_get_iteration(mppi_ctx* ctx, uint32_t* iter);
 mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iter);
 
 /* Rollout schedule actually used (MPPI_SCHED_LANE, _WAVE or _WIDE). */
@@ -183,6 +197,9 @@ mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
  * throughput with timing off.  mppi_get_timing synchronises. */
 mppi_status mppi_set_timing(mppi_ctx* ctx, int32_t enable);
 mppi_status mppi_get_timing(mppi_ctx* ctx, double times_ms[2], int64_t counts[2]);
+/* The individual launch durations (ms) behind mppi_get_timing, oldest first: up to
+ * cap of them into ms_out; *n_out = how many were recorded.  Synchronises. */
+mppi_status mppi_get_timing_samples(mppi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out);
 
 /* Differentiation form.  The free-energy objective of Eq. FreeEnergy estimated with
  * this iteration's K samples,

@@ -358,16 +358,38 @@ __global__ __launch_bounds__(kWaveBlock) void adjoint_wave_kernel(AdjointArgs a)
   }
 }
 
-// Sum of the per-block gradient partials in block order, plus the control-cost
-// term gamma * Delta_t / Sigma_ii of dJ/du_t.
-__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float* gpart, int G, int T,
-                                                             const float* stats, float gcs0, float gcs1,
-                                                             float* out) {
+// Sum of the G per-block gradient partials [G][stride] in two passes with a fixed
+// order.  Pass 1: row chunk y (rows [y G / R, (y+1) G / R)) of 64 columns per block;
+// the four waves take every fourth row of the chunk and their sums are added in wave
+// order.  Pass 2: the R chunk sums in chunk order, plus the control-cost term
+// gamma * Delta_t / Sigma_ii of dJ/du_t.
+__global__ __launch_bounds__(256) void adjoint_reduce_partial_kernel(const float* __restrict__ gpart, int G,
+                                                                     int stride, int R,
+                                                                     float* __restrict__ partial) {
+  __shared__ float red[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int sub = threadIdx.x >> 6;
+  const int y = blockIdx.y;
+  const int g0 = (int)(((long long)y * G) / R), g1 = (int)(((long long)(y + 1) * G) / R);
+  float acc = 0.0f;
+  if (col < stride)
+    for (int g = g0 + sub; g < g1; g += 4) acc += __builtin_nontemporal_load(gpart + (size_t)g * stride + col);
+  red[sub][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (sub == 0 && col < stride) {
+    const int c = threadIdx.x;
+    partial[(size_t)y * stride + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  }
+}
+
+__global__ __launch_bounds__(256) void adjoint_reduce_final_kernel(const float* __restrict__ partial, int R,
+                                                                   int T, const float* __restrict__ stats,
+                                                                   float gcs0, float gcs1, float* __restrict__ out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int stride = kNP32 + 2 * T;
   if (i >= stride) return;
   float acc = 0.0f;
-  for (int g = 0; g < G; ++g) acc += gpart[(size_t)g * stride + i];
+  for (int y = 0; y < R; ++y) acc += partial[(size_t)y * stride + i];
   if (i >= kNP32) {
     const int o = i - kNP32;
     acc += ((o & 1) ? gcs1 : gcs0) * stats[2 + o];

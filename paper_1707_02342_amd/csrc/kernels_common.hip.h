@@ -188,6 +188,78 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
   return last;
 }
 
+// The receding-horizon part of a control step (Algorithm 1's last block and the
+// plant), run by the final merge after the update: U is shifted (u_0 out,
+// u_{t-1} <- u_t, u_{T-1} <- (0, 0)), and the plant state in x0_dev advances by one
+// noise-free step x <- F(x, g(u_0)).  The network runs one neuron per lane of wave 0,
+// each neuron's sums in input order, so the new state equals a one-thread evaluation
+// bit for bit.  Every other block of the launch has read x0_dev before it published
+// its row, so x0_dev can be overwritten here.  lds (>= 2T floats) is free on entry.
+template <int NT, int kOut>
+__device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float* lds) {
+  __shared__ float s_h[2 * 64];
+  __shared__ float s_f[4];
+  const int tid = threadIdx.x;
+  const int T2 = 2 * a.T;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kOut; ++j) {
+    const int o = tid + j * NT;
+    if (o < T2) lds[o] = u_new[j];
+  }
+  __syncthreads();
+  for (int o = tid; o < T2; o += NT) a.Uout[o] = (o + 2 < T2) ? lds[o + 2] : 0.0f;
+  if (tid < 2 && a.u0_out) a.u0_out[tid] = lds[tid];
+  const int H = a.hidden;
+  const float* W1 = a.params;
+  const float* b1 = W1 + H * 6;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + 4 * H;
+  float x[kStateDim];
+#pragma unroll
+  for (int i = 0; i < kStateDim; ++i) x[i] = a.x0_dev[i];
+  const float vc0 = fminf(fmaxf(lds[0], a.u_lo0), a.u_hi0);
+  const float vc1 = fminf(fmaxf(lds[1], a.u_lo1), a.u_hi1);
+  const float in[6] = {x[3], x[4], x[5], x[6], vc0, vc1};
+  if (tid < H) {
+    float acc = b1[tid];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[tid * 6 + j], in[j], acc);
+    s_h[tid] = tanh_f(acc);
+  }
+  __syncthreads();
+  if (tid < H) {
+    float acc = b2[tid];
+    for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[tid * H + j], s_h[j], acc);
+    s_h[64 + tid] = tanh_f(acc);
+  }
+  __syncthreads();
+  if (tid < 4) {
+    float acc = b3[tid];
+    for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[tid * H + j], s_h[64 + j], acc);
+    s_f[tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float sth, cth;
+    sincosf(x[2], &sth, &cth);
+    float y[kStateDim];
+    y[0] = x[0] + a.dt * (cth * x[4] - sth * x[5]);
+    y[1] = x[1] + a.dt * (sth * x[4] + cth * x[5]);
+    y[2] = x[2] + a.dt * x[6];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[3 + i] = x[3 + i] + a.dt * s_f[i];
+    float* xs = const_cast<float*>(a.x0_dev);
+#pragma unroll
+    for (int i = 0; i < kStateDim; ++i) {
+      xs[i] = y[i];
+      if (a.x_copy) a.x_copy[i] = y[i];
+    }
+  }
+}
+
 // Called by every rollout block with its partial row (rho_g, eta_g and N_g[2T] in
 // LDS; tile = the block's index among the launch's blocks of this problem).  Blocks
 // arrive in groups of merge_group_size(G); the last to arrive in a group merges the
@@ -256,29 +328,30 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
         }
       }
       __syncthreads();
-      if (fin && a.update_U) {
+      float u_new[kOut];
 #pragma unroll
-        for (int j = 0; j < kOut; ++j) {
-          const int o = tid + j * NT;
-          if (o < T2) {
-            float upd;
-            if (w == 1) {
-              upd = lds[o];
+      for (int j = 0; j < kOut; ++j) {
+        const int o = tid + j * NT;
+        u_new[j] = u_old[j];
+        if (o < T2 && fin && a.update_U) {
+          float upd;
+          if (w == 1) {
+            upd = lds[o];
+          } else {
+            const int t = o >> 1, c = o & 1;
+            const int lo = min(max(t - w / 2, 0), a.T - w);
+            upd = 0.0f;
+            if (w <= kTapReg) {
+#pragma unroll
+              for (int i = 0; i < kTapReg; ++i)
+                if (i < w) upd = __builtin_fmaf(taps[j][i], lds[2 * (lo + i) + c], upd);
             } else {
-              const int t = o >> 1, c = o & 1;
-              const int lo = min(max(t - w / 2, 0), a.T - w);
-              upd = 0.0f;
-              if (w <= kTapReg) {
-#pragma unroll
-                for (int i = 0; i < kTapReg; ++i)
-                  if (i < w) upd = __builtin_fmaf(taps[j][i], lds[2 * (lo + i) + c], upd);
-              } else {
-                const float* row = a.sg + (size_t)t * w;
-                for (int i = 0; i < w; ++i) upd = __builtin_fmaf(row[i], lds[2 * (lo + i) + c], upd);
-              }
+              const float* row = a.sg + (size_t)t * w;
+              for (int i = 0; i < w; ++i) upd = __builtin_fmaf(row[i], lds[2 * (lo + i) + c], upd);
             }
-            a.Uout[o] = u_old[j] + upd;
           }
+          u_new[j] = u_old[j] + upd;
+          if (!a.recede) a.Uout[o] = u_new[j];
         }
       }
       if (tid == 0) {
@@ -287,6 +360,7 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
         a.stats[1] = fin ? eta : 0.0f;
         if (a.iter_dev) *a.iter_dev = *a.iter_dev + 1u;
       }
+      if (a.recede) receding_step<NT, kOut>(a, u_new, lds);
     }
   }
   __syncthreads();

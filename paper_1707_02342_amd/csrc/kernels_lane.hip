@@ -310,6 +310,7 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
 
 template <class Net>
 __global__ __launch_bounds__(kLaneBlock) void rollout_lane_kernel(RolloutArgs a) {
+  if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   __shared__ float sU[2 * kTMax];
   __shared__ float red[kLaneWaves * 2 * kTMax];
   __shared__ float scratch[kLaneWaves];

@@ -36,6 +36,7 @@ namespace mppi {
 
 template <int HID, int NQ>
 __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a) {
+  if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   static_assert(HID == 32, "the wave schedule maps 32 hidden units onto 32 lanes");
   extern __shared__ float smem[];
   const int T = a.T;

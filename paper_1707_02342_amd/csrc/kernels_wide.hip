@@ -70,6 +70,7 @@ __device__ __forceinline__ void sum64_2(float& hi, float& lo) {
 
 template <int NQ>
 __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a) {
+  if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   constexpr int HID = 32;
   extern __shared__ float smem[];
   const int T = a.T;

@@ -30,7 +30,9 @@ __global__ void plant_kernel(const float*, const float*, const float*, float*, f
                              float, float, float);
 __global__ void noise_kernel(NoiseKey, int, int, float*);
 __global__ void adjoint_wave_kernel(AdjointArgs);
-__global__ void adjoint_reduce_kernel(const float*, int, int, const float*, float, float, float*);
+__global__ void adjoint_reduce_partial_kernel(const float*, int, int, int, float*);
+__global__ void adjoint_reduce_final_kernel(const float*, int, int, const float*, float, float, float*);
+constexpr int kGradChunks = 16;   // row chunks of the first gradient reduction pass
 size_t adjoint_smem_bytes(int T, int ckpt_every);
 constexpr int kNP32Host = 1412;
 constexpr int kLaneBlockHost = 256;
@@ -85,6 +87,8 @@ struct mppi_ctx {
   float* d_ckpt = nullptr;    // objective checkpoints [K][n_ckpt][8]
   float* d_gpart = nullptr;   // adjoint per-block partials
   float* d_gout = nullptr;    // reduced gradient [1412 + 2T]
+  float* d_gred = nullptr;    // chunk sums of the gradient partials [16][1412 + 2T]
+  unsigned* d_iter = nullptr; // the iteration counter (Philox counter word 3), advanced on the device
   int ckpt_cap = 0;           // n_ckpt the checkpoint buffer holds
   bool objective_ready = false;
   int obj_ckpt_every = 0;
@@ -98,6 +102,7 @@ struct mppi_ctx {
   std::vector<PendingTiming> pending;
   std::vector<hipEvent_t> event_pool;
   double t_ms[2] = {0, 0};
+  std::vector<float> t_samples;   // per-launch kernel durations (ms) since timing was enabled
   int64_t t_cnt[2] = {0, 0};
 };
 
@@ -222,6 +227,7 @@ mppi_status drain_timing(mppi_ctx* c) {
     HIP_TRY(c, hipEventElapsedTime(&a, p.e0, p.e1));
     c->t_ms[0] += a;
     c->t_cnt[0] += 1;
+    c->t_samples.push_back(a);
     c->event_pool.push_back(p.e0);
     c->event_pool.push_back(p.e1);
   }
@@ -288,6 +294,11 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   a.nk.key_lo = (uint32_t)c->cfg.seed;
   a.nk.key_hi = (uint32_t)(c->cfg.seed >> 32);
   a.nk.iter = c->iter;
+  a.iter_dev = c->d_iter;
+  a.hidden = c->hidden;
+  a.recede = 0;
+  a.u0_out = nullptr;
+  a.x_copy = nullptr;
   a.nk.instance = c->cfg.instance;
   a.nk.sig0 = c->sig[0];
   a.nk.sig1 = c->sig[1];
@@ -308,7 +319,11 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
 }
 
 // Enqueue one iteration: rollout kernel, then weights/update kernel.
-mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0_dev) {
+// One launch: an iteration from x0 (host value or device pointer).  With recede set,
+// also the shift of U and the plant step of the state in x0_dev (in place), u_0 to
+// u0_out and the new state to x_copy (both device, nullable).
+mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0_dev, bool recede = false,
+                              float* u0_out = nullptr, float* x_copy = nullptr) {
   if (!c->have_map || !c->have_dyn)
     return fail(c, MPPI_E_STATE, "set the cost map and the dynamics before iterating");
   const int sched = c->schedule;
@@ -317,6 +332,9 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   c->objective_ready = false;
   RolloutArgs a = rollout_args(c, x0_host, x0_dev);
   a.G = G;
+  a.recede = recede ? 1 : 0;
+  a.u0_out = u0_out;
+  a.x_copy = x_copy;
   PendingTiming pt{};
   if (c->timing) {
     pt.e0 = take_event(c);
@@ -381,7 +399,7 @@ mppi_status launch_plant(mppi_ctx* c, const float* x_in_dev, const float* u_dev,
 void free_all(mppi_ctx* c) {
   float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_part, &c->d_part2,
                     &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x,
-                    &c->d_ckpt, &c->d_gpart, &c->d_gout};
+                    &c->d_ckpt, &c->d_gpart, &c->d_gout, &c->d_gred};
   for (float** b : bufs) {
     if (*b) (void)hipFree(*b);
     *b = nullptr;
@@ -390,6 +408,8 @@ void free_all(mppi_ctx* c) {
   c->d_status = nullptr;
   if (c->d_cnt) (void)hipFree(c->d_cnt);
   c->d_cnt = nullptr;
+  if (c->d_iter) (void)hipFree(c->d_iter);
+  c->d_iter = nullptr;
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
@@ -448,6 +468,8 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(float) * (2 + 2 * T), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_status, sizeof(int)));
     HIP_TRY(c, hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+    HIP_TRY(c, hipMalloc(&c->d_iter, sizeof(unsigned)));
+    HIP_TRY(c, hipMemsetAsync(c->d_iter, 0, sizeof(unsigned), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_x, sizeof(float) * kStateDim));
     HIP_TRY(c, hipMalloc(&c->d_u0, sizeof(float) * 2));
     std::vector<float> decay(T + 1);
@@ -644,11 +666,7 @@ mppi_status mppi_run_receding(mppi_ctx* c, const float x0[7], int32_t n_iter, fl
     HIP_TRY(c, hipMemcpyAsync(c->d_hist_x, x0, 7 * sizeof(float), hipMemcpyHostToDevice, c->stream));
     int nonfinite = 0;
     for (int i = 0; i < n_iter; ++i) {
-      mppi_status st = enqueue_iteration(c, nullptr, c->d_x);
-      if (st != MPPI_OK) return st;
-      hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(512), 0, c->stream, c->d_U, c->cfg.T, c->d_hist_u + 2 * i);
-      HIP_TRY(c, hipGetLastError());
-      st = launch_plant(c, c->d_x, c->d_hist_u + 2 * i, c->d_x, c->d_hist_x + 7 * (i + 1));
+      mppi_status st = enqueue_iteration(c, nullptr, c->d_x, true, c->d_hist_u + 2 * i, c->d_hist_x + 7 * (i + 1));
       if (st != MPPI_OK) return st;
     }
     if (u_hist && n_iter > 0)
@@ -694,16 +712,50 @@ mppi_status mppi_get_noise(mppi_ctx* c, uint32_t iter, float* eps_out) {
   });
 }
 
-mppi_status mppi_get_iteration(const mppi_ctx* c, uint32_t* iter) {
+mppi_status mppi_get_iteration(mppi_ctx* c, uint32_t* iter) {
   if (!c || !iter) return MPPI_E_INVAL;
-  *iter = c->iter;
-  return MPPI_OK;
+  return guarded(c, [&]() -> mppi_status {
+    HIP_TRY(c, hipSetDevice(c->device));
+    unsigned v = 0;
+    HIP_TRY(c, hipMemcpyAsync(&v, c->d_iter, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->iter = v;
+    *iter = v;
+    return MPPI_OK;
+  });
 }
 
 mppi_status mppi_set_iteration(mppi_ctx* c, uint32_t iter) {
   if (!c) return MPPI_E_INVAL;
-  c->iter = iter;
-  return MPPI_OK;
+  return guarded(c, [&]() -> mppi_status {
+    HIP_TRY(c, hipSetDevice(c->device));
+    unsigned v = iter;
+    HIP_TRY(c, hipMemcpyAsync(c->d_iter, &v, sizeof(unsigned), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->iter = iter;
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_get_timing_samples(mppi_ctx* c, float* ms_out, int32_t cap, int32_t* n_out) {
+  if (!c || !n_out || cap < 0 || (cap > 0 && !ms_out)) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    mppi_status st = drain_timing(c);
+    if (st != MPPI_OK) return st;
+    const int32_t n = (int32_t)std::min<size_t>((size_t)cap, c->t_samples.size());
+    for (int32_t i = 0; i < n; ++i) ms_out[i] = c->t_samples[i];
+    *n_out = (int32_t)c->t_samples.size();
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_step_device(mppi_ctx* c, float* x_dev, float* u0_out_dev) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x_dev) return fail(c, MPPI_E_INVAL, "x_dev is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return enqueue_iteration(c, nullptr, x_dev, true, u0_out_dev, nullptr);
+  });
 }
 
 mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
@@ -720,6 +772,7 @@ mppi_status mppi_set_timing(mppi_ctx* c, int32_t enable) {
     c->timing = enable != 0;
     c->t_ms[0] = c->t_ms[1] = 0;
     c->t_cnt[0] = c->t_cnt[1] = 0;
+    c->t_samples.clear();
     return MPPI_OK;
   });
 }
@@ -758,10 +811,9 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
       c->ckpt_cap = n_ckpt;
     }
     const int G = blocks_for(c, MPPI_SCHED_WAVE);
-    const uint32_t saved_iter = c->iter;
-    c->iter = iter;
     RolloutArgs a = rollout_args(c, x0, nullptr);
-    c->iter = saved_iter;
+    a.nk.iter = iter;      // an explicit iteration; the counter is neither read nor advanced
+    a.iter_dev = nullptr;
     a.ckpt = c->d_ckpt;
     a.ckpt_every = ckpt_every;
     a.G = G;
@@ -792,6 +844,7 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
     if (!c->d_gpart) {
       HIP_TRY(c, hipMalloc(&c->d_gpart, sizeof(float) * (size_t)c->part_cap * stride));
       HIP_TRY(c, hipMalloc(&c->d_gout, sizeof(float) * stride));
+      HIP_TRY(c, hipMalloc(&c->d_gred, sizeof(float) * kGradChunks * stride));
     }
     AdjointArgs a{};
     RolloutArgs r = rollout_args(c, nullptr, nullptr);
@@ -818,8 +871,12 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
     a.cost = r.cost;
     hipLaunchKernelGGL(adjoint_wave_kernel, dim3(G), dim3(kWaveBlockThreads), adjoint_smem_bytes(T, C), c->stream, a);
     HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, c->stream,
-                       c->d_gpart, G, T, c->d_stats, r.gcs0, r.gcs1, c->d_gout);
+    const int R = std::min(G, kGradChunks);
+    hipLaunchKernelGGL(adjoint_reduce_partial_kernel, dim3((unsigned)((stride + 63) / 64), (unsigned)R), dim3(256), 0,
+                       c->stream, c->d_gpart, G, (int)stride, R, c->d_gred);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(adjoint_reduce_final_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, c->stream,
+                       c->d_gred, R, T, c->d_stats, r.gcs0, r.gcs1, c->d_gout);
     HIP_TRY(c, hipGetLastError());
     std::vector<float> out(stride);
     HIP_TRY(c, hipMemcpyAsync(out.data(), c->d_gout, sizeof(float) * stride, hipMemcpyDeviceToHost, c->stream));

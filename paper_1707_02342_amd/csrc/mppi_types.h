@@ -62,7 +62,8 @@ struct RolloutArgs {
   int G;                   // blocks of this launch
   int sg_window;
   int update_U;            // 0: weights and Delta only (objective evaluation)
-  unsigned* iter_dev;      // nullable: iteration counter advanced by the final merge
+  unsigned* iter_dev;      // nullable: the iteration counter (read at the start of the launch in place
+                           // of nk.iter, advanced by the final merge)
   float* ckpt;             // nullable: [K][n_ckpt][8] full states every ckpt_every steps
   int ckpt_every;
   float x0[kStateDim];
@@ -73,6 +74,13 @@ struct RolloutArgs {
   float u_lo0, u_lo1, u_hi0, u_hi1;
   NoiseKey nk;
   CostArgs cost;
+  int hidden;              // network width (32 or 64)
+  // Receding-horizon step (recede = 1): after the update the final merge also shifts U
+  // (u_0 out, u_{t-1} <- u_t, u_{T-1} <- 0) and advances the plant x <- F(x, g(u_0)) in
+  // place in x0_dev.
+  int recede;
+  float* u0_out;           // nullable: [2] u_0 of this step
+  float* x_copy;           // nullable: [7] a copy of the new plant state
 };
 
 constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)

@@ -27,9 +27,9 @@ STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_N
 EXPORTED = [
     "mppi_create", "mppi_destroy", "mppi_last_error", "mppi_set_costmap", "mppi_set_dynamics",
     "mppi_set_controls", "mppi_iterate", "mppi_iterate_device", "mppi_get_controls", "mppi_shift",
-    "mppi_plant_step", "mppi_run_receding", "mppi_get_stats", "mppi_get_noise",
+    "mppi_plant_step", "mppi_run_receding", "mppi_step_device", "mppi_get_stats", "mppi_get_noise",
     "mppi_get_iteration", "mppi_set_iteration", "mppi_get_schedule", "mppi_set_timing",
-    "mppi_get_timing", "mppi_objective", "mppi_objective_backward",
+    "mppi_get_timing", "mppi_get_timing_samples", "mppi_objective", "mppi_objective_backward",
     "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error", "mppi_batch_set_costmap",
     "mppi_batch_set_dynamics", "mppi_batch_set_controls", "mppi_batch_iterate",
     "mppi_batch_get_controls", "mppi_batch_get_costs", "mppi_batch_get_schedule",
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
         L.mppi_shift.argtypes = [vp, fp]
         L.mppi_plant_step.argtypes = [vp, fp, fp, fp]
         L.mppi_run_receding.argtypes = [vp, fp, C.c_int32, fp, fp]
+        L.mppi_step_device.argtypes = [vp, vp, vp]
         L.mppi_get_stats.argtypes = [vp, fp, fp, fp]
         L.mppi_get_noise.argtypes = [vp, C.c_uint32, fp]
         L.mppi_get_iteration.argtypes = [vp, C.POINTER(C.c_uint32)]
@@ -90,6 +91,7 @@ def lib() -> C.CDLL:
         L.mppi_get_schedule.argtypes = [vp, C.POINTER(C.c_int32)]
         L.mppi_set_timing.argtypes = [vp, C.c_int32]
         L.mppi_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.mppi_get_timing_samples.argtypes = [vp, fp, C.c_int32, C.POINTER(C.c_int32)]
         L.mppi_objective.argtypes = [vp, fp, C.c_uint32, C.c_int32, C.POINTER(C.c_double), fp]
         L.mppi_objective_backward.argtypes = [vp, fp, fp]
         i32p = C.POINTER(C.c_int32)
@@ -206,6 +208,11 @@ def mppi_run_receding(ctx, x0, n_iter: int):
     return uh, xh, st
 
 
+def mppi_step_device(ctx, x_dev_ptr: int, u0_dev_ptr: int = 0) -> None:
+    """One receding-horizon step on device data (pointers as integers, e.g. data_ptr())."""
+    _check(ctx, lib().mppi_step_device(ctx, C.c_void_p(x_dev_ptr), C.c_void_p(u0_dev_ptr or None)))
+
+
 def mppi_get_stats(ctx, T: int):
     rho, eta = C.c_float(), C.c_float()
     d = np.zeros((T, 2), dtype=np.float32)
@@ -244,6 +251,14 @@ def mppi_get_timing(ctx):
     n = (C.c_int64 * 2)()
     _check(ctx, lib().mppi_get_timing(ctx, t, n))
     return (t[0], t[1]), (n[0], n[1])
+
+
+def mppi_get_timing_samples(ctx, cap: int = 1 << 16) -> np.ndarray:
+    """Per-launch kernel durations (ms) recorded since timing was enabled."""
+    buf = np.zeros(cap, dtype=np.float32)
+    n = C.c_int32()
+    _check(ctx, lib().mppi_get_timing_samples(ctx, _fp(buf), cap, C.byref(n)))
+    return buf[:min(n.value, cap)].copy()
 
 
 def mppi_objective(ctx, x0, it: int, ckpt_every: int = 10, K: Optional[int] = None):

@@ -253,6 +253,88 @@ def test_receding_horizon_loop(M, orc):
     assert np.array_equal(xh, np.array(xs))
 
 
+@pytest.mark.parametrize("schedule", _schedules())
+def test_step_device_matches_receding_loop(M, schedule):
+    """mppi_step_device (iterate, shift and plant step in one launch, on device data)
+    reproduces mppi_run_receding bit for bit, and advances the device-side counter."""
+    import torch
+    prob = synth.with_(synth.c2_problem(seed=3), K=700, T=40)
+    cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
+    n = 12
+    with _ctrl(M, prob, cmap, params, schedule) as c:
+        uh, xh, _ = M.mppi_run_receding(c.ctx, synth.C2_X0, n)
+        U_ref = c.controls()
+    stream = torch.cuda.current_stream()
+    with M.Controller(prob, cmap, params, stream=int(stream.cuda_stream), schedule=schedule) as c:
+        x = torch.tensor(synth.C2_X0, device="cuda")
+        u0 = torch.zeros(2, device="cuda")
+        us = []
+        for i in range(n):
+            M.mppi_step_device(c.ctx, x.data_ptr(), u0.data_ptr())
+            us.append(u0.cpu().numpy().copy())
+        torch.cuda.synchronize()
+        assert np.array_equal(np.array(us), uh)
+        assert np.array_equal(x.cpu().numpy(), xh[-1])
+        assert np.array_equal(c.controls(), U_ref)
+        assert c.iteration == n
+
+
+def test_step_device_graph_replay(M):
+    """One receding-horizon step captured in a HIP graph and replayed: every replay,
+    with eager work and synchronisations in between, equals the eager step sequence."""
+    import torch
+    prob = synth.with_(synth.c2_problem(seed=4), K=1920, T=100)
+    cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
+    n = 6
+    s = torch.cuda.Stream()
+    with M.Controller(prob, cmap, params, stream=int(s.cuda_stream)) as ref:
+        xr = torch.tensor(synth.C2_X0, device="cuda")
+        ur = torch.zeros(2, device="cuda")
+        ref_x, ref_u, ref_U = [], [], []
+        for i in range(n + 1):
+            with torch.cuda.stream(s):
+                M.mppi_step_device(ref.ctx, xr.data_ptr(), ur.data_ptr())
+            s.synchronize()
+            ref_x.append(xr.cpu().numpy().copy())
+            ref_u.append(ur.cpu().numpy().copy())
+            ref_U.append(ref.controls())
+    with M.Controller(prob, cmap, params, stream=int(s.cuda_stream)) as c:
+        x = torch.tensor(synth.C2_X0, device="cuda")
+        u0 = torch.zeros(2, device="cuda")
+        # the first step eagerly (the graph is captured from the second on)
+        with torch.cuda.stream(s):
+            M.mppi_step_device(c.ctx, x.data_ptr(), u0.data_ptr())
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            M.mppi_step_device(c.ctx, x.data_ptr(), u0.data_ptr())
+        # capture does not run the step: the state is still the eager step's
+        s.synchronize()
+        assert np.array_equal(x.cpu().numpy(), ref_x[0])
+        for i in range(1, n + 1):
+            g.replay()
+            torch.cuda.synchronize()
+            junk = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+            assert junk == 1000.0
+            assert np.array_equal(x.cpu().numpy(), ref_x[i]), f"replay {i}: state"
+            assert np.array_equal(u0.cpu().numpy(), ref_u[i]), f"replay {i}: u0"
+            assert np.array_equal(c.controls(), ref_U[i]), f"replay {i}: U"
+        assert c.iteration == n + 1
+
+
+def test_timing_samples(M):
+    prob = synth.c1_problem(seed=0)
+    with _ctrl(M, prob, synth.ring_map(), synth.mlp_params(32, 0)) as c:
+        M.mppi_set_timing(c.ctx, True)
+        for _ in range(7):
+            c.iterate(synth.C1_X0)
+        samples = M.mppi_get_timing_samples(c.ctx)
+        (t, _), (n, _) = M.mppi_get_timing(c.ctx)
+    assert len(samples) == 7 == n
+    assert np.all(samples > 0)
+    assert abs(samples.sum() - t) <= 1e-3 * t
+
+
 # ---------------------------------------------------------------------------
 # Determinism, resume, error paths
 # ---------------------------------------------------------------------------
