@@ -55,11 +55,14 @@ typedef enum {
 enum { MPPI_PREC_FP32 = 0, MPPI_PREC_BF16 = 1, MPPI_PREC_FP16 = 2 };
 
 /* Kernel schedule for the rollout (0 = pick automatically).  LANE: one sample per
- * lane (any K; FP32, BF16 or FP16 network, h = 32 or 64).  WAVE: 32 lanes per sample,
- * two samples per wavefront.  WIDE: 64 lanes (a whole wavefront) per sample.  WAVE and
- * WIDE run the FP32 network with h = 32 and suit a few thousand samples, where one
- * lane per sample leaves most of the device idle. */
-enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2, MPPI_SCHED_WIDE = 3 };
+ * lane (any K; FP32, BF16 or FP16 network, h = 32 or 64; BF16/FP16 on the matrix
+ * cores, 64 samples per instruction group).  WAVE: 32 lanes per sample, two samples per wavefront.  WIDE: 64 lanes (a
+ * whole wavefront) per sample.  WAVE and WIDE run the FP32 network with h = 32 and
+ * suit a few thousand samples, where one lane per sample leaves most of the device
+ * idle.  QUAD: 4 lanes per sample, 16 samples per wavefront, the network on the
+ * matrix cores in any precision (h = 32 or 64), for tens of thousands of samples.
+ * AUTO: WAVE for the FP32 h = 32 network up to K = 12288, QUAD otherwise. */
+enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2, MPPI_SCHED_WIDE = 3, MPPI_SCHED_QUAD = 4 };
 
 #define MPPI_T_MAX 256
 #define MPPI_STATE_DIM 7
@@ -186,7 +189,7 @@ mppi_status mppi_get_noise(mppi_ctx* ctx, uint32_t iter, float* eps_out);
 mppi_status mppi_get_iteration(mppi_ctx* ctx, uint32_t* iter);
 mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iter);
 
-/* Rollout schedule actually used (MPPI_SCHED_LANE, _WAVE or _WIDE). */
+/* Rollout schedule actually used (MPPI_SCHED_LANE, _WAVE, _WIDE or _QUAD). */
 mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
 
 /* Device time of the iteration kernel, measured with HIP events recorded on the
@@ -223,14 +226,16 @@ mppi_status mppi_objective_backward(mppi_ctx* ctx, float* dJdU, float* dJdtheta)
  * one cost and one FP32 6-32-32-4 network, each with its own K_i, T_i, x0, U and
  * iteration counter, advanced together by one persistent kernel launch per
  * mppi_batch_iterate (replayed from a HIP graph).  Instance i draws its noise with
- * Philox counter word 4 = cfg->instance + i, so it reproduces, bit for bit, a
- * single-problem context with K_i, T_i and that instance word.  cfg->K and cfg->T
- * are ignored.  The first iterate times several launch schedules (grid size and
- * work order) on the real problem and keeps the fastest; U and the counters are
- * restored afterwards and every schedule gives the same results.  With a NULL
- * stream the batch creates its own (graph capture needs a non-null stream).
- * INVAL: n outside [1, 65536], an instance's K/T invalid (as in mppi_config), or
- * a precision other than FP32. */
+ * Philox counter word 4 = cfg->instance + i.  cfg->schedule picks the work tiles:
+ * MPPI_SCHED_QUAD or AUTO (tiles of 64 samples, matrix-core network) or
+ * MPPI_SCHED_LANE (tiles of 256); instance i then reproduces, bit for bit, a
+ * single-problem context with K_i, T_i, that instance word and that schedule.
+ * cfg->K and cfg->T are ignored.  The first iterate times several launch shapes
+ * (grid size and work order) on the real problem and keeps the fastest; U and the
+ * counters are restored afterwards and every shape gives the same results.  With a
+ * NULL stream the batch creates its own (graph capture needs a non-null stream).
+ * INVAL: n outside [1, 65536], an instance's K/T invalid (as in mppi_config), a
+ * precision other than FP32, or a schedule other than AUTO, LANE or QUAD. */
 typedef struct mppi_batch mppi_batch;
 mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int32_t n, const int32_t* K,
                               const int32_t* T, int device, void* hip_stream, mppi_batch** out);

@@ -1,0 +1,567 @@
+// Rollout schedule "quad": four lanes per sample, sixteen samples per wavefront, the
+// network on the matrix cores -- FP32 (v_mfma_f32_16x16x4_f32), or BF16 / FP16
+// operands with FP32 accumulation (v_mfma_f32_16x16x32_{bf16,f16}) -- for the
+// throughput regime (tens of thousands of samples, or many problems at once).
+//
+// Lane l = 16 g + j: sample j of the wave, lane group g (0..3).  The 16 samples are the
+// 16 columns of every product out^T = W in^T, so a sample's values never mix with
+// another's.  With the instruction's layouts (A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k, D[i][j] in lane j + 16 (i / 4), item i % 4):
+//   layer 1: two k-steps; lane group g supplies input g (state component g) in the
+//            first and (v_0, v_1, 1, 0)[g] in the second (the 1 carries b1);
+//   layer 2: the accumulator of layer 1 holds neurons 16 m + 4 g + r in lane group g,
+//            item r -- exactly the k-row lane group g supplies at k-step (m, r), so
+//            the activations never leave their lane; b2 enters as the accumulator;
+//   layer 3: output o is placed in row 4 o, so it lands in lane group o, item 0: each
+//            lane receives derivative g of its own sample, and lane group g carries
+//            state component g (compensated two-sum update).
+// Kinematics and cost run in chunks of 16 steps, lane-parallel: lane group g takes
+// four consecutive steps of the chunk for its sample, with exclusive scans over the
+// four lane groups (v_permlane16_swap / v_permlane32_swap).  The noise of a chunk is
+// drawn before the chunk (four draws per lane) and regenerated for the weighted
+// perturbation sum at the end.
+#include "kernels_common.hip.h"
+
+namespace mppi {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float qf32x4;
+
+constexpr int kQuadBlock = 256;
+constexpr int kQuadWaves = 4;
+constexpr int kQuadSamples = 64;   // per block
+constexpr int kQuadChunk = 16;     // steps per chunk
+
+__device__ __forceinline__ float q_as_f(uint32_t v) { return __builtin_bit_cast(float, v); }
+__device__ __forceinline__ uint32_t q_as_u(float v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Every lane of a column (the four lanes of one sample) receives the values of all
+// four lane groups: v[0..3] = value of lane group 0..3.
+__device__ __forceinline__ void all4(float x, float v[4]) {
+  auto p = __builtin_amdgcn_permlane16_swap(q_as_u(x), q_as_u(x), false, false);
+  // p[0]: rows 0,1 -> row 0's value, rows 2,3 -> row 2's; p[1]: rows 1 and 3
+  auto q0 = __builtin_amdgcn_permlane32_swap(p[0], p[0], false, false);   // [v0 | v0], [v2 | v2]
+  auto q1 = __builtin_amdgcn_permlane32_swap(p[1], p[1], false, false);   // [v1 | v1], [v3 | v3]
+  v[0] = q_as_f(q0[0]);
+  v[2] = q_as_f(q0[1]);
+  v[1] = q_as_f(q1[0]);
+  v[3] = q_as_f(q1[1]);
+}
+
+// Compensated (hi, lo) of the four lane groups: exclusive prefix for lane group g and
+// the total, the same bits in the four lanes of a column.
+__device__ __forceinline__ void scan4_excl2(float hi, float lo, int g, float& ph, float& pl, float& th,
+                                            float& tl) {
+  float H[4], L[4];
+  all4(hi, H);
+  all4(lo, L);
+  float sh = 0.0f, sl = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i == g) {
+      ph = sh;
+      pl = sl;
+    }
+    float s_, e_;
+    two_sum(sh, H[i], s_, e_);
+    sh = s_;
+    sl = sl + (L[i] + e_);
+  }
+  th = sh;
+  tl = sl;
+}
+
+constexpr int kQPrecFP32 = 0;
+constexpr int kQPrecBF16 = 1;
+constexpr int kQPrecFP16 = 2;
+
+template <int PREC, int HID> struct QuadNet;
+
+// FP32: v_mfma_f32_16x16x4_f32, one k-row per lane group.
+template <int HID>
+struct QuadNet<kQPrecFP32, HID> {
+  static constexpr int NM = HID / 16;
+  float A1[NM][2];
+  float A2[NM][NM][4];
+  float A3[NM][4];
+  qf32x4 C2[NM];
+  qf32x4 C3;
+
+  __device__ explicit QuadNet(const float* __restrict__ P, int g, int i) {
+    const float* W1 = P;
+    const float* b1 = W1 + HID * 6;
+    const float* W2 = b1 + HID;
+    const float* b2 = W2 + HID * HID;
+    const float* W3 = b2 + HID;
+    const float* b3 = W3 + 4 * HID;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int n = 16 * m + i;
+      A1[m][0] = W1[n * 6 + g];
+      A1[m][1] = g == 0 ? W1[n * 6 + 4] : g == 1 ? W1[n * 6 + 5] : g == 2 ? b1[n] : 0.0f;
+#pragma unroll
+      for (int mi = 0; mi < NM; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A2[m][mi][r] = W2[n * HID + 16 * mi + 4 * g + r];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C2[m][r] = b2[16 * m + 4 * g + r];
+        A3[m][r] = (i & 3) == 0 ? W3[(i >> 2) * HID + 16 * m + 4 * g + r] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C3[r] = r == 0 ? b3[g] : 0.0f;
+  }
+
+  // f = derivative (lane group g) of this lane's sample; b0 = state component g,
+  // b1 = (v_0, v_1, 1, 0)[g].
+  __device__ __forceinline__ float eval(float b0, float b1) const {
+    float h1[NM][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      qf32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[m][0], b0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[m][1], b1, d, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h1[m][r] = tanh_f(d[r]);
+    }
+    float h2[NM][4];
+    qf32x4 d2[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) d2[m] = C2[m];
+#pragma unroll
+    for (int mi = 0; mi < NM; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+          d2[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(A2[m][mi][r], h1[mi][r], d2[m], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h2[m][r] = tanh_f(d2[m][r]);
+    qf32x4 d3 = C3;
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) d3 = __builtin_amdgcn_mfma_f32_16x16x4f32(A3[m][r], h2[m][r], d3, 0, 0, 0);
+    return d3[0];
+  }
+};
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 qbf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 qf16x8;
+
+template <int PREC> struct QuadOps;
+template <> struct QuadOps<kQPrecBF16> {
+  typedef qbf16x8 vec;
+  static __device__ __forceinline__ qf32x4 mma(vec a, vec b, qf32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec pack(const float v[8]) {
+    vec r;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r[c] = (__bf16)v[c];
+    return r;
+  }
+};
+template <> struct QuadOps<kQPrecFP16> {
+  typedef qf16x8 vec;
+  static __device__ __forceinline__ qf32x4 mma(vec a, vec b, qf32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec pack(const float v[8]) {
+    vec r;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r[c] = (_Float16)v[c];
+    return r;
+  }
+};
+
+// BF16 / FP16 operands, FP32 accumulation: v_mfma_f32_16x16x32_{bf16,f16}, eight k
+// slots per lane group (A[i][k] in lane i + 16 (k / 8), item k % 8; B likewise).
+// Layer 1 uses slots 0 (state component g) and 1 ((v_0, v_1, 1, 0)[g]) of each
+// group; k-block kb of layers 2 and 3 takes tiles 2 kb (items 0..3) and 2 kb + 1
+// (items 4..7), i.e. neurons 16 (2 kb + c / 4) + 4 g + c % 4 -- again what lane group
+// g holds of the previous layer's accumulators.
+template <int PREC, int HID>
+struct QuadNet {
+  typedef QuadOps<PREC> Ops;
+  typedef typename Ops::vec vec;
+  static constexpr int NM = HID / 16;
+  static constexpr int NKB = NM / 2;
+  vec A1[NM];
+  vec A2[NM][NKB];
+  vec A3[NKB];
+  qf32x4 C2[NM];
+  qf32x4 C3;
+
+  static __device__ __forceinline__ int neuron(int kb, int g, int c) {
+    return 16 * (2 * kb + (c >> 2)) + 4 * g + (c & 3);
+  }
+
+  __device__ explicit QuadNet(const float* __restrict__ P, int g, int i) {
+    const float* W1 = P;
+    const float* b1 = W1 + HID * 6;
+    const float* W2 = b1 + HID;
+    const float* b2 = W2 + HID * HID;
+    const float* W3 = b2 + HID;
+    const float* b3 = W3 + 4 * HID;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int n = 16 * m + i;
+      float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      v[0] = W1[n * 6 + g];
+      v[1] = g == 0 ? W1[n * 6 + 4] : g == 1 ? W1[n * 6 + 5] : g == 2 ? b1[n] : 0.0f;
+      A1[m] = Ops::pack(v);
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = W2[n * HID + neuron(kb, g, c)];
+        A2[m][kb] = Ops::pack(v);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) C2[m][r] = b2[16 * m + 4 * g + r];
+    }
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      float v[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] = (i & 3) == 0 ? W3[(i >> 2) * HID + neuron(kb, g, c)] : 0.0f;
+      A3[kb] = Ops::pack(v);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C3[r] = r == 0 ? b3[g] : 0.0f;
+  }
+
+  __device__ __forceinline__ float eval(float b0, float b1) const {
+    float v[8] = {b0, b1, 0, 0, 0, 0, 0, 0};
+    const vec B1 = Ops::pack(v);
+    float h1[NM][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const qf32x4 d = Ops::mma(A1[m], B1, qf32x4{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h1[m][r] = tanh_f(d[r]);
+    }
+    vec B2[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] = h1[2 * kb + (c >> 2)][c & 3];
+      B2[kb] = Ops::pack(v);
+    }
+    float h2[NM][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      qf32x4 d = C2[m];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) d = Ops::mma(A2[m][kb], B2[kb], d);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h2[m][r] = tanh_f(d[r]);
+    }
+    qf32x4 d3 = C3;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] = h2[2 * kb + (c >> 2)][c & 3];
+      d3 = Ops::mma(A3[kb], Ops::pack(v), d3);
+    }
+    return d3[0];
+  }
+};
+
+// One tile of 64 samples (tile * 64 ... + 63) of one problem; lds_f: the block's LDS.
+template <int PREC, int HID>
+__device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, float* sE, float* sX,
+                                  float* red) {
+  const int T = a.T;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int j = lane & 15;
+  const int k = tile * kQuadSamples + wv * 16 + j;
+  const bool valid = k < a.K;
+  float* wE = sE + wv * (kQuadChunk * 16 * 2);          // [chunk step][sample][2]
+  float* wX = sX + wv * ((kQuadChunk + 1) * 16 * 4);    // [chunk step 0..16][sample][4]
+
+  for (int i = threadIdx.x; i < 2 * T; i += kQuadBlock) sU[i] = a.U[i];
+  __syncthreads();
+
+  const QuadNet<PREC, HID> net(a.params, g, j);
+  float x0v[kStateDim];
+#pragma unroll
+  for (int i = 0; i < kStateDim; ++i) x0v[i] = a.x0_dev ? a.x0_dev[i] : a.x0[i];
+  const float lo_g = g == 0 ? a.u_lo0 : a.u_lo1;
+  const float hi_g = g == 0 ? a.u_hi0 : a.u_hi1;
+  const float gcs_g = g == 0 ? a.gcs0 : a.gcs1;
+
+  Acc xd{x0v[3 + g], 0.0f};          // state component g (roll, v_x, v_y, theta_dot)
+  // pose carries (compensated), the same in the four lanes of a sample
+  float th_h = x0v[2], th_l = 0.0f, px_h = x0v[0], px_l = 0.0f, py_h = x0v[1], py_l = 0.0f;
+  Acc Sacc{0.0f, 0.0f};
+  bool ok = true;
+  wX[j * 4 + g] = xd.hi;             // chunk row 0 = the state entering the chunk
+
+  for (int cs = 0; cs < T; cs += kQuadChunk) {
+    const int n = min(kQuadChunk, T - cs);
+    // noise of the chunk: pair p = lane + 64 q -> (step cs + p / 16, sample p % 16)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = lane + 64 * q;
+      const int ts = min(cs + (p >> 4), T - 1);
+      float e0, e1;
+      draw_eps((uint32_t)ts, (uint32_t)(tile * kQuadSamples + wv * 16 + (p & 15)), a.nk, e0, e1);
+      wE[p * 2] = e0;
+      wE[p * 2 + 1] = e1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the serial chain over the chunk
+    for (int s = 0; s < n; ++s) {
+      const int t = cs + s;
+      float b1v;
+      if (g < 2) {
+        const float e = wE[(s * 16 + j) * 2 + g];
+        const float u = sU[2 * t + g];
+        b1v = fminf(fmaxf(u + e, lo_g), hi_g);
+        Sacc.add(gcs_g * (u * e));   // the control-cost term, one component per lane
+      } else {
+        b1v = g == 2 ? 1.0f : 0.0f;
+      }
+      const float f = net.eval(xd.hi, b1v);
+      xd.add(a.dt * f);
+      wX[((s + 1) * 16 + j) * 4 + g] = xd.value();
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // kinematics and cost of the chunk: lane group g takes steps cs + 4 g .. cs + 4 g + 3
+    float tdh = 0.0f, tdl = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int s = 4 * g + q;
+      if (s < n) {
+        float s_, e_;
+        two_sum(tdh, a.dt * wX[(s * 16 + j) * 4 + 3], s_, e_);
+        tdh = s_;
+        tdl += e_;
+      }
+    }
+    float pth, ptl, Tth, Ttl;
+    scan4_excl2(tdh, tdl, g, pth, ptl, Tth, Ttl);
+    float th = th_h, thl = th_l;
+    {
+      float s_, e_;
+      two_sum(th, pth, s_, e_);
+      th = s_;
+      thl = thl + (ptl + e_);
+    }
+    float dpx[4], dpy[4];
+    float dxh = 0.0f, dxl = 0.0f, dyh = 0.0f, dyl = 0.0f;
+    {
+      float th2 = th, thl2 = thl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int s = 4 * g + q;
+        dpx[q] = 0.0f;
+        dpy[q] = 0.0f;
+        if (s < n) {
+          const float4 xs = *reinterpret_cast<const float4*>(wX + (s * 16 + j) * 4);
+          float sn, c_;
+          sincosf(th2 + thl2, &sn, &c_);
+          dpx[q] = a.dt * (c_ * xs.y - sn * xs.z);
+          dpy[q] = a.dt * (sn * xs.y + c_ * xs.z);
+          float s_, e_;
+          two_sum(dxh, dpx[q], s_, e_);
+          dxh = s_;
+          dxl += e_;
+          two_sum(dyh, dpy[q], s_, e_);
+          dyh = s_;
+          dyl += e_;
+          two_sum(th2, a.dt * xs.w, s_, e_);
+          th2 = s_;
+          thl2 += e_;
+        }
+      }
+    }
+    float pxh, pxl, Txh, Txl, pyh, pyl, Tyh, Tyl;
+    scan4_excl2(dxh, dxl, g, pxh, pxl, Txh, Txl);
+    scan4_excl2(dyh, dyl, g, pyh, pyl, Tyh, Tyl);
+    float ph_x = px_h, pl_x = px_l, ph_y = py_h, pl_y = py_l;
+    {
+      float s_, e_;
+      two_sum(ph_x, pxh, s_, e_);
+      ph_x = s_;
+      pl_x = pl_x + (pxl + e_);
+      two_sum(ph_y, pyh, s_, e_);
+      ph_y = s_;
+      pl_y = pl_y + (pyl + e_);
+    }
+    // positions after each of the lane's steps, then every map and decay load at once
+    float qxh[4], qxl[4], qyh[4], qyl[4], qth[4];
+    {
+      float th2 = th, thl2 = thl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int s = 4 * g + q;
+        if (s < n) {
+          float s_, e_;
+          two_sum(ph_x, dpx[q], s_, e_);
+          ph_x = s_;
+          pl_x += e_;
+          two_sum(ph_y, dpy[q], s_, e_);
+          ph_y = s_;
+          pl_y += e_;
+          two_sum(th2, a.dt * wX[(s * 16 + j) * 4 + 3], s_, e_);
+          th2 = s_;
+          thl2 += e_;
+        }
+        qxh[q] = ph_x;
+        qxl[q] = pl_x;
+        qyh[q] = ph_y;
+        qyl[q] = pl_y;
+        qth[q] = th2 + thl2;
+      }
+    }
+    float mv[4][4], fxv[4], fyv[4], dec[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int idx[4];
+      map_taps(a.cost, qxh[q], qxl[q], qyh[q], qyl[q], idx, fxv[q], fyv[q]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mv[q][i] = a.map[idx[i]];
+      dec[q] = a.decay[min(cs + 4 * g + q, T - 1) + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int s = 4 * g + q;
+      if (s < n) {
+        const float4 xn = *reinterpret_cast<const float4*>(wX + ((s + 1) * 16 + j) * 4);
+        Sacc.add(state_cost_h(a.cost, bilerp(mv[q], fxv[q], fyv[q]), dec[q], xn.y, xn.z));
+        ok = ok && finite_f(qxh[q] + qxl[q]) && finite_f(qyh[q] + qyl[q]) && finite_f(qth[q]) &&
+             finite_f(xn.x) && finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
+      }
+    }
+    // carries into the next chunk
+    {
+      float s_, e_;
+      two_sum(th_h, Tth, s_, e_);
+      th_h = s_;
+      th_l = th_l + (Ttl + e_);
+      two_sum(px_h, Txh, s_, e_);
+      px_h = s_;
+      px_l = px_l + (Txl + e_);
+      two_sum(py_h, Tyh, s_, e_);
+      py_h = s_;
+      py_l = py_l + (Tyl + e_);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the chunk's last state enters the next chunk as its row 0
+    wX[j * 4 + g] = wX[(n * 16 + j) * 4 + g];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+
+  // S_k: the four lanes' sums
+  float H[4], L[4];
+  all4(Sacc.hi, H);
+  all4(Sacc.lo, L);
+  float Sh = 0.0f, Sl = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float s_, e_;
+    two_sum(Sh, H[i], s_, e_);
+    Sh = s_;
+    Sl = Sl + (L[i] + e_);
+  }
+  float S = Sh + Sl;
+  float okv[4];
+  all4(ok ? 1.0f : 0.0f, okv);
+  const bool okc = okv[0] != 0.0f && okv[1] != 0.0f && okv[2] != 0.0f && okv[3] != 0.0f;
+  if (!valid || !okc || !finite_f(S)) S = kInf;
+  if (valid && g == 0) store_through(a.S + k, S);   // read by the host only; kept out of L2
+
+  // ---- the block's softmin partial ----------------------------------------------------
+  float* scratch = red + kQuadWaves * 2 * kTMax;   // [8]
+  float wmin = S;
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) wmin = fminf(wmin, __shfl_xor(wmin, m, 16));
+  if (lane == 0) scratch[wv] = wmin;
+  __syncthreads();
+  const float rho = fminf(fminf(scratch[0], scratch[1]), fminf(scratch[2], scratch[3]));
+  const float e = rel_weight(S, rho, a.inv_lambda);
+  float esum = e;
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) esum += __shfl_xor(esum, m, 16);
+  if (lane == 0) scratch[4 + wv] = esum;
+  // N[t] = sum_k e_k eps_{k,t}: lane group g regenerates steps t = g, g + 4, ... of its
+  // sample and the 16 samples of a row are summed with shuffles
+  for (int t0 = 0; t0 < T; t0 += 4) {
+    const int t = t0 + g;
+    float e0 = 0.0f, e1 = 0.0f;
+    if (t < T && valid) draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+    float n0 = e * e0, n1 = e * e1;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) {
+      n0 += __shfl_xor(n0, m, 16);
+      n1 += __shfl_xor(n1, m, 16);
+    }
+    if (j == 0 && t < T) {
+      red[wv * 2 * kTMax + 2 * t] = n0;
+      red[wv * 2 * kTMax + 2 * t + 1] = n1;
+    }
+  }
+  __syncthreads();
+  float* N_lds = sE;   // the noise chunks are no longer read
+  for (int o = threadIdx.x; o < 2 * T; o += kQuadBlock)
+    N_lds[o] = ((red[o] + red[2 * kTMax + o]) + red[2 * 2 * kTMax + o]) + red[3 * 2 * kTMax + o];
+  const float eta = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
+  finish_iteration<kQuadBlock>(a, tile, rho, eta, N_lds, red);
+}
+
+template <int PREC, int HID>
+__global__ __launch_bounds__(kQuadBlock) void rollout_quad_kernel(RolloutArgs a) {
+  if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
+  __shared__ float sU[2 * kTMax];
+  __shared__ float sE[kQuadWaves * kQuadChunk * 16 * 2 > 2 * kTMax ? kQuadWaves * kQuadChunk * 16 * 2 : 2 * kTMax];
+  __shared__ float sX[kQuadWaves * (kQuadChunk + 1) * 16 * 4];
+  __shared__ float red[kQuadWaves * 2 * kTMax + 8];
+  quad_rollout_tile<PREC, HID>(a, blockIdx.x, sU, sE, sX, red);
+}
+
+// Batched form on quad tiles: block b processes items b, b + gridDim.x, ... (item =
+// (instance, tile of 64 samples)); the shared map, network and decay table come from
+// kernel arguments.  A tile's arithmetic and an instance's merge order do not depend
+// on the grid or the item order.
+__global__ __launch_bounds__(kQuadBlock) void rollout_batch_quad_kernel(const RolloutArgs* __restrict__ inst,
+                                                                      const int2* __restrict__ items, int n_items,
+                                                                      const float* __restrict__ map,
+                                                                      const float* __restrict__ params,
+                                                                      const float* __restrict__ decay) {
+  __shared__ float sU[2 * kTMax];
+  __shared__ float sE[kQuadWaves * kQuadChunk * 16 * 2 > 2 * kTMax ? kQuadWaves * kQuadChunk * 16 * 2 : 2 * kTMax];
+  __shared__ float sX[kQuadWaves * (kQuadChunk + 1) * 16 * 4];
+  __shared__ float red[kQuadWaves * 2 * kTMax + 8];
+  for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
+    const int2 it = items[b];
+    RolloutArgs a = inst[it.x];
+    a.map = map;
+    a.params = params;
+    a.decay = decay;
+    a.nk.iter = *a.iter_dev;
+    quad_rollout_tile<kQPrecFP32, 32>(a, it.y, sU, sE, sX, red);
+  }
+}
+
+template __global__ void rollout_quad_kernel<kQPrecFP32, 32>(RolloutArgs);
+template __global__ void rollout_quad_kernel<kQPrecFP32, 64>(RolloutArgs);
+template __global__ void rollout_quad_kernel<kQPrecBF16, 32>(RolloutArgs);
+template __global__ void rollout_quad_kernel<kQPrecBF16, 64>(RolloutArgs);
+template __global__ void rollout_quad_kernel<kQPrecFP16, 32>(RolloutArgs);
+template __global__ void rollout_quad_kernel<kQPrecFP16, 64>(RolloutArgs);
+
+}  // namespace mppi

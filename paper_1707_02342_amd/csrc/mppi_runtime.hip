@@ -24,6 +24,7 @@ template <int HID, int NQ> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T);
 size_t wide_smem_bytes(int T);
 template <int NQ> __global__ void rollout_wide_kernel(RolloutArgs);
+template <int PREC, int HID> __global__ void rollout_quad_kernel(RolloutArgs);
 __global__ void shift_kernel(float*, int, float*);
 template <int HID>
 __global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
@@ -40,6 +41,8 @@ constexpr int kWaveSamplesPerBlock = 8;   // 4 waves x 2 samples of 32 lanes
 constexpr int kWaveBlockThreads = 256;
 constexpr int kWideSamplesPerBlock = 8;   // 8 waves x 1 sample of 64 lanes
 constexpr int kWideBlockThreads = 512;
+constexpr int kQuadSamplesPerBlock = 64;  // 4 waves x 16 samples of 4 lanes
+constexpr int kQuadBlockThreads = 256;
 }  // namespace mppi
 
 using namespace mppi;
@@ -51,7 +54,7 @@ thread_local std::string g_create_error;
 constexpr int32_t kMaxK = 1 << 22;
 // Automatic schedule: 32 lanes per sample while that still fits the chip in a few
 // waves per SIMD (latency-bound regime), one lane per sample beyond.
-constexpr int32_t kWaveAutoMaxK = 32768;
+constexpr int32_t kWaveAutoMaxK = 12288;   // AUTO: WAVE up to here, QUAD above
 
 struct PendingTiming {
   hipEvent_t e0, e1;
@@ -129,7 +132,8 @@ mppi_status fail(mppi_ctx* c, mppi_status st, const char* fmt, ...) {
 bool finite(float v) { return std::isfinite(v); }
 
 int sched_ok(int s) {
-  return s == MPPI_SCHED_AUTO || s == MPPI_SCHED_LANE || s == MPPI_SCHED_WAVE || s == MPPI_SCHED_WIDE;
+  return s == MPPI_SCHED_AUTO || s == MPPI_SCHED_LANE || s == MPPI_SCHED_WAVE || s == MPPI_SCHED_WIDE ||
+         s == MPPI_SCHED_QUAD;
 }
 // The schedules that spread one sample over several lanes (FP32, h = 32 only).
 bool multi_lane(int s) { return s == MPPI_SCHED_WAVE || s == MPPI_SCHED_WIDE; }
@@ -239,6 +243,7 @@ int blocks_for(const mppi_ctx* c, int sched) {
   const int K = c->cfg.K;
   if (sched == MPPI_SCHED_WAVE) return (K + kWaveSamplesPerBlock - 1) / kWaveSamplesPerBlock;
   if (sched == MPPI_SCHED_WIDE) return (K + kWideSamplesPerBlock - 1) / kWideSamplesPerBlock;
+  if (sched == MPPI_SCHED_QUAD) return (K + kQuadSamplesPerBlock - 1) / kQuadSamplesPerBlock;
   return (K + kLaneBlockHost - 1) / kLaneBlockHost;
 }
 
@@ -258,6 +263,21 @@ void launch_wide(int G, int T, hipStream_t stream, const RolloutArgs& a) {
     hipLaunchKernelGGL((rollout_wide_kernel<2>), dim3(G), dim3(kWideBlockThreads), wide_smem_bytes(T), stream, a);
   else
     hipLaunchKernelGGL((rollout_wide_kernel<4>), dim3(G), dim3(kWideBlockThreads), wide_smem_bytes(T), stream, a);
+}
+
+// The quad kernel for the network's precision (MPPI_PREC_*, the same codes as the
+// kernel's) and width.
+void launch_quad(int precision, int hidden, int G, hipStream_t stream, const RolloutArgs& a) {
+  const dim3 grid(G), block(kQuadBlockThreads);
+#define MPPI_QUAD(P, H) hipLaunchKernelGGL((rollout_quad_kernel<P, H>), grid, block, 0, stream, a)
+  if (precision == MPPI_PREC_BF16) {
+    if (hidden == 32) MPPI_QUAD(1, 32); else MPPI_QUAD(1, 64);
+  } else if (precision == MPPI_PREC_FP16) {
+    if (hidden == 32) MPPI_QUAD(2, 32); else MPPI_QUAD(2, 64);
+  } else {
+    if (hidden == 32) MPPI_QUAD(0, 32); else MPPI_QUAD(0, 64);
+  }
+#undef MPPI_QUAD
 }
 
 RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x0_dev) {
@@ -348,6 +368,8 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   } else if (sched == MPPI_SCHED_WIDE) {
     if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wide schedule supports hidden 32 only");
     launch_wide(G, c->cfg.T, c->stream, a);
+  } else if (sched == MPPI_SCHED_QUAD) {
+    launch_quad(c->cfg.precision, c->hidden, G, c->stream, a);
   } else {
     HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
   }
@@ -453,14 +475,15 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     c->sig[1] = std::sqrt(cfg->sigma2[1]);
     c->schedule = cfg->schedule;
     c->part_cap = std::max({blocks_for(c, MPPI_SCHED_LANE), blocks_for(c, MPPI_SCHED_WAVE),
-                            blocks_for(c, MPPI_SCHED_WIDE)});
+                            blocks_for(c, MPPI_SCHED_WIDE), blocks_for(c, MPPI_SCHED_QUAD)});
     HIP_TRY(c, hipMalloc(&c->d_U, sizeof(float) * 2 * T));
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
     const int ngrp_cap = std::max({merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WAVE)),
-                                   merge_groups(blocks_for(c, MPPI_SCHED_WIDE))});
+                                   merge_groups(blocks_for(c, MPPI_SCHED_WIDE)),
+                                   merge_groups(blocks_for(c, MPPI_SCHED_QUAD))});
     HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)ngrp_cap * (2 + 2 * T)));
     HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(unsigned) * (ngrp_cap + 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (ngrp_cap + 1), c->stream));
@@ -557,9 +580,14 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     c->objective_ready = false;
     c->hidden = h;
     c->have_dyn = true;
-    if (c->cfg.schedule == MPPI_SCHED_AUTO)
-      c->schedule = (h == 32 && c->cfg.precision == MPPI_PREC_FP32 && c->cfg.K <= kWaveAutoMaxK)
-                        ? MPPI_SCHED_WAVE : MPPI_SCHED_LANE;
+    if (c->cfg.schedule == MPPI_SCHED_AUTO) {
+      // measured on MI355X at T = 100: the 32-lane schedule is fastest while the chains
+      // are few (latency-bound), the matrix-core quad schedule once K fills the device
+      if (c->cfg.precision == MPPI_PREC_FP32 && h == 32 && c->cfg.K <= kWaveAutoMaxK)
+        c->schedule = MPPI_SCHED_WAVE;
+      else
+        c->schedule = MPPI_SCHED_QUAD;
+    }
     return MPPI_OK;
   });
 }
@@ -894,6 +922,8 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
 // ===========================================================================
 namespace mppi {
 __global__ void rollout_batch_kernel(const RolloutArgs*, const int2*, int, const float*, const float*, const float*);
+__global__ void rollout_batch_quad_kernel(const RolloutArgs*, const int2*, int, const float*, const float*,
+                                          const float*);
 }
 
 struct mppi_batch {
@@ -925,6 +955,7 @@ struct mppi_batch {
   bool have_map = false, have_dyn = false, ready = false;
   int grid = 0, order = 0;
   double tuned_us = 0;
+  bool quad = true;                      // tiles of the quad schedule (64 samples) or the lane one (256)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool own_stream = false;
@@ -985,6 +1016,7 @@ std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
     a.G = b->G[i];
     a.sg_window = b->cfg.sg_window;
     a.update_U = 1;
+    a.hidden = 32;
     a.iter_dev = b->d_iter + i;
     a.ckpt = nullptr;
     a.ckpt_every = 1;
@@ -1045,9 +1077,14 @@ std::vector<int2> batch_items(const mppi_batch* b, int order) {
 }
 
 mppi_status batch_launch(mppi_batch* b, int grid) {
-  hipLaunchKernelGGL(rollout_batch_kernel, dim3(grid), dim3(kLaneBlockHost), 0, b->stream,
-                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
-                     (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
+  if (b->quad)
+    hipLaunchKernelGGL(rollout_batch_quad_kernel, dim3(grid), dim3(kQuadBlockThreads), 0, b->stream,
+                       (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
+                       (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
+  else
+    hipLaunchKernelGGL(rollout_batch_kernel, dim3(grid), dim3(kLaneBlockHost), 0, b->stream,
+                       (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
+                       (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
   BHIP_TRY(b, hipGetLastError());
   return MPPI_OK;
 }
@@ -1118,10 +1155,8 @@ mppi_status batch_prepare(mppi_batch* b) {
   if (b->graph) BHIP_TRY(b, hipGraphDestroy(b->graph));
   b->graph = nullptr;
   BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  hipLaunchKernelGGL(rollout_batch_kernel, dim3(b->grid), dim3(kLaneBlockHost), 0, b->stream,
-                     (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
-                     (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
-  hipError_t le = hipGetLastError();
+  mppi_status lst = batch_launch(b, b->grid);
+  hipError_t le = lst == MPPI_OK ? hipGetLastError() : hipErrorLaunchFailure;
   hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
   if (le != hipSuccess) return bfail(b, MPPI_E_DEVICE, "capture launch: %s", hipGetErrorString(le));
   if (ce != hipSuccess) return bfail(b, MPPI_E_DEVICE, "end capture: %s", hipGetErrorString(ce));
@@ -1155,6 +1190,8 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     sgmax = std::max(sgmax, T[i] * cfg->sg_window);
   }
   if (cfg->precision != MPPI_PREC_FP32) return bfail(nullptr, MPPI_E_INVAL, "the batched form runs the FP32 network");
+  if (cfg->schedule != MPPI_SCHED_AUTO && cfg->schedule != MPPI_SCHED_LANE && cfg->schedule != MPPI_SCHED_QUAD)
+    return bfail(nullptr, MPPI_E_INVAL, "the batched form runs the lane or quad schedule");
   mppi_status st = validate_cost(cost);
   if (st != MPPI_OK) return st;
   int ndev = 0;
@@ -1167,6 +1204,7 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
   b->device = device;
   b->stream = (hipStream_t)hip_stream;
   b->n = n;
+  b->quad = cfg->schedule != MPPI_SCHED_LANE;
   auto body = [&]() -> mppi_status {
     BHIP_TRY(b, hipSetDevice(device));
     if (!b->stream) {   // graph capture needs a stream other than the null stream
@@ -1176,7 +1214,8 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     size_t u = 0, s = 0, p = 0, p2 = 0, cn = 0, so = 0, sg = 0;
     int items = 0, Tmax = 0;
     for (int i = 0; i < n; ++i) {
-      const int g = (K[i] + kLaneBlockHost - 1) / kLaneBlockHost;
+      const int tile = b->quad ? kQuadSamplesPerBlock : kLaneBlockHost;
+      const int g = (K[i] + tile - 1) / tile;
       const int ng = merge_groups(g);
       b->K.push_back(K[i]);
       b->T.push_back(T[i]);

@@ -17,7 +17,7 @@ LIB_PATH = PKG / "libmppi.so"
 
 MPPI_OK, MPPI_E_INVAL, MPPI_E_STATE, MPPI_E_NOMEM, MPPI_E_DEVICE, MPPI_E_NONFINITE = range(6)
 MPPI_PREC_FP32, MPPI_PREC_BF16, MPPI_PREC_FP16 = 0, 1, 2
-MPPI_SCHED_AUTO, MPPI_SCHED_LANE, MPPI_SCHED_WAVE, MPPI_SCHED_WIDE = 0, 1, 2, 3
+MPPI_SCHED_AUTO, MPPI_SCHED_LANE, MPPI_SCHED_WAVE, MPPI_SCHED_WIDE, MPPI_SCHED_QUAD = 0, 1, 2, 3, 4
 MPPI_T_MAX = 256
 
 STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_NOMEM",
@@ -349,11 +349,12 @@ def mppi_batch_synchronize(b) -> None:
 class Batch:
     """Many MPPI problems advanced by one persistent launch (see mppi_batch_create)."""
 
-    def __init__(self, base_prob, Ks, Ts, cmap, params, device: int = 0, stream: Optional[int] = None):
+    def __init__(self, base_prob, Ks, Ts, cmap, params, device: int = 0, stream: Optional[int] = None,
+                 schedule: int = MPPI_SCHED_AUTO):
         self.Ks = [int(k) for k in Ks]
         self.Ts = [int(t) for t in Ts]
-        self.b = mppi_batch_create(make_config(base_prob), make_cost(base_prob.cost), self.Ks, self.Ts, device,
-                                   0 if stream is None else stream)
+        self.b = mppi_batch_create(make_config(base_prob, schedule=schedule), make_cost(base_prob.cost), self.Ks,
+                                   self.Ts, device, 0 if stream is None else stream)
         try:
             mppi_batch_set_costmap(self.b, cmap.data, cmap.origin_x, cmap.origin_y, cmap.resolution)
             mppi_batch_set_dynamics(self.b, params)

@@ -52,15 +52,16 @@ def _record(name, payload):
         f.write(json.dumps({"case": name, **payload}) + "\n")
 
 
-@pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
-def test_precision_form_error_vs_fp64(M, orc, prec, seed):
-    """K=16384, T=100, 6-64-64-4 network, ring map, C1 cost; BF16 (1) or FP16 (2) operands."""
+@pytest.mark.parametrize("prec,schedule,seed", [(p, 4, s) for p in (1, 2) for s in range(5)] +
+                         [(p, 1, 0) for p in (1, 2)])
+def test_precision_form_error_vs_fp64(M, orc, prec, schedule, seed):
+    """K=16384, T=100, 6-64-64-4 network, ring map, C1 cost; BF16 (1) or FP16 (2) operands
+    on the quad schedule (4 lanes per sample, the default) and on the lane schedule."""
     prob = synth.c3_problem(K=16384, seed=seed)
     params = synth.mlp_params(64, 0)
     cmap = synth.ring_map()
-    print(f"precision {prec} seed {seed}", flush=True)
-    with M.Controller(prob, cmap, params, precision=prec) as c:
+    print(f"precision {prec} schedule {schedule} seed {seed}", flush=True)
+    with M.Controller(prob, cmap, params, precision=prec, schedule=schedule) as c:
         S, st = c.iterate(synth.C1_X0, want_costs=True)
         U = c.controls()
     op = orc.OracleProblem(prob, cmap, params)
@@ -74,7 +75,7 @@ def test_precision_form_error_vs_fp64(M, orc, prec, seed):
     dU_r = np.abs(U - ref_r.U).max()
     print(f"  S rel max {rel.max():.2e} (rounded weights {rel_r.max():.2e}); |dU| {dU:.2e} ({dU_r:.2e})",
           flush=True)
-    _record(f"precision{prec}_seed{seed}", {"S_rel_max": float(rel.max()), "S_rel_median": float(np.median(rel)),
+    _record(f"precision{prec}_sched{schedule}_seed{seed}", {"S_rel_max": float(rel.max()), "S_rel_median": float(np.median(rel)),
                                             "S_rel_max_rounded_weights": float(rel_r.max()),
                                             "dU_max": float(dU), "dU_max_rounded_weights": float(dU_r)})
     assert st == M.MPPI_OK
@@ -130,10 +131,12 @@ def test_precision_form_h32_matches_fp32_closely(M, orc):
 # Batched form
 # ---------------------------------------------------------------------------
 
-def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None):
+def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None, schedule=4):
+    """The batch (tiles of the given schedule; AUTO means quad) against single-problem
+    contexts running the same schedule."""
     base = synth.c2_problem(seed=7)
     cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
-    with M.Batch(base, Ks, Ts, cmap, params) as b:
+    with M.Batch(base, Ks, Ts, cmap, params, schedule=schedule) as b:
         for _ in range(n_iter):
             b.iterate(x0s)
         b.synchronize()
@@ -143,7 +146,7 @@ def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None):
     print(f"batch of {len(Ks)}: autotuned grid {grid}, order {order}, {us:.1f} us/launch", flush=True)
     for i in got:
         p = synth.with_(base, K=Ks[i], T=Ts[i], instance=i)
-        with M.Controller(p, cmap, params, schedule=1) as c:
+        with M.Controller(p, cmap, params, schedule=schedule) as c:
             for _ in range(n_iter):
                 S, _ = c.iterate(x0s[i], want_costs=True)
             U = c.controls()
@@ -152,14 +155,15 @@ def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None):
     return got
 
 
-def test_batch_matches_single_contexts(M):
+@pytest.mark.parametrize("schedule", [1, 4])
+def test_batch_matches_single_contexts(M, schedule):
     rng = np.random.default_rng(0)
     n = 24
     Ks = rng.choice([256, 300, 512, 1000], size=n)
     Ts = rng.choice([20, 33, 50], size=n)
     x0s = np.stack([synth.ellipse_pose(float(p), float(v)) for p, v in
                     zip(rng.uniform(0, 2 * np.pi, n), rng.uniform(2, 10, n))])
-    _batch_vs_single(M, Ks, Ts, x0s, n_iter=3)
+    _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, schedule=schedule)
 
 
 def test_batch_full_size_spot_checks(M, orc):
@@ -204,10 +208,10 @@ def test_batch_new_map_and_network_take_effect(M):
         got = [(b.controls(i), b.costs(i)) for i in range(3)]
     for i in range(3):
         p = synth.with_(base, K=Ks[i], T=Ts[i], instance=i)
-        with M.Controller(p, m1, p1, schedule=1) as c:
+        with M.Controller(p, m1, p1, schedule=4) as c:
             c.iterate(x0s[i])
             U1 = c.controls()
-        with M.Controller(p, m2, p2, schedule=1) as c:
+        with M.Controller(p, m2, p2, schedule=4) as c:
             c.set_controls(U1)
             c.iteration = 1
             S, _ = c.iterate(x0s[i], want_costs=True)
@@ -223,6 +227,8 @@ def test_batch_rejects_bad_shapes(M):
         M.mppi_batch_create(cfg, cost, [256, 0], [20, 20])
     with pytest.raises(M.MppiError):
         M.mppi_batch_create(cfg, cost, [256], [300])
+    with pytest.raises(M.MppiError):
+        M.mppi_batch_create(M.make_config(base, schedule=2), cost, [256], [20])
     b = M.mppi_batch_create(cfg, cost, [256], [20])
     try:
         with pytest.raises(M.MppiError) as e:

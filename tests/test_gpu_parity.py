@@ -47,7 +47,7 @@ def _say(*a):
 
 
 def _schedules():
-    return [1, 2, 3]
+    return [1, 2, 3, 4]
 
 
 # ---------------------------------------------------------------------------
@@ -172,10 +172,11 @@ def test_ragged_shapes(M, orc, schedule, K, T):
                      synth.random_controls(T, K), schedule)
 
 
-@pytest.mark.parametrize("schedule,K", [(2, 2049), (2, 4100), (2, 32768), (3, 2049), (3, 4100), (1, 65537), (1, 70000)])
+@pytest.mark.parametrize("schedule,K", [(2, 2049), (2, 4100), (2, 32768), (3, 2049), (3, 4100), (4, 16385),
+                                        (4, 70000), (1, 65537), (1, 70000)])
 def test_many_blocks(M, orc, schedule, K):
     """Launches of more than 256 blocks: the partial rows are merged in groups of
-    ceil(sqrt(G)) blocks (wave and wide: 8 samples per block, lane: 256)."""
+    ceil(sqrt(G)) blocks (wave and wide: 8 samples per block, quad: 64, lane: 256)."""
     T = 12
     prob = synth.with_(synth.c1_problem(seed=K), K=K, T=T)
     _say("many blocks", schedule, K)
