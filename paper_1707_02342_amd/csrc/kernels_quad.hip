@@ -523,8 +523,10 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   finish_iteration<kQuadBlock>(a, tile, rho, eta, N_lds, red);
 }
 
+// h = 32 fits three waves per SIMD without spilling (168 registers); h = 64 keeps the
+// compiler's allocation.
 template <int PREC, int HID>
-__global__ __launch_bounds__(kQuadBlock) void rollout_quad_kernel(RolloutArgs a) {
+__global__ __launch_bounds__(kQuadBlock, HID == 32 ? 3 : 1) void rollout_quad_kernel(RolloutArgs a) {
   if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   __shared__ float sU[2 * kTMax];
   __shared__ float sE[kQuadWaves * kQuadChunk * 16 * 2 > 2 * kTMax ? kQuadWaves * kQuadChunk * 16 * 2 : 2 * kTMax];
