@@ -30,7 +30,9 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector (and FP32 matrix) peak
+PEAK_BF16_TFLOPS = 2500.0         # MI355X published dense BF16/FP16 matrix peak
+VALU_LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one FP32 op per lane per cycle
 TRAFFIC_FILE = ROOT / "profiles" / "rollout_wave_k1920_t100_traffic.json"
 # the sources the benchmarked kernel (rollout_wave_kernel<32, 4>) is built from: stored
 # counter readings are used only while these files are unchanged
@@ -193,6 +195,20 @@ def measure_forms(M, stream, iters: int = 30):
         ms = _timed_iterations(ctl, synth.C1_X0, iters, stream)
         ctl.close()
         prec[name] = {"ms_per_iteration": ms, "steps_per_s": prob.K * prob.T / (ms * 1e-3)}
+    # rooflines: FP32 on the matrix cores against the FP32 matrix peak; BF16/FP16 are
+    # bound by the vector ALU (tanh: exp and rcp at quarter rate + 3 FMA = 11 slots, 128
+    # per step at h = 64, plus ~150 other slots) -- reported against that bound and,
+    # for reference, as a fraction of the BF16/FP16 matrix peak
+    flop = NET_FLOP_PER_STEP[64]
+    valu_steps_peak = VALU_LANE_SLOTS_PER_S / (128 * 11 + 150)
+    f32_tflops = prec["fp32"]["steps_per_s"] * flop / 1e12
+    prec["fp32"]["roofline"] = {"bound": "mfma", "achieved": f32_tflops, "peak": PEAK_FP32_TFLOPS,
+                                "unit": "TFLOP/s", "frac": f32_tflops / PEAK_FP32_TFLOPS}
+    for name in ("bf16", "fp16"):
+        st = prec[name]["steps_per_s"]
+        prec[name]["roofline"] = {"bound": "alu", "achieved": st / 1e9, "peak": valu_steps_peak / 1e9,
+                                  "unit": "Gsteps/s", "frac": st / valu_steps_peak,
+                                  "mfma_frac": st * flop / 1e12 / PEAK_BF16_TFLOPS}
     prec["bf16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["bf16"]["ms_per_iteration"]
     prec["fp16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["fp16"]["ms_per_iteration"]
     prec["workload"] = "K=16384, T=100, 6-64-64-4 network, 256x256 ring map"
@@ -211,7 +227,10 @@ def measure_forms(M, stream, iters: int = 30):
         ms = (time.perf_counter() - t0) * 1e3 / iters
         grid, order, tuned_us = b.schedule()
     work = float(sum(k * t for k, t in zip(Ks, Ts)))
+    bt = work * NET_FLOP_PER_STEP[32] / (ms * 1e-3) / 1e12
     out["batched"] = {"ms_per_iteration": ms, "steps_per_s": work / (ms * 1e-3), "instances": len(Ks),
+                      "roofline": {"bound": "mfma", "achieved": bt, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": bt / PEAK_FP32_TFLOPS},
                       "grid": grid, "order": order,
                       "workload": "512 instances, K_i in {512..4096}, T_i in {50..150}, 2048x2048 map"}
 

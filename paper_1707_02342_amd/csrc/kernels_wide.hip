@@ -1,9 +1,10 @@
 // Rollout schedule "wide": a whole wavefront (64 lanes) per sample, eight samples per
-// 512-thread block, for the latency-bound regime of a few thousand samples.  At
-// K = 1920 this gives two waves per SIMD; one wave alone issues a vector
-// instruction only every ~4 cycles, so two independent waves per SIMD keep the unit
-// busy where the 32-lane layout (two samples per wave, one wave per SIMD) leaves it
-// half idle, and each wave's serial chain carries half as many layer-2 products.
+// 512-thread block.  Each step carries half as many layer-2 products per lane as the
+// 32-lane layout, and at K = 1920 there are two waves per SIMD.  Measured on MI355X
+// it is nevertheless slower than the 32-lane layout (67.9 vs 53.2 us per iteration at
+// K = 1920, T = 100): the DPP operand instructions that carry the products do not
+// issue concurrently from two waves, so per sample the 64-lane layout spends more
+// SIMD cycles on them.  It is kept as an explicit schedule.
 //
 // Lane l = 16 r + c (row r = 0..3, column c = 0..15).  Phases as in the 32-lane
 // layout (noise, serial chain of the dynamic states, kinematics and cost parallel

@@ -52,15 +52,16 @@ def _record(name, payload):
         f.write(json.dumps({"case": name, **payload}) + "\n")
 
 
-@pytest.mark.parametrize("prec,schedule,seed", [(p, 4, s) for p in (1, 2) for s in range(5)] +
-                         [(p, 1, 0) for p in (1, 2)])
-def test_precision_form_error_vs_fp64(M, orc, prec, schedule, seed):
-    """K=16384, T=100, 6-64-64-4 network, ring map, C1 cost; BF16 (1) or FP16 (2) operands
-    on the quad schedule (4 lanes per sample, the default) and on the lane schedule."""
-    prob = synth.c3_problem(K=16384, seed=seed)
+@pytest.mark.parametrize("prec,schedule,seed,K", [(p, 4, s, 16384) for p in (1, 2) for s in range(5)] +
+                         [(p, 1, 0, 16384) for p in (1, 2)] + [(p, 4, 0, 65536) for p in (1, 2)])
+def test_precision_form_error_vs_fp64(M, orc, prec, schedule, seed, K):
+    """K=16384 (and 65536), T=100, 6-64-64-4 network, ring map, C1 cost; BF16 (1) or FP16
+    (2) operands on the quad schedule (4 lanes per sample, the default) and on the lane
+    schedule."""
+    prob = synth.c3_problem(K=K, seed=seed)
     params = synth.mlp_params(64, 0)
     cmap = synth.ring_map()
-    print(f"precision {prec} schedule {schedule} seed {seed}", flush=True)
+    print(f"precision {prec} schedule {schedule} seed {seed} K {K}", flush=True)
     with M.Controller(prob, cmap, params, precision=prec, schedule=schedule) as c:
         S, st = c.iterate(synth.C1_X0, want_costs=True)
         U = c.controls()
@@ -75,7 +76,7 @@ def test_precision_form_error_vs_fp64(M, orc, prec, schedule, seed):
     dU_r = np.abs(U - ref_r.U).max()
     print(f"  S rel max {rel.max():.2e} (rounded weights {rel_r.max():.2e}); |dU| {dU:.2e} ({dU_r:.2e})",
           flush=True)
-    _record(f"precision{prec}_sched{schedule}_seed{seed}", {"S_rel_max": float(rel.max()), "S_rel_median": float(np.median(rel)),
+    _record(f"precision{prec}_sched{schedule}_seed{seed}_K{K}", {"S_rel_max": float(rel.max()), "S_rel_median": float(np.median(rel)),
                                             "S_rel_max_rounded_weights": float(rel_r.max()),
                                             "dU_max": float(dU), "dU_max_rounded_weights": float(dU_r)})
     assert st == M.MPPI_OK
