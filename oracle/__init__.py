@@ -49,7 +49,8 @@ class Problem(C.Structure):
         ("H", C.c_int32), ("W", C.c_int32),
         ("origin_x", C.c_float), ("origin_y", C.c_float), ("resolution", C.c_float),
         ("map", C.POINTER(C.c_float)), ("params", C.POINTER(C.c_float)),
-        ("seed", C.c_uint64), ("instance", C.c_uint32), ("nthreads", C.c_int32),
+        ("seed", C.c_uint64), ("instance", C.c_uint32), ("explore", C.c_float),
+        ("nthreads", C.c_int32),
     ]
 
 
@@ -138,6 +139,7 @@ class OracleProblem:
         s.params = _ptr(self.params, C.c_float)
         s.seed = int(prob.seed)
         s.instance = int(getattr(prob, "instance", 0))
+        s.explore = float(getattr(prob, "explore", 0.0))
         s.nthreads = int(nthreads or min(16, os.cpu_count() or 1))
         self.s = s
 

@@ -58,6 +58,7 @@ typedef struct {
   const float* params;      // packed W1,b1,W2,b2,W3,b3 (row-major [out][in])
   uint64_t seed;
   uint32_t instance;
+  float explore;            // exploration fraction alpha of Algorithm 1 (0 = none)
   int32_t nthreads;
 } orc_problem;
 
@@ -189,6 +190,12 @@ struct Prob {
   R ox, oy, res;
   const float* map;
   std::vector<R> W1, b1, W2, b2, W3, b3;
+  double explore;   // alpha of Algorithm 1, exactly as given (float widened)
+
+  // Algorithm 1 draws sample k (counted from 0) around the nominal controls when
+  // k < (1 - alpha) K and around zero otherwise (the exploration samples of the
+  // disturbance discussion in Section IV).  The comparison is made in FP64.
+  bool exploration(int k) const { return !((double)k < (1.0 - explore) * (double)K); }
 };
 
 template <class R>
@@ -224,6 +231,7 @@ Prob<R> make_prob(const orc_problem* p, const double* params_override = nullptr)
   P.H = p->H; P.W = p->W;
   P.ox = (R)p->origin_x; P.oy = (R)p->origin_y; P.res = (R)p->resolution;
   P.map = p->map;
+  P.explore = (double)p->explore;
   load_params(P, p->params, params_override);
   return P;
 }
@@ -328,12 +336,17 @@ void dynamics_step(const Prob<R>& P, const R x[7], const R vc[2], R xn[7], R* h1
   for (int i = 0; i < 4; ++i) xn[3 + i] = x[3 + i] + P.dt * f[i];
 }
 
-// Algorithm 1 inner loop for sample k: x <- F(x, g(u_{t} + eps_t)),
-// S += c(x, t+1) + gamma * sum_i u_{t,i} eps_{t,i} / Sigma_ii (the epsilon form of
-// the control cost, equal to the paper's gamma u^T Sigma^-1 v up to a term that
-// is the same for every sample).  Non-finite state or cost gives S = +inf.
+// Algorithm 1 inner loop for sample k.  The control applied is
+//   v_t = u_t + eps_t  (importance sample)   or   v_t = eps_t  (exploration sample),
+// the state advances as x <- F(x, g(v_t)), and the running cost is
+//   S += c(x, t+1) + gamma * sum_i u_{t,i} delta_{t,i} / Sigma_ii,   delta_t = v_t - u_t.
+// This is the paper's gamma u^T Sigma^-1 v written with v - u in place of v: the two
+// differ by gamma * sum_t u_t^T Sigma^-1 u_t, which is the same for every sample, so
+// weights and updates are unchanged.  For importance samples delta_t is eps_t
+// itself (no rounding).  Non-finite state or cost gives S = +inf.
 template <class R>
-R rollout_one(const Prob<R>& P, const float* x0, const float* U, const float* eps_k, R* traj) {
+R rollout_one(const Prob<R>& P, const float* x0, const float* U, const float* eps_k,
+              bool zero_mean, R* traj) {
   std::vector<R> h1(P.h), h2(P.h);
   R x[7];
   for (int i = 0; i < 7; ++i) x[i] = (R)x0[i];
@@ -343,14 +356,18 @@ R rollout_one(const Prob<R>& P, const float* x0, const float* U, const float* ep
   for (int t = 0; t < P.T; ++t) {
     const R u[2] = {(R)U[2 * t], (R)U[2 * t + 1]};
     const R e[2] = {(R)eps_k[2 * t], (R)eps_k[2 * t + 1]};
-    const R vc[2] = {clampv(u[0] + e[0], P.u_lo[0], P.u_hi[0]),
-                     clampv(u[1] + e[1], P.u_lo[1], P.u_hi[1])};
+    R v[2], d[2];
+    for (int i = 0; i < 2; ++i) {
+      v[i] = zero_mean ? e[i] : u[i] + e[i];
+      d[i] = zero_mean ? e[i] - u[i] : e[i];
+    }
+    const R vc[2] = {clampv(v[0], P.u_lo[0], P.u_hi[0]), clampv(v[1], P.u_lo[1], P.u_hi[1])};
     R xn[7];
     dynamics_step(P, x, vc, xn, h1.data(), h2.data());
     for (int i = 0; i < 7; ++i) { x[i] = xn[i]; ok = ok && std::isfinite((double)x[i]); }
     if (traj) for (int i = 0; i < 7; ++i) traj[(size_t)(t + 1) * 7 + i] = x[i];
     S += state_cost(P, x, t + 1) +
-         P.gamma * (u[0] * e[0] / P.sigma2[0] + u[1] * e[1] / P.sigma2[1]);
+         P.gamma * (u[0] * d[0] / P.sigma2[0] + u[1] * d[1] / P.sigma2[1]);
   }
   if (!ok || !std::isfinite((double)S)) S = std::numeric_limits<R>::infinity();
   return S;
@@ -371,7 +388,7 @@ template <class R>
 void rollout_all(const Prob<R>& P, int nthreads, const float* x0, const float* U, const float* eps,
                  R* S, R* traj) {
   parallel_for(P.K, nthreads, [&](int k) {
-    S[k] = rollout_one(P, x0, U, eps + (size_t)k * P.T * 2,
+    S[k] = rollout_one(P, x0, U, eps + (size_t)k * P.T * 2, P.exploration(k),
                        traj ? traj + (size_t)k * (P.T + 1) * 7 : nullptr);
   });
 }
@@ -458,6 +475,7 @@ bool valid_problem(const orc_problem* p) {
   if (p->sg_window < 1 || p->sg_window % 2 == 0 || p->sg_window > p->T) return false;
   if (p->sg_order < 0 || p->sg_order >= p->sg_window) return false;
   if (!p->map || !p->params || p->H <= 0 || p->W <= 0 || !(p->resolution > 0)) return false;
+  if (!(p->explore >= 0.0f && p->explore <= 1.0f)) return false;
   return true;
 }
 
@@ -498,7 +516,12 @@ int orc_weights(int K, const double* S, double lambda, double* w, double* rho, d
 void orc_sgf_matrix(int T, int window, int order, double* M) { sgf_matrix(T, window, order, M); }
 
 // One iteration of Algorithm 1 (without the shift): noise, rollouts, weights,
-// Delta_t = sum_k w_k eps_{k,t}, U_out = U + SGF * Delta.  Outputs in FP64.
+// Delta_t = sum_k w_k delta_{k,t}, U_out = U + SGF * Delta, where delta_{k,t} =
+// v_{k,t} - u_t is eps_{k,t} for importance samples and eps_{k,t} - u_t for
+// exploration samples.  (Algorithm 1 writes the sum with E^k for every sample; with
+// exploration samples that is not the optimal-control update of Eq. IT-Controls,
+// u* = sum_k w_k v_k = u + sum_k w_k (v_k - u), which is what is computed here.)
+// Outputs in FP64.
 // eps_in (nullable) overrides the generated noise.  rho_eta_out = {rho, eta~}.
 int orc_iterate(const orc_problem* p, const float* x0, const float* U, uint32_t iter,
                 const float* eps_in, double* U_out, double* S_out, double* w_out,
@@ -518,8 +541,13 @@ int orc_iterate(const orc_problem* p, const float* x0, const float* U, uint32_t 
   if (rho_eta_out) { rho_eta_out[0] = rho; rho_eta_out[1] = eta; }
   for (int i = 0; i < 2 * T; ++i) U_out[i] = (double)U[i];
   if (st != ORC_OK) { if (delta_out) std::fill(delta_out, delta_out + 2 * T, 0.0); return st; }
-  for (int k = 0; k < K; ++k)
-    for (int i = 0; i < 2 * T; ++i) delta[i] += w[k] * (double)eps[(size_t)k * T * 2 + i];
+  for (int k = 0; k < K; ++k) {
+    const bool zero_mean = P.exploration(k);
+    for (int i = 0; i < 2 * T; ++i) {
+      const double e = (double)eps[(size_t)k * T * 2 + i];
+      delta[i] += w[k] * (zero_mean ? e - (double)U[i] : e);
+    }
+  }
   if (delta_out) std::copy(delta.begin(), delta.end(), delta_out);
   sgf_matrix(T, p->sg_window, p->sg_order, M.data());
   for (int t = 0; t < T; ++t)
@@ -551,9 +579,11 @@ void orc_plant_step(const orc_problem* p, const double* x, const double* u, doub
 //   = rho - lambda log(eta~/K)            (Eq. FreeEnergy with the Monte-Carlo
 // estimate over the K samples of this iteration's noise), evaluated at FP64
 // nominal controls U and FP64 network parameters (nullable: use the problem's).
+// Defined for importance samples only (exploration fraction 0; otherwise INVAL).
 int orc_objective(const orc_problem* p, const float* x0, const double* U, const double* params,
                   uint32_t iter, double* J, double* S_out) {
   if (!valid_problem(p)) return ORC_E_INVAL;
+  if (p->explore != 0.0f) return ORC_E_INVAL;   // defined for importance samples only
   const int K = p->K, T = p->T;
   std::vector<float> eps((size_t)K * T * 2);
   noise_all(p, iter, eps.data());
@@ -594,6 +624,7 @@ int orc_objective(const orc_problem* p, const float* x0, const double* U, const 
 int orc_objective_grad(const orc_problem* p, const float* x0, const double* U, const double* params,
                        uint32_t iter, double* J, double* dJdU, double* dJdtheta) {
   if (!valid_problem(p)) return ORC_E_INVAL;
+  if (p->explore != 0.0f) return ORC_E_INVAL;
   const int K = p->K, T = p->T, h = p->hidden;
   std::vector<float> eps((size_t)K * T * 2);
   noise_all(p, iter, eps.data());
@@ -711,7 +742,7 @@ int orc_threshold_margins(const orc_problem* p, const float* x0, const float* U,
   const int T = P.T;
   parallel_for(P.K, p->nthreads, [&](int k) {
     std::vector<double> tr((size_t)(T + 1) * 7);
-    rollout_one(P, x0, U, eps + (size_t)k * T * 2, tr.data());
+    rollout_one(P, x0, U, eps + (size_t)k * T * 2, P.exploration(k), tr.data());
     double m = std::numeric_limits<double>::infinity();
     for (int t = 1; t <= T; ++t) {
       const double* x = &tr[(size_t)t * 7];

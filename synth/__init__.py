@@ -230,6 +230,7 @@ class Problem:
     sg_order: int = 0
     seed: int = 0
     instance: int = 0
+    explore: float = 0.0                 # fraction of zero-mean (exploration) samples
     cost: CostParams = field(default_factory=CostParams)
 
     @property
@@ -277,6 +278,14 @@ def c5_problem(seed: int = 0) -> Problem:
     return Problem(K=4096, T=100, hidden=32, dt=0.02, lam=1.0, sigma2=(0.3, 0.35),
                    sg_window=1, sg_order=0, seed=seed,
                    cost=CostParams(w_map=100.0, w_speed=1.0, v_des=6.0))
+
+
+def explore_problem(seed: int = 0, K: int = 1920, explore: float = 0.01) -> Problem:
+    """Exploration samples with the paper's parameter table: the paper-shaped C2 problem
+    with lambda=12.5, gamma=0.1, Sigma=Diag(0.0306, 0.0506) (variances) and a fraction
+    alpha=0.01 of zero-mean samples."""
+    return Problem(K=K, T=100, hidden=32, dt=0.02, lam=12.5, gamma=0.1, sigma2=(0.0306, 0.0506),
+                   sg_window=9, sg_order=2, seed=seed, explore=explore, cost=c2_cost())
 
 
 def ellipse_pose(phi: float, v_x: float, center=(51.2, 51.2), semi_axes=(40.0, 25.0)) -> np.ndarray:
