@@ -72,7 +72,14 @@ enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2, MPPI_SCHED
  * Invalid (MPPI_E_INVAL): K < 1 or K > 1<<22; T < 1 or T > MPPI_T_MAX; dt, lambda
  * not finite and > 0; sigma2[i] not finite and > 0 (Sigma^-1 must exist); gamma not
  * finite; u_lo[i] > u_hi[i]; sg_window even, < 1 or > T; sg_order < 0 or
- * >= sg_window; precision not one of MPPI_PREC_*; schedule not one of MPPI_SCHED_*. */
+ * >= sg_window; precision not one of MPPI_PREC_*; schedule not one of MPPI_SCHED_*;
+ * explore not in [0, 1].
+ * Exploration samples (Algorithm 1's alpha and the disturbance discussion of
+ * Section IV): sample k is drawn around zero when k >= ceil((1 - explore) K).  For every
+ * sample delta_t = v_t - u_t enters the running cost as gamma u_t^T Sigma^-1 delta_t
+ * (the paper's gamma u^T Sigma^-1 v up to a constant shared by all samples) and the
+ * update as U <- U + SGF * sum_k w_k delta_k (Eq. IT-Controls).  With explore = 0,
+ * delta = eps. */
 typedef struct {
   int32_t K;            /* samples per iteration                                   */
   int32_t T;            /* horizon (time steps)                                    */
@@ -88,6 +95,9 @@ typedef struct {
   int32_t schedule;     /* MPPI_SCHED_*                                            */
   uint64_t seed;        /* Philox4x32-10 key (lo, hi 32-bit words)                 */
   uint32_t instance;    /* fourth Philox counter word                              */
+  float explore;        /* alpha of Algorithm 1: samples k >= ceil((1 - alpha) K)
+                           are drawn around zero (v = eps) instead of around U;
+                           0 = every sample around U                              */
 } mppi_config;
 
 /* State cost c(x, t) at the post-step state x_t, t = 1..T (Section VI-C):
@@ -211,7 +221,8 @@ mppi_status mppi_get_timing_samples(mppi_ctx* ctx, float* ms_out, int32_t cap, i
  * counter is not advanced and U is not changed).  The forward pass stores every
  * sample's full state each `ckpt_every` steps (1..16) for the backward pass.
  * Synchronises.  J_out and costs_out ([K]) may be NULL.  Requires h = 32.
- * INVAL: ckpt_every outside [1, 16] or h != 32.  NONFINITE: no finite cost. */
+ * INVAL: ckpt_every outside [1, 16], h != 32 or explore != 0 (the objective is
+ * defined over importance samples only).  NONFINITE: no finite cost. */
 mppi_status mppi_objective(mppi_ctx* ctx, const float x0[7], uint32_t iter, int32_t ckpt_every,
                            double* J_out, float* costs_out);
 

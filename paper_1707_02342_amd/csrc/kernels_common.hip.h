@@ -2,8 +2,9 @@
 //
 // Each rollout block ends by summarising its samples as
 //   rho_g = min_k S_k,  eta_g = sum_k exp(-(S_k - rho_g)/lambda),
-//   N_g[t] = sum_k exp(-(S_k - rho_g)/lambda) eps_{k,t}
-// so that the last block to finish can form Algorithm 2's weights and the weighted
+//   N_g[t] = sum_k exp(-(S_k - rho_g)/lambda) delta_{k,t},
+// delta_{k,t} = v_{k,t} - u_t (eps_{k,t}, or eps_{k,t} - u_t for an exploration sample drawn
+// around zero), so that the last block to finish can form Algorithm 2's weights and the weighted
 // perturbation sum exactly: rho = min_g rho_g, eta~ = sum_g e^{-(rho_g-rho)/lambda} eta_g,
 // Delta_t = sum_g e^{-(rho_g-rho)/lambda} N_g[t] / eta~.  All sums run in a fixed
 // order, so results are reproducible run to run.

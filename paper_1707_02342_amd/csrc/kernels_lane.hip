@@ -226,10 +226,12 @@ struct NetMfma {
 
 // This block's (rho_g, eta_g, N_g[T][2]), N_g regenerating eps; N_g goes to N_lds
 // (complete after the block's next barrier).
+// delta_{k,t} = v_{k,t} - u_t (eps, or eps - u_t for exploration samples) in place of
+// eps; sU is the nominal sequence in LDS and may alias N_lds.
 __device__ __forceinline__ void lane_block_partial(const RolloutArgs& a, float S, bool valid, int k,
                                                    float* red /* [kLaneWaves][2*kTMax] */,
-                                                   float* scratch, float* N_lds, float& rho_out,
-                                                   float& eta_out) {
+                                                   float* scratch, const float* sU, float* N_lds,
+                                                   float& rho_out, float& eta_out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const float sv = valid ? S : kInf;
   const float rho = block_min<kLaneWaves>(sv, scratch);
@@ -237,7 +239,13 @@ __device__ __forceinline__ void lane_block_partial(const RolloutArgs& a, float S
   const float eta = block_sum<kLaneWaves>(e, scratch);
   for (int t = 0; t < a.T; ++t) {
     float e0 = 0.0f, e1 = 0.0f;
-    if (valid) draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+    if (valid) {
+      draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+      if (k >= a.K_imp) {
+        e0 -= sU[2 * t];
+        e1 -= sU[2 * t + 1];
+      }
+    }
     const float n0 = wave_sum(e * e0);
     const float n1 = wave_sum(e * e1);
     if (lane == 0) {
@@ -263,6 +271,7 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   __syncthreads();
   const int k = tile * kLaneBlock + threadIdx.x;
   const bool valid = k < a.K;
+  const bool zm = k >= a.K_imp;   // exploration sample: v = eps
   const Net net(a.params);
   // State and cost in compensated form (hi + lo); the network and the kinematics read
   // the hi parts, the cost reads hi + lo.  Lanes past K run too (the matrix-core
@@ -279,8 +288,9 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
     float e0, e1;
     draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
     const float u0 = sU[2 * t], u1 = sU[2 * t + 1];
-    const float vc0 = fminf(fmaxf(u0 + e0, a.u_lo0), a.u_hi0);
-    const float vc1 = fminf(fmaxf(u1 + e1, a.u_lo1), a.u_hi1);
+    const float vc0 = fminf(fmaxf(zm ? e0 : u0 + e0, a.u_lo0), a.u_hi0);
+    const float vc1 = fminf(fmaxf(zm ? e1 : u1 + e1, a.u_lo1), a.u_hi1);
+    const float d0 = zm ? e0 - u0 : e0, d1 = zm ? e1 - u1 : e1;   // v - u
     const float in[6] = {x[3].hi, x[4].hi, x[5].hi, x[6].hi, vc0, vc1};
     float f[4];
     net.eval(in, f);
@@ -298,13 +308,13 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
     for (int i = 0; i < kStateDim; ++i) ok = ok && finite_f(x[i].hi);
     S.add(state_cost2(a.cost, a.map, a.decay, x[0].hi, x[0].lo, x[1].hi, x[1].lo, x[4].value(),
                       x[5].value(), t + 1));
-    S.add(a.gcs0 * (u0 * e0) + a.gcs1 * (u1 * e1));
+    S.add(a.gcs0 * (u0 * d0) + a.gcs1 * (u1 * d1));
   }
   float Sv = S.value();
   if (!ok || !finite_f(Sv)) Sv = kInf;
   if (valid) store_through(a.S + k, Sv);   // read by the host only; kept out of L2
   float rho, eta;
-  lane_block_partial(a, Sv, valid, k, red, scratch, sU, rho, eta);
+  lane_block_partial(a, Sv, valid, k, red, scratch, sU, sU, rho, eta);
   finish_iteration<kLaneBlock>(a, tile, rho, eta, sU, red);
 }
 

@@ -281,6 +281,7 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   const int j = lane & 15;
   const int k = tile * kQuadSamples + wv * 16 + j;
   const bool valid = k < a.K;
+  const bool zm = k >= a.K_imp;   // exploration sample: v = eps, delta = eps - u
   float* wE = sE + wv * (kQuadChunk * 16 * 2);          // [chunk step][sample][2]
   float* wX = sX + wv * ((kQuadChunk + 1) * 16 * 4);    // [chunk step 0..16][sample][4]
 
@@ -324,8 +325,8 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
       if (g < 2) {
         const float e = wE[(s * 16 + j) * 2 + g];
         const float u = sU[2 * t + g];
-        b1v = fminf(fmaxf(u + e, lo_g), hi_g);
-        Sacc.add(gcs_g * (u * e));   // the control-cost term, one component per lane
+        b1v = fminf(fmaxf(zm ? e : u + e, lo_g), hi_g);
+        Sacc.add(gcs_g * (u * (zm ? e - u : e)));   // the control-cost term, one component per lane
       } else {
         b1v = g == 2 ? 1.0f : 0.0f;
       }
@@ -498,12 +499,18 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
 #pragma unroll
   for (int m = 8; m >= 1; m >>= 1) esum += __shfl_xor(esum, m, 16);
   if (lane == 0) scratch[4 + wv] = esum;
-  // N[t] = sum_k e_k eps_{k,t}: lane group g regenerates steps t = g, g + 4, ... of its
+  // N[t] = sum_k e_k delta_{k,t}: lane group g regenerates steps t = g, g + 4, ... of its
   // sample and the 16 samples of a row are summed with shuffles
   for (int t0 = 0; t0 < T; t0 += 4) {
     const int t = t0 + g;
     float e0 = 0.0f, e1 = 0.0f;
-    if (t < T && valid) draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+    if (t < T && valid) {
+      draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+      if (zm) {
+        e0 -= sU[2 * t];
+        e1 -= sU[2 * t + 1];
+      }
+    }
     float n0 = e * e0, n1 = e * e1;
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) {

@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   const int slot = wv * 2 + half;
   const int k = blockIdx.x * kWaveSlots + slot;
   const bool valid = k < a.K;
+  const bool zm = k >= a.K_imp;   // exploration sample: v = eps, delta = eps - u
   float* myE = sE + slot * eStride;
   float4* myX = reinterpret_cast<float4*>(sX + slot * T4 * 4);
 
@@ -138,8 +139,8 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     const int tn = min(t + 1, T - 1);
     const float2 u_next = *reinterpret_cast<const float2*>(sU + 2 * tn);
     const float2 e_next = *reinterpret_cast<const float2*>(myE + 2 * tn);
-    const float vc0 = fminf(fmaxf(u.x + e.x, a.u_lo0), a.u_hi0);
-    const float vc1 = fminf(fmaxf(u.y + e.y, a.u_lo1), a.u_hi1);
+    const float vc0 = fminf(fmaxf(zm ? e.x : u.x + e.x, a.u_lo0), a.u_hi0);
+    const float vc1 = fminf(fmaxf(zm ? e.y : u.y + e.y, a.u_lo1), a.u_hi1);
     // layer 1
     float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
     acc1 = __builtin_fmaf(w1[5], vc1, acc1);
@@ -332,7 +333,10 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
         cp[3] = xn.x; cp[4] = xn.y; cp[5] = xn.z; cp[6] = xn.w;
       }
       Sacc.add(state_cost_h(a.cost, bilerp(mv[q], fxv[q], fyv[q]), dec[q], xn.y, xn.z));
-      Sacc.add(a.gcs0 * (sU[2 * t] * myE[2 * t]) + a.gcs1 * (sU[2 * t + 1] * myE[2 * t + 1]));
+      const float u0 = sU[2 * t], u1 = sU[2 * t + 1];
+      const float d0 = zm ? myE[2 * t] - u0 : myE[2 * t];
+      const float d1 = zm ? myE[2 * t + 1] - u1 : myE[2 * t + 1];
+      Sacc.add(a.gcs0 * (u0 * d0) + a.gcs1 * (u1 * d1));
       ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1[q]) && finite_f(xn.x) &&
            finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
     }
@@ -359,7 +363,10 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   for (int i = 0; i < NQ; ++i) {
     if (i < NT) {
       const int t = 32 * i + c32;
-      const float n0 = e * ea[i], n1 = e * eb[i];
+      const int tc = min(t, T - 1);
+      const float d0 = zm ? ea[i] - sU[2 * tc] : ea[i];
+      const float d1 = zm ? eb[i] - sU[2 * tc + 1] : eb[i];
+      const float n0 = e * d0, n1 = e * d1;
       const float p0 = n0 + __shfl_xor(n0, 32, 64);
       const float p1 = n1 + __shfl_xor(n1, 32, 64);
       if (half == 0 && t < T) {

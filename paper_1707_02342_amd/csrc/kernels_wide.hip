@@ -91,6 +91,7 @@ __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a)
   const int h = l >> 5;
   const int k = blockIdx.x * kWideSlots + wv;
   const bool valid = k < a.K;
+  const bool zm = k >= a.K_imp;   // exploration sample: v = eps, delta = eps - u
   float* myE = sE + wv * eStride;
   float4* myX = reinterpret_cast<float4*>(sX + wv * T4 * 4);
 
@@ -164,8 +165,8 @@ __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a)
       const int tn = min(t + 1, T - 1);
       const float2 u_next = *reinterpret_cast<const float2*>(sU + 2 * tn);
       const float2 e_next = *reinterpret_cast<const float2*>(myE + 2 * tn);
-      const float vc0 = fminf(fmaxf(u.x + e.x, a.u_lo0), a.u_hi0);
-      const float vc1 = fminf(fmaxf(u.y + e.y, a.u_lo1), a.u_hi1);
+      const float vc0 = fminf(fmaxf(zm ? e.x : u.x + e.x, a.u_lo0), a.u_hi0);
+      const float vc1 = fminf(fmaxf(zm ? e.y : u.y + e.y, a.u_lo1), a.u_hi1);
       // layer 1
       float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
       acc1 = __builtin_fmaf(w1[5], vc1, acc1);
@@ -317,7 +318,10 @@ __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a)
       const float4 xn = myX[t + 1];
       const float px1 = pxh[q] + pxl[q], py1 = pyh[q] + pyl[q];
       Sacc.add(state_cost_h(a.cost, bilerp(mv[q], fxv[q], fyv[q]), dec[q], xn.y, xn.z));
-      Sacc.add(a.gcs0 * (sU[2 * t] * myE[2 * t]) + a.gcs1 * (sU[2 * t + 1] * myE[2 * t + 1]));
+      const float u0 = sU[2 * t], u1 = sU[2 * t + 1];
+      const float d0 = zm ? myE[2 * t] - u0 : myE[2 * t];
+      const float d1 = zm ? myE[2 * t + 1] - u1 : myE[2 * t + 1];
+      Sacc.add(a.gcs0 * (u0 * d0) + a.gcs1 * (u1 * d1));
       ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1[q]) && finite_f(xn.x) &&
            finite_f(xn.y) && finite_f(xn.z) && finite_f(xn.w);
     }
@@ -343,8 +347,10 @@ __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a)
   for (int i = 0; i < NQ; ++i) {
     const int t = 64 * i + l;
     if (i < NT && t < T) {
-      red[wv * eStride + 2 * t] = e * ea[i];
-      red[wv * eStride + 2 * t + 1] = e * eb[i];
+      const float d0 = zm ? ea[i] - sU[2 * t] : ea[i];
+      const float d1 = zm ? eb[i] - sU[2 * t + 1] : eb[i];
+      red[wv * eStride + 2 * t] = e * d0;
+      red[wv * eStride + 2 * t + 1] = e * d1;
     }
   }
   __syncthreads();

@@ -158,7 +158,16 @@ mppi_status validate_config(const mppi_config* c) {
   if (c->precision != MPPI_PREC_FP32 && c->precision != MPPI_PREC_BF16 && c->precision != MPPI_PREC_FP16)
     return fail(nullptr, MPPI_E_INVAL, "unknown precision %d", c->precision);
   if (!sched_ok(c->schedule)) return fail(nullptr, MPPI_E_INVAL, "unknown schedule %d", c->schedule);
+  if (!(c->explore >= 0.0f && c->explore <= 1.0f))
+    return fail(nullptr, MPPI_E_INVAL, "explore must be in [0, 1]");
   return MPPI_OK;
+}
+
+// Algorithm 1 draws sample k around U while k < (1 - alpha) K: the first
+// ceil((1 - alpha) K) samples (evaluated in FP64); the rest are drawn around zero.
+int importance_samples(int K, float explore) {
+  const double n = std::ceil((1.0 - (double)explore) * (double)K);
+  return (int)std::min<double>(std::max<double>(n, 0.0), (double)K);
 }
 
 mppi_status validate_cost(const mppi_cost* c) {
@@ -303,6 +312,7 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
   a.K = c->cfg.K;
   a.T = c->cfg.T;
+  a.K_imp = importance_samples(c->cfg.K, c->cfg.explore);
   a.dt = c->cfg.dt;
   a.inv_lambda = 1.0f / c->cfg.lambda;
   a.gcs0 = c->cfg.gamma / c->cfg.sigma2[0];
@@ -828,6 +838,8 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
     if (ckpt_every < 1 || ckpt_every > 16) return fail(c, MPPI_E_INVAL, "ckpt_every=%d outside [1, 16]", ckpt_every);
     if (!c->have_map || !c->have_dyn) return fail(c, MPPI_E_STATE, "set the cost map and the dynamics first");
     if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "the objective gradient supports h = 32 only");
+    if (c->cfg.explore != 0.0f)
+      return fail(c, MPPI_E_INVAL, "the objective is defined for importance samples only (explore = 0)");
     HIP_TRY(c, hipSetDevice(c->device));
     const int K = c->cfg.K, T = c->cfg.T;
     const int n_ckpt = T / ckpt_every + 1;
@@ -1022,6 +1034,7 @@ std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
     a.ckpt_every = 1;
     a.K = b->K[i];
     a.T = b->T[i];
+    a.K_imp = importance_samples(b->K[i], b->cfg.explore);
     a.dt = b->cfg.dt;
     a.inv_lambda = 1.0f / b->cfg.lambda;
     a.gcs0 = b->cfg.gamma / b->cfg.sigma2[0];

@@ -68,6 +68,8 @@ struct RolloutArgs {
   int ckpt_every;
   float x0[kStateDim];
   int K, T;
+  int K_imp;               // samples k < K_imp are drawn around U (v = u + eps); the rest
+                           // are exploration samples around zero (v = eps)
   float dt;
   float inv_lambda;
   float gcs0, gcs1;        // gamma / Sigma_ii (control-cost weights)

@@ -42,7 +42,7 @@ class mppi_config(C.Structure):
                 ("gamma", C.c_float), ("sigma2", C.c_float * 2), ("u_lo", C.c_float * 2),
                 ("u_hi", C.c_float * 2), ("sg_window", C.c_int32), ("sg_order", C.c_int32),
                 ("precision", C.c_int32), ("schedule", C.c_int32), ("seed", C.c_uint64),
-                ("instance", C.c_uint32)]
+                ("instance", C.c_uint32), ("explore", C.c_float)]
 
 
 class mppi_cost(C.Structure):
@@ -411,6 +411,7 @@ def make_config(prob, precision: int = MPPI_PREC_FP32, schedule: int = MPPI_SCHE
     c.precision, c.schedule = precision, schedule
     c.seed = int(prob.seed)
     c.instance = int(getattr(prob, "instance", 0))
+    c.explore = float(getattr(prob, "explore", 0.0))
     return c
 
 

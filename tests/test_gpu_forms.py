@@ -132,10 +132,10 @@ def test_precision_form_h32_matches_fp32_closely(M, orc):
 # Batched form
 # ---------------------------------------------------------------------------
 
-def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None, schedule=4):
+def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None, schedule=4, base=None):
     """The batch (tiles of the given schedule; AUTO means quad) against single-problem
     contexts running the same schedule."""
-    base = synth.c2_problem(seed=7)
+    base = synth.c2_problem(seed=7) if base is None else base
     cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
     with M.Batch(base, Ks, Ts, cmap, params, schedule=schedule) as b:
         for _ in range(n_iter):
@@ -165,6 +165,19 @@ def test_batch_matches_single_contexts(M, schedule):
     x0s = np.stack([synth.ellipse_pose(float(p), float(v)) for p, v in
                     zip(rng.uniform(0, 2 * np.pi, n), rng.uniform(2, 10, n))])
     _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, schedule=schedule)
+
+
+@pytest.mark.parametrize("schedule", [1, 4])
+def test_batch_exploration_matches_single_contexts(M, schedule):
+    """Exploration samples in the batched form: each instance draws its last
+    K_i - ceil((1 - alpha) K_i) samples around zero, as a single context does."""
+    rng = np.random.default_rng(1)
+    n = 12
+    Ks = rng.choice([256, 300, 1000], size=n)
+    Ts = rng.choice([20, 50], size=n)
+    x0s = np.stack([synth.ellipse_pose(float(p), 6.0) for p in rng.uniform(0, 2 * np.pi, n)])
+    _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, schedule=schedule,
+                     base=synth.explore_problem(seed=7, explore=0.05))
 
 
 def test_batch_full_size_spot_checks(M, orc):

@@ -78,16 +78,26 @@ def test_noise_full_size_bit_identical(M, orc):
 # One iteration
 # ---------------------------------------------------------------------------
 
+def deltas(prob, eps, U0):
+    """delta_{k,t} = v_{k,t} - u_t: eps for samples k < (1 - alpha) K (Algorithm 1's
+    importance samples), eps - u_t for the exploration samples after them."""
+    d = eps.astype(np.float64).copy()
+    alpha = float(np.float32(getattr(prob, "explore", 0.0)))
+    zero_mean = ~(np.arange(d.shape[0]) < (1.0 - alpha) * d.shape[0])
+    d[zero_mean] -= U0.astype(np.float64)[None]
+    return d
+
+
 def e2e_explained(orc, prob, S_gpu, S_ref, eps, U0, U_gpu, margin=None):
     """End-to-end control difference and its first-order prediction from the cost
-    differences dS: d(Delta_t) = -(1/lambda) sum_k w_k (eps_kt - Delta_t)(dS_k - sum_j w_j dS_j),
+    differences dS: d(Delta_t) = -(1/lambda) sum_k w_k (delta_kt - Delta_t)(dS_k - sum_j w_j dS_j),
     smoothed by the SG matrix.  Returns (max|dU|, max|dU - dU_pred|, max|dU_pred|)."""
     S_r = S_ref.copy()
     if margin is not None:
         near = margin < 1e-4
         S_r[near] = S_gpu[near]
     st, w, rho, eta = orc.weights(S_r, prob.lam)
-    e64 = eps.astype(np.float64)
+    e64 = deltas(prob, eps, U0)
     delta = np.tensordot(w, e64, axes=(0, 0))
     Mx = orc.sgf_matrix(prob.T, prob.sg_window, prob.sg_order)
     U_ref = U0.astype(np.float64) + Mx @ delta
@@ -127,7 +137,7 @@ def _check_iteration(M, orc, prob, cmap, params, x0, U0, schedule, it=0, impulse
     assert err.max() <= COST_RTOL, f"S_{worst}: gpu {S[worst]} ref {ref.S[worst]} rel {err.max():.3e}"
     # stage-isolated: oracle weights + update on the GPU's S and the same eps
     st2, w, rho, eta = orc.weights(S.astype(np.float64), prob.lam)
-    delta = np.tensordot(w, eps.astype(np.float64), axes=(0, 0))
+    delta = np.tensordot(w, deltas(prob, eps, U0), axes=(0, 0))
     Mx = orc.sgf_matrix(prob.T, prob.sg_window, prob.sg_order)
     U_iso = U0.astype(np.float64) + Mx @ delta
     e_iso = np.abs(Ug - U_iso).max()
@@ -207,6 +217,55 @@ def test_hidden64_fp32(M, orc, schedule):
     prob = synth.with_(synth.c3_problem(K=1024), T=40)
     _check_iteration(M, orc, prob, synth.ring_map(), synth.mlp_params(64, 0), synth.C1_X0,
                      synth.random_controls(40, 9), schedule)
+
+
+# ---------------------------------------------------------------------------
+# Exploration samples (zero-mean samples k >= (1 - alpha) K) and decoupled gamma
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("schedule", _schedules())
+@pytest.mark.parametrize("seed", [0, 1])
+def test_exploration_paper_parameters(M, orc, schedule, seed):
+    """The parameter table's lambda = 12.5, gamma = 0.1, Sigma = Diag(0.0306, 0.0506) with
+    alpha = 0.01 (19 of 1920 samples around zero) on the paper-shaped workload; the
+    boundary sample 1901 falls inside a block and a sample group of every schedule."""
+    prob = synth.explore_problem(seed)
+    _say("explore paper", schedule, seed)
+    _check_iteration(M, orc, prob, synth.ellipse_map(), synth.mlp_params(32, 0), synth.C2_X0,
+                     synth.random_controls(100, 20 + seed, scale=0.2), schedule, it=seed,
+                     impulses=True)
+
+
+@pytest.mark.parametrize("schedule", _schedules())
+@pytest.mark.parametrize("K,T,alpha", [(257, 33, 0.25), (100, 20, 1.0), (65, 7, 0.5 / 65),
+                                       (4100, 12, 0.3)])
+def test_exploration_fractions(M, orc, schedule, K, T, alpha):
+    prob = synth.with_(synth.c1_problem(seed=K), K=K, T=T, gamma=0.5, explore=alpha)
+    _say("explore", schedule, K, T, alpha)
+    _check_iteration(M, orc, prob, synth.ring_map(), synth.mlp_params(32, 0), synth.C1_X0,
+                     synth.random_controls(T, 3, scale=0.5), schedule)
+
+
+@pytest.mark.parametrize("schedule", [1, 4])
+def test_exploration_hidden64(M, orc, schedule):
+    """h = 64 FP32 on the lane and quad schedules with exploration samples."""
+    prob = synth.with_(synth.c3_problem(K=1024), T=40, gamma=0.3, explore=0.05)
+    _check_iteration(M, orc, prob, synth.ring_map(), synth.mlp_params(64, 0), synth.C1_X0,
+                     synth.random_controls(40, 9), schedule)
+
+
+def test_exploration_rejected_outside_unit_interval(M):
+    for alpha in (-0.1, 1.5, float("nan")):
+        prob = synth.with_(synth.c1_problem(), explore=alpha)
+        with pytest.raises(M.MppiError):
+            M.Controller(prob, synth.ring_map(), synth.mlp_params(32, 0))
+
+
+def test_objective_rejects_exploration(M):
+    prob = synth.with_(synth.c5_problem(), K=256, T=20, explore=0.1)
+    with M.Controller(prob, synth.ring_map(), synth.mlp_params(32, 0)) as c:
+        with pytest.raises(M.MppiError):
+            c.objective(synth.C1_X0, 0)
 
 
 # ---------------------------------------------------------------------------
