@@ -23,6 +23,7 @@ SRC = HERE / "oracle.cpp"
 LIB = HERE / "liboracle.so"
 
 OK, E_INVAL, E_NONFINITE = 0, 1, 5
+WEIGHTS_IT, WEIGHTS_CEM = 0, 1
 
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
             "-pthread", "-Wall", "-Wextra"]
@@ -50,7 +51,7 @@ class Problem(C.Structure):
         ("origin_x", C.c_float), ("origin_y", C.c_float), ("resolution", C.c_float),
         ("map", C.POINTER(C.c_float)), ("params", C.POINTER(C.c_float)),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("explore", C.c_float),
-        ("nthreads", C.c_int32),
+        ("weighting", C.c_int32), ("elite", C.c_float), ("nthreads", C.c_int32),
     ]
 
 
@@ -75,6 +76,10 @@ def lib():
         L.orc_rollout_f64.argtypes = [pp, fp, fp, fp, dp, dp]
         L.orc_rollout_f32.argtypes = [pp, fp, fp, fp, fp, fp]
         L.orc_weights.argtypes = [C.c_int, dp, C.c_double, dp, dp, dp]
+        L.orc_cem_zeta.argtypes = [C.c_int, C.c_float]
+        L.orc_cem_zeta.restype = C.c_int
+        L.orc_weights_cem.argtypes = [C.c_int, dp, C.c_int, dp, dp, dp]
+        L.orc_weights_cem.restype = C.c_int
         L.orc_sgf_matrix.argtypes = [C.c_int, C.c_int, C.c_int, dp]
         L.orc_iterate.argtypes = [pp, fp, fp, C.c_uint32, fp, dp, dp, dp, dp, dp]
         L.orc_shift.argtypes = [C.c_int, dp, dp, dp]
@@ -140,6 +145,8 @@ class OracleProblem:
         s.seed = int(prob.seed)
         s.instance = int(getattr(prob, "instance", 0))
         s.explore = float(getattr(prob, "explore", 0.0))
+        s.weighting = int(getattr(prob, "weighting", WEIGHTS_IT))
+        s.elite = float(getattr(prob, "elite", 0.8))
         s.nthreads = int(nthreads or min(16, os.cpu_count() or 1))
         self.s = s
 
@@ -206,6 +213,22 @@ def weights(S, lam: float):
     st = lib().orc_weights(S.size, _ptr(S, C.c_double), float(lam), _ptr(w, C.c_double),
                            C.byref(rho), C.byref(eta))
     return st, w, rho.value, eta.value
+
+
+def cem_zeta(K: int, elite: float) -> int:
+    return int(lib().orc_cem_zeta(int(K), float(elite)))
+
+
+def weights_cem(S, zeta: int):
+    """Algorithm 3: (status, w, largest elite cost, elite count)."""
+    S = _f64(S)
+    w = np.zeros_like(S)
+    z, n = C.c_double(), C.c_double()
+    st = lib().orc_weights_cem(S.size, _ptr(S, C.c_double), int(zeta), _ptr(w, C.c_double),
+                               C.byref(z), C.byref(n))
+    if st == E_INVAL:
+        raise ValueError("oracle: invalid CEM arguments")
+    return st, w, z.value, int(n.value)
 
 
 def sgf_matrix(T: int, window: int, order: int) -> np.ndarray:

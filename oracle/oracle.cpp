@@ -59,10 +59,13 @@ typedef struct {
   uint64_t seed;
   uint32_t instance;
   float explore;            // exploration fraction alpha of Algorithm 1 (0 = none)
+  int32_t weighting;        // ORC_WEIGHTS_IT (Algorithm 2) or ORC_WEIGHTS_CEM (Algorithm 3)
+  float elite;              // Algorithm 3's eliteness threshold delta, in [0, 1)
   int32_t nthreads;
 } orc_problem;
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NONFINITE = 5 };
+enum { ORC_WEIGHTS_IT = 0, ORC_WEIGHTS_CEM = 1 };
 
 }  // extern "C"
 
@@ -424,6 +427,35 @@ int weights(int K, const double* S, double lambda, double* w, double* rho_out, d
   return ORC_OK;
 }
 
+// Algorithm 3 (cross-entropy weights).  zeta = round(K (1 - delta)), rounded half away
+// from zero in FP64 from the FP32 delta.  The elite set is read as the zeta samples of
+// lowest cost -- the unweighted average over the best samples that Section V describes,
+// and the elite set of its enumerated procedure (cost <= the zeta-th cost); taken
+// literally, the strict comparison with the zeta-th cost would keep zeta - 1 samples
+// with weights summing to (zeta - 1)/zeta.  Samples are ordered by (S_k, k), so equal
+// costs go to the lower index; non-finite costs are never elite.  With n finite costs
+// the elite set is the first min(zeta, n) in that order and every elite sample weighs
+// 1/|E|.  z_out = the largest elite cost, n_out = |E|.
+int cem_zeta(int K, float delta) {
+  return (int)std::round((double)K * (1.0 - (double)delta));
+}
+
+int weights_cem(int K, const double* S, int zeta, double* w, double* z_out, double* n_out) {
+  std::vector<int> idx;
+  for (int k = 0; k < K; ++k) if (std::isfinite(S[k])) idx.push_back(k);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return S[a] < S[b] || (S[a] == S[b] && a < b); });
+  const int n = std::min<int>(zeta, (int)idx.size());
+  for (int k = 0; k < K; ++k) w[k] = 0.0;
+  if (n_out) *n_out = (double)n;
+  if (n == 0) {
+    if (z_out) *z_out = std::numeric_limits<double>::infinity();
+    return ORC_E_NONFINITE;
+  }
+  for (int i = 0; i < n; ++i) w[idx[i]] = 1.0 / (double)n;
+  if (z_out) *z_out = S[idx[n - 1]];
+  return ORC_OK;
+}
+
 // Savitzky-Golay smoothing (Section III-D-4) as a [T][T] matrix: row t evaluates at
 // t the least-squares polynomial of degree `order` through the `window` points
 // centred on t, or through the first / last `window` points near the ends.
@@ -476,6 +508,9 @@ bool valid_problem(const orc_problem* p) {
   if (p->sg_order < 0 || p->sg_order >= p->sg_window) return false;
   if (!p->map || !p->params || p->H <= 0 || p->W <= 0 || !(p->resolution > 0)) return false;
   if (!(p->explore >= 0.0f && p->explore <= 1.0f)) return false;
+  if (p->weighting != ORC_WEIGHTS_IT && p->weighting != ORC_WEIGHTS_CEM) return false;
+  if (p->weighting == ORC_WEIGHTS_CEM &&
+      !(p->elite >= 0.0f && p->elite < 1.0f && cem_zeta(p->K, p->elite) >= 1)) return false;
   return true;
 }
 
@@ -513,9 +548,17 @@ int orc_weights(int K, const double* S, double lambda, double* w, double* rho, d
   return weights(K, S, lambda, w, rho, eta);
 }
 
+int orc_cem_zeta(int K, float delta) { return cem_zeta(K, delta); }
+
+int orc_weights_cem(int K, const double* S, int zeta, double* w, double* z, double* n) {
+  if (K < 1 || zeta < 1) return ORC_E_INVAL;
+  return weights_cem(K, S, zeta, w, z, n);
+}
+
 void orc_sgf_matrix(int T, int window, int order, double* M) { sgf_matrix(T, window, order, M); }
 
-// One iteration of Algorithm 1 (without the shift): noise, rollouts, weights,
+// One iteration of Algorithm 1 (without the shift): noise, rollouts, weights
+// (Algorithm 2, or Algorithm 3 for the cross-entropy variant),
 // Delta_t = sum_k w_k delta_{k,t}, U_out = U + SGF * Delta, where delta_{k,t} =
 // v_{k,t} - u_t is eps_{k,t} for importance samples and eps_{k,t} - u_t for
 // exploration samples.  (Algorithm 1 writes the sum with E^k for every sample; with
@@ -535,7 +578,9 @@ int orc_iterate(const orc_problem* p, const float* x0, const float* U, uint32_t 
   std::vector<double> S(K), w(K), delta((size_t)T * 2, 0.0), M((size_t)T * T);
   rollout_all(P, p->nthreads, x0, U, eps, S.data(), (double*)nullptr);
   double rho = 0, eta = 0;
-  const int st = weights(K, S.data(), (double)p->lambda, w.data(), &rho, &eta);
+  const int st = p->weighting == ORC_WEIGHTS_CEM
+                     ? weights_cem(K, S.data(), cem_zeta(K, p->elite), w.data(), &rho, &eta)
+                     : weights(K, S.data(), (double)p->lambda, w.data(), &rho, &eta);
   if (S_out) std::copy(S.begin(), S.end(), S_out);
   if (w_out) std::copy(w.begin(), w.end(), w_out);
   if (rho_eta_out) { rho_eta_out[0] = rho; rho_eta_out[1] = eta; }
@@ -579,11 +624,12 @@ void orc_plant_step(const orc_problem* p, const double* x, const double* u, doub
 //   = rho - lambda log(eta~/K)            (Eq. FreeEnergy with the Monte-Carlo
 // estimate over the K samples of this iteration's noise), evaluated at FP64
 // nominal controls U and FP64 network parameters (nullable: use the problem's).
-// Defined for importance samples only (exploration fraction 0; otherwise INVAL).
+// Defined for importance samples and Algorithm 2's weights only (otherwise INVAL).
 int orc_objective(const orc_problem* p, const float* x0, const double* U, const double* params,
                   uint32_t iter, double* J, double* S_out) {
   if (!valid_problem(p)) return ORC_E_INVAL;
-  if (p->explore != 0.0f) return ORC_E_INVAL;   // defined for importance samples only
+  // defined for importance samples and the information-theoretic weights only
+  if (p->explore != 0.0f || p->weighting != ORC_WEIGHTS_IT) return ORC_E_INVAL;
   const int K = p->K, T = p->T;
   std::vector<float> eps((size_t)K * T * 2);
   noise_all(p, iter, eps.data());
@@ -624,7 +670,7 @@ int orc_objective(const orc_problem* p, const float* x0, const double* U, const 
 int orc_objective_grad(const orc_problem* p, const float* x0, const double* U, const double* params,
                        uint32_t iter, double* J, double* dJdU, double* dJdtheta) {
   if (!valid_problem(p)) return ORC_E_INVAL;
-  if (p->explore != 0.0f) return ORC_E_INVAL;
+  if (p->explore != 0.0f || p->weighting != ORC_WEIGHTS_IT) return ORC_E_INVAL;
   const int K = p->K, T = p->T, h = p->hidden;
   std::vector<float> eps((size_t)K * T * 2);
   noise_all(p, iter, eps.data());

@@ -231,6 +231,8 @@ class Problem:
     seed: int = 0
     instance: int = 0
     explore: float = 0.0                 # fraction of zero-mean (exploration) samples
+    weighting: int = 0                   # 0: Algorithm 2 (information theoretic), 1: Algorithm 3 (CEM)
+    elite: float = 0.8                   # Algorithm 3's eliteness threshold (percentile)
     cost: CostParams = field(default_factory=CostParams)
 
     @property
@@ -286,6 +288,12 @@ def explore_problem(seed: int = 0, K: int = 1920, explore: float = 0.01) -> Prob
     alpha=0.01 of zero-mean samples."""
     return Problem(K=K, T=100, hidden=32, dt=0.02, lam=12.5, gamma=0.1, sigma2=(0.0306, 0.0506),
                    sg_window=9, sg_order=2, seed=seed, explore=explore, cost=c2_cost())
+
+
+def cem_problem(seed: int = 0, K: int = 1920, elite: float = 0.8) -> Problem:
+    """Cross-entropy weights (Algorithm 3) on the parameter-table problem: the top
+    20 % of the samples (eliteness threshold 0.8), no exploration samples."""
+    return replace(explore_problem(seed, K=K, explore=0.0), weighting=1, elite=elite)
 
 
 def ellipse_pose(phi: float, v_x: float, center=(51.2, 51.2), semi_axes=(40.0, 25.0)) -> np.ndarray:
