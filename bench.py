@@ -182,7 +182,8 @@ def measure_forms(M, stream, iters: int = 30):
     differentiation: K=4096, T=100, free-energy objective plus its adjoint gradient
       with checkpoints every 10 steps;
     exploration: the paper-shaped receding-horizon step with the parameter table's
-      lambda, gamma and Sigma and 1 % of the samples drawn around zero."""
+      lambda, gamma and Sigma and 1 % of the samples drawn around zero;
+    cem: the same step with Algorithm 3's weights (the best 20 % averaged)."""
     import torch
     import synth
     out = {}
@@ -251,24 +252,30 @@ def measure_forms(M, stream, iters: int = 30):
     out["differentiation"] = {"ms_per_value_and_gradient": ms,
                               "workload": "K=4096, T=100, checkpoints every 10 steps, 1612 gradient entries"}
 
-    prob = synth.explore_problem(seed=0)
-    with M.Controller(prob, synth.ellipse_map(), synth.mlp_params(32, 0), stream=int(stream.cuda_stream)) as c:
-        M.mppi_run_receding(c.ctx, synth.C2_X0, 20)
-        torch.cuda.synchronize()
-        n_blk = 3
-        t0 = time.perf_counter()
-        for _ in range(n_blk):
-            M.mppi_run_receding(c.ctx, synth.C2_X0, 100)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / (100 * n_blk)
-        sched = c.schedule
-    st = prob.K * prob.T / (ms * 1e-3)
-    tf = st * NET_FLOP_PER_STEP[32] / 1e12
-    out["exploration"] = {"ms_per_step": ms, "steps_per_s": st, "schedule": sched,
-                          "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
-                                       "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS},
-                          "workload": "K=1920 (19 exploration samples), T=100, lambda=12.5, gamma=0.1, "
-                                      "Sigma=Diag(0.0306, 0.0506), receding horizon, 2048x2048 map"}
+    emap = synth.ellipse_map()
+    for name, prob, desc in (
+            ("exploration", synth.explore_problem(seed=0),
+             "K=1920 (19 exploration samples), T=100, lambda=12.5, gamma=0.1, Sigma=Diag(0.0306, 0.0506), "
+             "receding horizon, 2048x2048 map"),
+            ("cem", synth.cem_problem(seed=0),
+             "Algorithm 3 weights (384 elite of K=1920), T=100, gamma=0.1, Sigma=Diag(0.0306, 0.0506), "
+             "receding horizon, 2048x2048 map")):
+        with M.Controller(prob, emap, synth.mlp_params(32, 0), stream=int(stream.cuda_stream)) as c:
+            M.mppi_run_receding(c.ctx, synth.C2_X0, 20)
+            torch.cuda.synchronize()
+            n_blk = 3
+            t0 = time.perf_counter()
+            for _ in range(n_blk):
+                M.mppi_run_receding(c.ctx, synth.C2_X0, 100)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / (100 * n_blk)
+            sched = c.schedule
+        st = prob.K * prob.T / (ms * 1e-3)
+        tf = st * NET_FLOP_PER_STEP[32] / 1e12
+        out[name] = {"ms_per_step": ms, "steps_per_s": st, "schedule": sched,
+                     "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS},
+                     "workload": desc}
     return out
 
 

@@ -54,6 +54,12 @@ typedef enum {
 
 enum { MPPI_PREC_FP32 = 0, MPPI_PREC_BF16 = 1, MPPI_PREC_FP16 = 2 };
 
+/* Trajectory weights: Algorithm 2 (information theoretic, softmin at temperature
+ * lambda) or Algorithm 3 (cross entropy: the zeta = round(K (1 - elite)) samples of
+ * lowest cost weigh 1/zeta each, ties to the lower sample index, non-finite costs never
+ * elite; with fewer than zeta finite costs every finite sample weighs 1/their number). */
+enum { MPPI_WEIGHTS_IT = 0, MPPI_WEIGHTS_CEM = 1 };
+
 /* Kernel schedule for the rollout (0 = pick automatically).  LANE: one sample per
  * lane (any K; FP32, BF16 or FP16 network, h = 32 or 64; BF16/FP16 on the matrix
  * cores, 64 samples per instruction group).  WAVE: 32 lanes per sample, two samples per wavefront.  WIDE: 64 lanes (a
@@ -73,7 +79,8 @@ enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2, MPPI_SCHED
  * not finite and > 0; sigma2[i] not finite and > 0 (Sigma^-1 must exist); gamma not
  * finite; u_lo[i] > u_hi[i]; sg_window even, < 1 or > T; sg_order < 0 or
  * >= sg_window; precision not one of MPPI_PREC_*; schedule not one of MPPI_SCHED_*;
- * explore not in [0, 1].
+ * explore not in [0, 1]; weighting not one of MPPI_WEIGHTS_*; with MPPI_WEIGHTS_CEM,
+ * elite not in [0, 1) or round(K (1 - elite)) < 1 (computed in FP64 from the FP32 value).
  * Exploration samples (Algorithm 1's alpha and the disturbance discussion of
  * Section IV): sample k is drawn around zero when k >= ceil((1 - explore) K).  For every
  * sample delta_t = v_t - u_t enters the running cost as gamma u_t^T Sigma^-1 delta_t
@@ -98,6 +105,8 @@ typedef struct {
   float explore;        /* alpha of Algorithm 1: samples k >= ceil((1 - alpha) K)
                            are drawn around zero (v = eps) instead of around U;
                            0 = every sample around U                              */
+  int32_t weighting;    /* MPPI_WEIGHTS_*                                          */
+  float elite;          /* Algorithm 3's eliteness threshold (0.8: the best 20 %)  */
 } mppi_config;
 
 /* State cost c(x, t) at the post-step state x_t, t = 1..T (Section VI-C):
@@ -184,7 +193,8 @@ mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
 
 /* Diagnostics of the most recent iteration (synchronises): rho = min_k S_k,
  * eta~ = sum_k exp(-(S_k - rho)/lambda), and the unsmoothed update
- * Delta_t = sum_k w_k eps_{k,t} ([T][2]).  Any output pointer may be NULL. */
+ * Delta_t = sum_k w_k delta_{k,t} ([T][2]).  With MPPI_WEIGHTS_CEM, rho is the largest
+ * elite cost and eta the number of elite samples.  Any output pointer may be NULL. */
 mppi_status mppi_get_stats(mppi_ctx* ctx, float* rho, float* eta, float* delta_out);
 
 /* The perturbations eps ([K][T][2]) that the device generator draws for
@@ -221,8 +231,9 @@ mppi_status mppi_get_timing_samples(mppi_ctx* ctx, float* ms_out, int32_t cap, i
  * counter is not advanced and U is not changed).  The forward pass stores every
  * sample's full state each `ckpt_every` steps (1..16) for the backward pass.
  * Synchronises.  J_out and costs_out ([K]) may be NULL.  Requires h = 32.
- * INVAL: ckpt_every outside [1, 16], h != 32 or explore != 0 (the objective is
- * defined over importance samples only).  NONFINITE: no finite cost. */
+ * INVAL: ckpt_every outside [1, 16], h != 32, explore != 0 or MPPI_WEIGHTS_CEM (the
+ * objective is defined over importance samples and Algorithm 2's weights only).
+ * NONFINITE: no finite cost. */
 mppi_status mppi_objective(mppi_ctx* ctx, const float x0[7], uint32_t iter, int32_t ckpt_every,
                            double* J_out, float* costs_out);
 

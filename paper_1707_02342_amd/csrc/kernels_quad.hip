@@ -484,7 +484,26 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   all4(ok ? 1.0f : 0.0f, okv);
   const bool okc = okv[0] != 0.0f && okv[1] != 0.0f && okv[2] != 0.0f && okv[3] != 0.0f;
   if (!valid || !okc || !finite_f(S)) S = kInf;
-  if (valid && g == 0) store_through(a.S + k, S);   // read by the host only; kept out of L2
+  if (valid && g == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's merge
+
+  if (a.cem_zeta > 0) {
+    // Algorithm 3: the sample's delta row (lane group g regenerates steps g, g + 4, ...)
+    if (valid) {
+      float* drow = a.D + (size_t)k * 2 * T;
+      for (int t = g; t < T; t += 4) {
+        float e0, e1;
+        draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+        if (zm) {
+          e0 -= sU[2 * t];
+          e1 -= sU[2 * t + 1];
+        }
+        store_through(drow + 2 * t, e0);
+        store_through(drow + 2 * t + 1, e1);
+      }
+    }
+    finish_iteration_cem<kQuadBlock>(a, red);
+    return;
+  }
 
   // ---- the block's softmin partial ----------------------------------------------------
   float* scratch = red + kQuadWaves * 2 * kTMax;   // [8]

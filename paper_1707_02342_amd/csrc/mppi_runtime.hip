@@ -76,6 +76,7 @@ struct mppi_ctx {
   float* d_params = nullptr;
   float* d_decay = nullptr;
   float* d_S = nullptr;
+  float* d_D = nullptr;      // Algorithm 3 only: [K][T][2] delta rows
   float* d_part = nullptr;
   float* d_part2 = nullptr;
   unsigned* d_cnt = nullptr;
@@ -138,6 +139,11 @@ int sched_ok(int s) {
 // The schedules that spread one sample over several lanes (FP32, h = 32 only).
 bool multi_lane(int s) { return s == MPPI_SCHED_WAVE || s == MPPI_SCHED_WIDE; }
 
+// Algorithm 3's zeta = round(K (1 - delta)), half away from zero, in FP64.
+int cem_elite_count(int K, float elite) {
+  return (int)std::round((double)K * (1.0 - (double)elite));
+}
+
 mppi_status validate_config(const mppi_config* c) {
   if (!c) return fail(nullptr, MPPI_E_INVAL, "config is NULL");
   if (c->K < 1 || c->K > kMaxK) return fail(nullptr, MPPI_E_INVAL, "K=%d outside [1, %d]", c->K, kMaxK);
@@ -160,6 +166,13 @@ mppi_status validate_config(const mppi_config* c) {
   if (!sched_ok(c->schedule)) return fail(nullptr, MPPI_E_INVAL, "unknown schedule %d", c->schedule);
   if (!(c->explore >= 0.0f && c->explore <= 1.0f))
     return fail(nullptr, MPPI_E_INVAL, "explore must be in [0, 1]");
+  if (c->weighting != MPPI_WEIGHTS_IT && c->weighting != MPPI_WEIGHTS_CEM)
+    return fail(nullptr, MPPI_E_INVAL, "unknown weighting %d", c->weighting);
+  if (c->weighting == MPPI_WEIGHTS_CEM) {
+    if (!(c->elite >= 0.0f && c->elite < 1.0f)) return fail(nullptr, MPPI_E_INVAL, "elite must be in [0, 1)");
+    if (cem_elite_count(c->K, c->elite) < 1)
+      return fail(nullptr, MPPI_E_INVAL, "round(K (1 - elite)) must be at least 1");
+  }
   return MPPI_OK;
 }
 
@@ -313,6 +326,8 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   a.K = c->cfg.K;
   a.T = c->cfg.T;
   a.K_imp = importance_samples(c->cfg.K, c->cfg.explore);
+  a.cem_zeta = c->cfg.weighting == MPPI_WEIGHTS_CEM ? cem_elite_count(c->cfg.K, c->cfg.elite) : 0;
+  a.D = c->d_D;
   a.dt = c->cfg.dt;
   a.inv_lambda = 1.0f / c->cfg.lambda;
   a.gcs0 = c->cfg.gamma / c->cfg.sigma2[0];
@@ -429,7 +444,7 @@ mppi_status launch_plant(mppi_ctx* c, const float* x_in_dev, const float* u_dev,
 }
 
 void free_all(mppi_ctx* c) {
-  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_part, &c->d_part2,
+  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_D, &c->d_part, &c->d_part2,
                     &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x,
                     &c->d_ckpt, &c->d_gpart, &c->d_gout, &c->d_gred};
   for (float** b : bufs) {
@@ -489,6 +504,7 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMalloc(&c->d_U, sizeof(float) * 2 * T));
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
+    if (cfg->weighting == MPPI_WEIGHTS_CEM) HIP_TRY(c, hipMalloc(&c->d_D, sizeof(float) * (size_t)K * 2 * T));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
     const int ngrp_cap = std::max({merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WAVE)),
@@ -840,6 +856,8 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
     if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "the objective gradient supports h = 32 only");
     if (c->cfg.explore != 0.0f)
       return fail(c, MPPI_E_INVAL, "the objective is defined for importance samples only (explore = 0)");
+    if (c->cfg.weighting != MPPI_WEIGHTS_IT)
+      return fail(c, MPPI_E_INVAL, "the objective is defined for Algorithm 2's weights only");
     HIP_TRY(c, hipSetDevice(c->device));
     const int K = c->cfg.K, T = c->cfg.T;
     const int n_ckpt = T / ckpt_every + 1;
@@ -1035,6 +1053,8 @@ std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
     a.K = b->K[i];
     a.T = b->T[i];
     a.K_imp = importance_samples(b->K[i], b->cfg.explore);
+    a.cem_zeta = 0;
+    a.D = nullptr;
     a.dt = b->cfg.dt;
     a.inv_lambda = 1.0f / b->cfg.lambda;
     a.gcs0 = b->cfg.gamma / b->cfg.sigma2[0];
@@ -1203,6 +1223,8 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     sgmax = std::max(sgmax, T[i] * cfg->sg_window);
   }
   if (cfg->precision != MPPI_PREC_FP32) return bfail(nullptr, MPPI_E_INVAL, "the batched form runs the FP32 network");
+  if (cfg->weighting != MPPI_WEIGHTS_IT)
+    return bfail(nullptr, MPPI_E_INVAL, "the batched form uses Algorithm 2's weights");
   if (cfg->schedule != MPPI_SCHED_AUTO && cfg->schedule != MPPI_SCHED_LANE && cfg->schedule != MPPI_SCHED_QUAD)
     return bfail(nullptr, MPPI_E_INVAL, "the batched form runs the lane or quad schedule");
   mppi_status st = validate_cost(cost);

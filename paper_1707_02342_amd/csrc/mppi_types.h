@@ -70,6 +70,8 @@ struct RolloutArgs {
   int K, T;
   int K_imp;               // samples k < K_imp are drawn around U (v = u + eps); the rest
                            // are exploration samples around zero (v = eps)
+  int cem_zeta;            // 0: Algorithm 2's weights; > 0: Algorithm 3 with this many elite samples
+  float* D;                // Algorithm 3 only: [K][T][2] delta rows (v - u) of every sample
   float dt;
   float inv_lambda;
   float gcs0, gcs1;        // gamma / Sigma_ii (control-cost weights)

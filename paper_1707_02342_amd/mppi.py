@@ -18,6 +18,7 @@ LIB_PATH = PKG / "libmppi.so"
 MPPI_OK, MPPI_E_INVAL, MPPI_E_STATE, MPPI_E_NOMEM, MPPI_E_DEVICE, MPPI_E_NONFINITE = range(6)
 MPPI_PREC_FP32, MPPI_PREC_BF16, MPPI_PREC_FP16 = 0, 1, 2
 MPPI_SCHED_AUTO, MPPI_SCHED_LANE, MPPI_SCHED_WAVE, MPPI_SCHED_WIDE, MPPI_SCHED_QUAD = 0, 1, 2, 3, 4
+MPPI_WEIGHTS_IT, MPPI_WEIGHTS_CEM = 0, 1
 MPPI_T_MAX = 256
 
 STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_NOMEM",
@@ -42,7 +43,8 @@ class mppi_config(C.Structure):
                 ("gamma", C.c_float), ("sigma2", C.c_float * 2), ("u_lo", C.c_float * 2),
                 ("u_hi", C.c_float * 2), ("sg_window", C.c_int32), ("sg_order", C.c_int32),
                 ("precision", C.c_int32), ("schedule", C.c_int32), ("seed", C.c_uint64),
-                ("instance", C.c_uint32), ("explore", C.c_float)]
+                ("instance", C.c_uint32), ("explore", C.c_float), ("weighting", C.c_int32),
+                ("elite", C.c_float)]
 
 
 class mppi_cost(C.Structure):
@@ -412,6 +414,8 @@ def make_config(prob, precision: int = MPPI_PREC_FP32, schedule: int = MPPI_SCHE
     c.seed = int(prob.seed)
     c.instance = int(getattr(prob, "instance", 0))
     c.explore = float(getattr(prob, "explore", 0.0))
+    c.weighting = int(getattr(prob, "weighting", MPPI_WEIGHTS_IT))
+    c.elite = float(getattr(prob, "elite", 0.8))
     return c
 
 

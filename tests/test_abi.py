@@ -41,10 +41,13 @@ def test_exports_every_declared_symbol(M):
 
 def test_struct_layout_matches_header(M):
     # int32 K, T; float dt, lambda, gamma, sigma2[2], u_lo[2], u_hi[2]; int32 sg_window, sg_order,
-    # precision, schedule; uint64 seed; uint32 instance; float explore -> 15*4 + pad 4 + 8 + 4 + 4 = 80
-    assert C.sizeof(M.mppi_config) == 80
+    # precision, schedule; uint64 seed; uint32 instance; float explore; int32 weighting;
+    # float elite -> 15*4 + pad 4 + 8 + 4 + 4 + 4 + 4 = 88
+    assert C.sizeof(M.mppi_config) == 88
     assert M.mppi_config.seed.offset == 64
     assert M.mppi_config.explore.offset == 76
+    assert M.mppi_config.weighting.offset == 80
+    assert M.mppi_config.elite.offset == 84
     assert C.sizeof(M.mppi_cost) == 36
 
 
