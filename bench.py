@@ -270,9 +270,16 @@ def measure_forms(M, stream, iters: int = 30):
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / (100 * n_blk)
             sched = c.schedule
+            M.mppi_set_timing(c.ctx, True)
+            M.mppi_run_receding(c.ctx, synth.C2_X0, 100)
+            launch = M.mppi_get_timing_samples(c.ctx)
+            M.mppi_set_timing(c.ctx, False)
         st = prob.K * prob.T / (ms * 1e-3)
-        tf = st * NET_FLOP_PER_STEP[32] / 1e12
+        launch_ms = float(np.mean(launch))
+        tf = NET_FLOP_PER_STEP[32] * prob.K * prob.T / (launch_ms * 1e-3) / 1e12
         out[name] = {"ms_per_step": ms, "steps_per_s": st, "schedule": sched,
+                     "launch_us": {"mean": launch_ms * 1e3, "p50": float(np.percentile(launch, 50)) * 1e3,
+                                   "p99": float(np.percentile(launch, 99)) * 1e3},
                      "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
                                   "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS},
                      "workload": desc}

@@ -19,7 +19,7 @@ CSRC = PKG / "csrc"
 LIB = PKG / "libmppi.so"
 
 SOURCES = ["mppi_runtime.hip", "kernels_lane.hip", "kernels_wave.hip", "kernels_wide.hip", "kernels_quad.hip",
-           "kernels_adjoint.hip", "kernels_update.hip"]
+           "kernels_adjoint.hip", "kernels_update.hip", "kernels_cem.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

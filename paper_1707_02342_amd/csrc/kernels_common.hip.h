@@ -382,182 +382,4 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// Algorithm 3 (cross-entropy weights)
-// ---------------------------------------------------------------------------
-
-// Monotone map of a cost to an unsigned key (-0 and +0 alike); the cost of a
-// non-finite sample (+inf) maps above every finite cost.
-__device__ __forceinline__ unsigned cost_key(float s) {
-  const unsigned b = __float_as_uint(s + 0.0f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float key_cost(unsigned key) {
-  return __uint_as_float((key & 0x80000000u) ? (key & 0x7FFFFFFFu) : ~key);
-}
-constexpr unsigned kInfKey = 0xFF800000u;   // cost_key(+inf)
-
-// Exclusive prefix count of `flag` over the block in thread order; total = the block's
-// count.  Called by the whole block.
-template <int NT>
-__device__ __forceinline__ int block_excl_count(bool flag, unsigned* s_cnt /* [NT/64] */, int& total) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const unsigned long long m = __ballot(flag);
-  const int below = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) s_cnt[wv] = (unsigned)__popcll(m);
-  __syncthreads();
-  int base = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    const int c = (int)s_cnt[i];
-    base += (i < wv) ? c : 0;
-    tot += c;
-  }
-  __syncthreads();
-  total = tot;
-  return base + below;
-}
-
-// The key of the rank-th smallest of the K costs (rank >= 1, at most the number of
-// finite costs), by a most-significant-digit-first radix select with 8-bit digits, and
-// how many of the costs equal to it fall within the first `rank` (rank_eq).  Called by
-// the whole block.
-template <int NT>
-__device__ void radix_select(const float* S, int K, int rank, unsigned* s_hist /* [256] */,
-                             unsigned* s_sel /* [2] */, unsigned& key_out, int& rank_eq) {
-  const int tid = threadIdx.x;
-  unsigned prefix = 0u, mask = 0u;
-  unsigned r = (unsigned)rank;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int i = tid; i < 256; i += NT) s_hist[i] = 0u;
-    __syncthreads();
-    for (int k = tid; k < K; k += NT) {
-      const unsigned key = cost_key(__builtin_nontemporal_load(S + k));
-      if ((key & mask) == prefix) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (tid < 64) {
-      const unsigned c0 = s_hist[4 * tid], c1 = s_hist[4 * tid + 1];
-      const unsigned c2 = s_hist[4 * tid + 2], c3 = s_hist[4 * tid + 3];
-      const unsigned own = c0 + c1 + c2 + c3;
-      unsigned incl = own;
-      for (int d = 1; d < 64; d <<= 1) {
-        const unsigned n = __shfl_up(incl, d, 64);
-        if (tid >= d) incl += n;
-      }
-      unsigned before = incl - own;
-      if (before < r && r <= incl) {
-        unsigned b = 4u * tid;
-        if (r > before + c0) {
-          before += c0;
-          ++b;
-          if (r > before + c1) {
-            before += c1;
-            ++b;
-            if (r > before + c2) {
-              before += c2;
-              ++b;
-            }
-          }
-        }
-        s_sel[0] = b;
-        s_sel[1] = r - before;
-      }
-    }
-    __syncthreads();
-    prefix |= s_sel[0] << shift;
-    mask |= 255u << shift;
-    r = s_sel[1];
-  }
-  key_out = prefix;
-  rank_eq = (int)r;
-}
-
-// Algorithm 3's update, called by every rollout block after its samples' costs S[k]
-// and delta rows D[k][T][2] are written (through L2) by the waves that own them.  The
-// last block to arrive selects the elite set -- the min(zeta, n_finite) samples of
-// lowest cost, equal costs to the lower sample index -- by a radix select on the costs,
-// sums the elite delta rows in sample order (compensated) and applies the update with
-// weight 1/|E|.
-// Statistics: stats[0] = the largest elite cost, stats[1] = |E|.
-template <int NT>
-__device__ void finish_iteration_cem(const RolloutArgs& a, float* lds /* >= 2T floats */) {
-  __shared__ unsigned s_flag;
-  __shared__ unsigned s_hist[256];
-  __shared__ unsigned s_sel[2];
-  __shared__ unsigned s_cnt[NT / 64];
-  __shared__ int s_list[NT];
-  constexpr int kOut = FinalStage<NT>::kOut;
-  const int tid = threadIdx.x;
-  const int T2 = 2 * a.T;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (tid == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    s_flag = (atomicAdd(a.cnt, 1u) == (unsigned)a.G - 1u) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (s_flag == 0u) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  FinalStage<NT> fs;
-  fs.prefetch(a);
-  if (tid == 0) {
-    a.cnt[0] = 0u;
-    s_sel[0] = 0u;
-  }
-  __syncthreads();
-  // the number of finite costs
-  unsigned nf = 0u;
-  for (int k = tid; k < a.K; k += NT) nf += cost_key(__builtin_nontemporal_load(a.S + k)) < kInfKey ? 1u : 0u;
-  atomicAdd(&s_sel[0], nf);
-  __syncthreads();
-  const int zeff = min(a.cem_zeta, (int)s_sel[0]);
-  __syncthreads();
-  Acc acc[kOut];   // compensated: the elite set can hold millions of rows
-#pragma unroll
-  for (int j = 0; j < kOut; ++j) acc[j] = Acc{0.0f, 0.0f};
-  unsigned zkey = kInfKey;
-  if (zeff > 0) {
-    int need_eq;
-    radix_select<NT>(a.S, a.K, zeff, s_hist, s_sel, zkey, need_eq);
-    int eq_taken = 0;
-    for (int c0 = 0; c0 < a.K; c0 += NT) {
-      const int k = c0 + tid;
-      const unsigned key = (k < a.K) ? cost_key(__builtin_nontemporal_load(a.S + k)) : 0xFFFFFFFFu;
-      const bool eq = key == zkey;
-      int n_eq, n_el;
-      const int eq_rank = eq_taken + block_excl_count<NT>(eq, s_cnt, n_eq);
-      const bool elite = key < zkey || (eq && eq_rank < need_eq);
-      const int pos = block_excl_count<NT>(elite, s_cnt, n_el);
-      if (elite) s_list[pos] = k;
-      eq_taken += n_eq;
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kOut; ++j) {
-        const int o = tid + j * NT;
-        if (o < T2) {
-          int e = 0;
-          for (; e + 8 <= n_el; e += 8) {
-            float v[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = __builtin_nontemporal_load(a.D + (size_t)s_list[e + i] * T2 + o);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) acc[j].add(v[i]);
-          }
-          for (; e < n_el; ++e) acc[j].add(__builtin_nontemporal_load(a.D + (size_t)s_list[e] * T2 + o));
-        }
-      }
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kOut; ++j) {
-    const int o = tid + j * NT;
-    if (o < T2) lds[o] = acc[j].value();
-  }
-  fs.apply(a, lds, zeff > 0, zeff > 0 ? 1.0f / (float)zeff : 0.0f, key_cost(zkey), (float)zeff);
-  __syncthreads();
-}
-
 }  // namespace mppi

@@ -312,9 +312,9 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   }
   float Sv = S.value();
   if (!ok || !finite_f(Sv)) Sv = kInf;
-  if (valid) store_through(a.S + k, Sv);   // read by the host or Algorithm 3's merge
+  if (valid) store_through(a.S + k, Sv);   // read by the host or Algorithm 3's update
   if (a.cem_zeta > 0) {
-    // Algorithm 3: the sample's delta row, for the elite average of the final block
+    // Algorithm 3: the sample's delta row, for the elite average
     if (valid) {
       float* drow = a.D + (size_t)k * 2 * a.T;
       for (int t = 0; t < a.T; ++t) {
@@ -324,12 +324,11 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
           e0 -= sU[2 * t];
           e1 -= sU[2 * t + 1];
         }
-        store_through(drow + 2 * t, e0);
-        store_through(drow + 2 * t + 1, e1);
+        drow[2 * t] = e0;
+        drow[2 * t + 1] = e1;
       }
     }
-    finish_iteration_cem<kLaneBlock>(a, red);
-    return;
+    return;   // the cross-entropy update runs in the launch that follows
   }
   float rho, eta;
   lane_block_partial(a, Sv, valid, k, red, scratch, sU, sU, rho, eta);

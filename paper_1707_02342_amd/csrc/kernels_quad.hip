@@ -484,7 +484,7 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   all4(ok ? 1.0f : 0.0f, okv);
   const bool okc = okv[0] != 0.0f && okv[1] != 0.0f && okv[2] != 0.0f && okv[3] != 0.0f;
   if (!valid || !okc || !finite_f(S)) S = kInf;
-  if (valid && g == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's merge
+  if (valid && g == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's update
 
   if (a.cem_zeta > 0) {
     // Algorithm 3: the sample's delta row (lane group g regenerates steps g, g + 4, ...)
@@ -497,12 +497,11 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
           e0 -= sU[2 * t];
           e1 -= sU[2 * t + 1];
         }
-        store_through(drow + 2 * t, e0);
-        store_through(drow + 2 * t + 1, e1);
+        drow[2 * t] = e0;
+        drow[2 * t + 1] = e1;
       }
     }
-    finish_iteration_cem<kQuadBlock>(a, red);
-    return;
+    return;   // the cross-entropy update runs in the launch that follows
   }
 
   // ---- the block's softmin partial ----------------------------------------------------

@@ -348,16 +348,15 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
 #pragma unroll
   for (int m = 16; m >= 1; m >>= 1) okc &= __shfl_xor(okc, m, 32);
   if (!valid || !okc || !finite_f(S)) S = kInf;
-  if (valid && c32 == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's merge
+  if (valid && c32 == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's update
 
   if (a.cem_zeta > 0) {
-    // Algorithm 3: the sample's delta row, for the elite average of the final block
+    // Algorithm 3: the sample's delta row, for the elite average
     if (valid) {
       float* drow = a.D + (size_t)k * 2 * T;
-      for (int o = c32; o < 2 * T; o += 32) store_through(drow + o, zm ? myE[o] - sU[o] : myE[o]);
+      for (int o = c32; o < 2 * T; o += 32) drow[o] = zm ? myE[o] - sU[o] : myE[o];
     }
-    finish_iteration_cem<kWaveBlock>(a, red);
-    return;
+    return;   // the cross-entropy update runs in the launch that follows
   }
 
   // ---- D: softmin partial of the block's samples ------------------------------------

@@ -333,16 +333,15 @@ __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a)
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) okc &= __shfl_xor(okc, m, 64);
   if (!valid || !okc || !finite_f(S)) S = kInf;
-  if (valid && l == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's merge
+  if (valid && l == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's update
 
   if (a.cem_zeta > 0) {
-    // Algorithm 3: the sample's delta row, for the elite average of the final block
+    // Algorithm 3: the sample's delta row, for the elite average
     if (valid) {
       float* drow = a.D + (size_t)k * 2 * T;
-      for (int o = l; o < 2 * T; o += 64) store_through(drow + o, zm ? myE[o] - sU[o] : myE[o]);
+      for (int o = l; o < 2 * T; o += 64) drow[o] = zm ? myE[o] - sU[o] : myE[o];
     }
-    finish_iteration_cem<kWideBlock>(a, red);
-    return;
+    return;   // the cross-entropy update runs in the launch that follows
   }
 
   // ---- D: softmin partial of the block's samples ------------------------------------

@@ -31,6 +31,8 @@ __global__ void plant_kernel(const float*, const float*, const float*, float*, f
                              float, float, float);
 __global__ void noise_kernel(NoiseKey, int, int, float*);
 __global__ void adjoint_wave_kernel(AdjointArgs);
+template <int NCOL> __global__ void cem_update_kernel(RolloutArgs);
+constexpr int kCemBlockThreads = 1024;
 __global__ void adjoint_reduce_partial_kernel(const float*, int, int, int, float*);
 __global__ void adjoint_reduce_final_kernel(const float*, int, int, const float*, float, float, float*);
 constexpr int kGradChunks = 16;   // row chunks of the first gradient reduction pass
@@ -399,6 +401,14 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
     HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
   }
   HIP_TRY(c, hipGetLastError());
+  // Algorithm 3: the rollout launch leaves costs and delta rows; the update follows
+  if (a.cem_zeta > 0) {
+    if (c->cfg.T <= 128)
+      hipLaunchKernelGGL(cem_update_kernel<2>, dim3(1), dim3(kCemBlockThreads), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL(cem_update_kernel<4>, dim3(1), dim3(kCemBlockThreads), 0, c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+  }
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
     c->pending.push_back(pt);

@@ -106,7 +106,8 @@ def test_cem_paper_parameters(M, orc, schedule, seed):
 
 @pytest.mark.parametrize("schedule", _schedules())
 @pytest.mark.parametrize("K,T,elite", [(1, 1, 0.0), (7, 5, 0.5), (65, 31, 0.9), (257, 9, 0.0),
-                                       (1000, 64, 0.8), (4100, 12, 0.95)])
+                                       (1000, 64, 0.8), (4100, 12, 0.95), (300, 200, 0.8),
+                                       (50, 256, 0.5), (9000, 10, 0.3)])
 def test_cem_ragged(M, orc, schedule, K, T, elite):
     prob = synth.with_(synth.c1_problem(seed=K + T), K=K, T=T, weighting=1, elite=elite)
     _say("cem ragged", schedule, K, T, elite)
