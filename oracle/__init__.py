@@ -24,6 +24,7 @@ LIB = HERE / "liboracle.so"
 
 OK, E_INVAL, E_NONFINITE = 0, 1, 5
 WEIGHTS_IT, WEIGHTS_CEM = 0, 1
+MODEL_NET, MODEL_BASIS = 0, 1
 
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
             "-pthread", "-Wall", "-Wextra"]
@@ -51,7 +52,7 @@ class Problem(C.Structure):
         ("origin_x", C.c_float), ("origin_y", C.c_float), ("resolution", C.c_float),
         ("map", C.POINTER(C.c_float)), ("params", C.POINTER(C.c_float)),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("explore", C.c_float),
-        ("weighting", C.c_int32), ("elite", C.c_float), ("nthreads", C.c_int32),
+        ("weighting", C.c_int32), ("elite", C.c_float), ("model", C.c_int32), ("nthreads", C.c_int32),
     ]
 
 
@@ -92,6 +93,7 @@ def lib():
         L.orc_threshold_margins.argtypes = [pp, fp, fp, fp, dp]
         L.orc_threshold_margins.restype = C.c_int
         L.orc_mlp_forward.argtypes = [pp, dp, dp]
+        L.orc_basis_phi.argtypes = [dp, dp, dp]
         L.orc_costmap.argtypes = [pp, C.c_double, C.c_double, dp]
         L.orc_costmap.restype = C.c_double
         L.orc_state_cost.argtypes = [pp, dp, C.c_int, dp]
@@ -147,6 +149,7 @@ class OracleProblem:
         s.explore = float(getattr(prob, "explore", 0.0))
         s.weighting = int(getattr(prob, "weighting", WEIGHTS_IT))
         s.elite = float(getattr(prob, "elite", 0.8))
+        s.model = int(getattr(prob, "model", MODEL_NET))
         s.nthreads = int(nthreads or min(16, os.cpu_count() or 1))
         self.s = s
 
@@ -325,6 +328,15 @@ def mlp_forward(op: OracleProblem, inp) -> np.ndarray:
     st = lib().orc_mlp_forward(op.ref(), _ptr(x, C.c_double), _ptr(out, C.c_double))
     if st != OK:
         raise ValueError("oracle mlp status")
+    return out
+
+
+def basis_phi(xd, u) -> np.ndarray:
+    """The 25 basis functions at x_d = (roll, v_x, v_y, heading rate), u = (steer, throttle)."""
+    x = _f64(xd)
+    uu = _f64(u)
+    out = np.zeros(25)
+    lib().orc_basis_phi(_ptr(x, C.c_double), _ptr(uu, C.c_double), _ptr(out, C.c_double))
     return out
 
 

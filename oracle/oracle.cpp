@@ -61,11 +61,14 @@ typedef struct {
   float explore;            // exploration fraction alpha of Algorithm 1 (0 = none)
   int32_t weighting;        // ORC_WEIGHTS_IT (Algorithm 2) or ORC_WEIGHTS_CEM (Algorithm 3)
   float elite;              // Algorithm 3's eliteness threshold delta, in [0, 1)
+  int32_t model;            // ORC_MODEL_NET (params = network) or ORC_MODEL_BASIS (params = Theta[25][4])
   int32_t nthreads;
 } orc_problem;
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NONFINITE = 5 };
 enum { ORC_WEIGHTS_IT = 0, ORC_WEIGHTS_CEM = 1 };
+enum { ORC_MODEL_NET = 0, ORC_MODEL_BASIS = 1 };
+enum { ORC_NBASIS = 25 };
 
 }  // extern "C"
 
@@ -192,7 +195,9 @@ struct Prob {
   int H, W;
   R ox, oy, res;
   const float* map;
+  int model;
   std::vector<R> W1, b1, W2, b2, W3, b3;
+  std::vector<R> theta;   // basis-function model: Theta[i][o], row-major [25][4]
   double explore;   // alpha of Algorithm 1, exactly as given (float widened)
 
   // Algorithm 1 draws sample k (counted from 0) around the nominal controls when
@@ -235,7 +240,14 @@ Prob<R> make_prob(const orc_problem* p, const double* params_override = nullptr)
   P.ox = (R)p->origin_x; P.oy = (R)p->origin_y; P.res = (R)p->resolution;
   P.map = p->map;
   P.explore = (double)p->explore;
-  load_params(P, p->params, params_override);
+  P.model = p->model;
+  if (P.model == ORC_MODEL_BASIS) {
+    P.theta.resize(ORC_NBASIS * 4);
+    for (int i = 0; i < ORC_NBASIS * 4; ++i)
+      P.theta[i] = params_override ? (R)params_override[i] : (R)p->params[i];
+  } else {
+    load_params(P, p->params, params_override);
+  }
   return P;
 }
 
@@ -325,13 +337,65 @@ R state_cost(const Prob<R>& P, const R x[7], int t, R* grad = nullptr) {
 
 template <class R> R clampv(R v, R lo, R hi) { return std::min(std::max(v, lo), hi); }
 
+// The 25 basis functions of the basis-function model (appendix), written as printed.
+// The appendix uses the bicycle-model names: r for the heading (yaw) rate and theta for
+// the roll angle; in this state layout those are x_d[3] (theta-dot) and x_d[0] (r).
+// u_delta = steering g(v)_1, u_F = throttle g(v)_2.
+template <class R>
+void basis_functions(const R xd[4], R u_delta, R u_F, R phi[ORC_NBASIS]) {
+  const R roll = xd[0], vx = xd[1], vy = xd[2], yaw_rate = xd[3];
+  const bool moving = vx > (R)0.1;
+  const R alpha_f = moving ? std::atan(vy / vx + (R)0.45 * yaw_rate / vx - u_delta) : -u_delta;
+  const R alpha_r = moving ? std::atan(vy / vx - (R)0.35 * yaw_rate / vx) : (R)0;
+  const R tf = std::tan(alpha_f), tr = std::tan(alpha_r);
+  const R sd = std::sin(u_delta);
+  phi[0] = u_F;
+  phi[1] = vx / 10;
+  phi[2] = sd * tf / 1200;
+  phi[3] = sd * tf * std::fabs(tf) / (1200.0 * 1200.0);
+  phi[4] = sd * tf * tf * tf / (1200.0 * 1200.0 * 1200.0);
+  phi[5] = yaw_rate * vy / 25;
+  phi[6] = yaw_rate / 10;
+  phi[7] = vy / 10;
+  phi[8] = sd;
+  phi[9] = moving ? (vy / vx) / 40 : (R)0;
+  phi[10] = tf / 1400;
+  phi[11] = tf * std::fabs(tf) / (1400.0 * 1400.0);
+  phi[12] = tf * tf * tf / (1400.0 * 1400.0 * 1400.0);
+  phi[13] = tr / 40;
+  phi[14] = tr * std::fabs(tr) / (40.0 * 40.0);
+  phi[15] = tr * tr * tr / (40.0 * 40.0 * 40.0);
+  phi[16] = yaw_rate * vx / 50;
+  phi[17] = roll;
+  phi[18] = roll * yaw_rate;
+  phi[19] = roll * vx / 3;
+  phi[20] = roll * vx * yaw_rate / 5;
+  phi[21] = vx * vx / 100;
+  phi[22] = vx * vx * vx / 1000;
+  phi[23] = u_F * u_F;
+  phi[24] = u_F * u_F * u_F;
+}
+
+// f(x_d, v) = Theta^T phi(x_d, v) (Section VI-B-1).
+template <class R>
+void basis_forward(const Prob<R>& P, const R in[6], R out[4]) {
+  R phi[ORC_NBASIS];
+  basis_functions(in, in[4], in[5], phi);
+  for (int o = 0; o < 4; ++o) {
+    R a = 0;
+    for (int i = 0; i < ORC_NBASIS; ++i) a += P.theta[i * 4 + o] * phi[i];
+    out[o] = a;
+  }
+}
+
 // One step of the full equations of motion (Section VI-B): kinematic states by
 // explicit Euler with the pre-step state, dynamic states x_d += f(x_d, v) dt.
 template <class R>
 void dynamics_step(const Prob<R>& P, const R x[7], const R vc[2], R xn[7], R* h1, R* h2) {
   const R in[6] = {x[3], x[4], x[5], x[6], vc[0], vc[1]};
   R f[4];
-  mlp_forward(P, in, f, h1, h2);
+  if (P.model == ORC_MODEL_BASIS) basis_forward(P, in, f);
+  else mlp_forward(P, in, f, h1, h2);
   const R c = std::cos(x[2]), s = std::sin(x[2]);
   xn[0] = x[0] + P.dt * (c * x[4] - s * x[5]);
   xn[1] = x[1] + P.dt * (s * x[4] + c * x[5]);
@@ -502,7 +566,9 @@ void sgf_matrix(int T, int window, int order, double* M) {
 }
 
 bool valid_problem(const orc_problem* p) {
-  if (!p || p->K <= 0 || p->T <= 0 || p->hidden <= 0) return false;
+  if (!p || p->K <= 0 || p->T <= 0) return false;
+  if (p->model != ORC_MODEL_NET && p->model != ORC_MODEL_BASIS) return false;
+  if (p->model == ORC_MODEL_NET && p->hidden <= 0) return false;
   if (!(p->sigma2[0] > 0 && p->sigma2[1] > 0 && p->lambda > 0)) return false;
   if (p->sg_window < 1 || p->sg_window % 2 == 0 || p->sg_window > p->T) return false;
   if (p->sg_order < 0 || p->sg_order >= p->sg_window) return false;
@@ -624,12 +690,13 @@ void orc_plant_step(const orc_problem* p, const double* x, const double* u, doub
 //   = rho - lambda log(eta~/K)            (Eq. FreeEnergy with the Monte-Carlo
 // estimate over the K samples of this iteration's noise), evaluated at FP64
 // nominal controls U and FP64 network parameters (nullable: use the problem's).
-// Defined for importance samples and Algorithm 2's weights only (otherwise INVAL).
+// Defined for importance samples, Algorithm 2's weights and the network model only
+// (otherwise INVAL).
 int orc_objective(const orc_problem* p, const float* x0, const double* U, const double* params,
                   uint32_t iter, double* J, double* S_out) {
   if (!valid_problem(p)) return ORC_E_INVAL;
-  // defined for importance samples and the information-theoretic weights only
-  if (p->explore != 0.0f || p->weighting != ORC_WEIGHTS_IT) return ORC_E_INVAL;
+  // defined for importance samples, the information-theoretic weights and the network
+  if (p->explore != 0.0f || p->weighting != ORC_WEIGHTS_IT || p->model != ORC_MODEL_NET) return ORC_E_INVAL;
   const int K = p->K, T = p->T;
   std::vector<float> eps((size_t)K * T * 2);
   noise_all(p, iter, eps.data());
@@ -670,7 +737,7 @@ int orc_objective(const orc_problem* p, const float* x0, const double* U, const 
 int orc_objective_grad(const orc_problem* p, const float* x0, const double* U, const double* params,
                        uint32_t iter, double* J, double* dJdU, double* dJdtheta) {
   if (!valid_problem(p)) return ORC_E_INVAL;
-  if (p->explore != 0.0f || p->weighting != ORC_WEIGHTS_IT) return ORC_E_INVAL;
+  if (p->explore != 0.0f || p->weighting != ORC_WEIGHTS_IT || p->model != ORC_MODEL_NET) return ORC_E_INVAL;
   const int K = p->K, T = p->T, h = p->hidden;
   std::vector<float> eps((size_t)K * T * 2);
   noise_all(p, iter, eps.data());
@@ -811,6 +878,10 @@ int orc_mlp_forward(const orc_problem* p, const double* in, double* out) {
   std::vector<double> h1(P.h), h2(P.h);
   mlp_forward(P, in, out, h1.data(), h2.data());
   return ORC_OK;
+}
+
+void orc_basis_phi(const double xd[4], const double u[2], double phi[ORC_NBASIS]) {
+  basis_functions(xd, u[0], u[1], phi);
 }
 
 double orc_costmap(const orc_problem* p, double px, double py, double* grad2) {

@@ -59,6 +59,34 @@ def mlp_params(hidden: int = 32, seed: int = 0, bias_scale: float = 0.0) -> np.n
     return out
 
 
+# Basis-function model (appendix): Theta is [25][4], row i for basis function i + 1,
+# column o for d/dt of (roll, v_x, v_y, heading rate).  No system-identification data is
+# available, so Theta is synthetic: a damped, steerable base written in the appendix's
+# own terms (throttle drives v_x, the front and rear tyre terms tan(alpha) drive v_y and
+# the heading rate, rates are damped, roll relaxes) plus seeded N(0, noise^2) entries
+# scaled by each basis function's normaliser, so that every basis function contributes.
+N_BASIS = 25
+_BASIS_NORM = [1.0, 10.0, 1200.0, 1200.0 ** 2, 1200.0 ** 3, 25.0, 10.0, 10.0, 1.0, 40.0, 1400.0,
+               1400.0 ** 2, 1400.0 ** 3, 40.0, 40.0 ** 2, 40.0 ** 3, 50.0, 1.0, 1.0, 3.0, 5.0, 100.0,
+               1000.0, 1.0, 1.0]
+# (basis function number, output, coefficient of the basis function times its normaliser,
+# e.g. -0.3 on v_x for basis 2 = v_x / 10)
+_BASIS_BASE = [(18, 0, -4.0), (17, 0, 0.04),
+               (1, 1, 6.0), (2, 1, -0.3), (22, 1, -0.02), (6, 1, 1.0),
+               (17, 2, -1.0), (8, 2, -2.0), (11, 2, -4.0), (14, 2, -3.0),
+               (11, 3, -5.0), (14, 3, 3.0), (7, 3, -1.0)]
+
+
+def basis_theta(seed: int = 0, noise: float = 0.05) -> np.ndarray:
+    """A synthetic Theta [25][4] (float32, row-major) for the basis-function model."""
+    rng = np.random.default_rng(20_000 + seed)
+    norm = np.array(_BASIS_NORM)[:, None]
+    theta = noise * rng.standard_normal((N_BASIS, 4)) * norm
+    for i, o, c in _BASIS_BASE:
+        theta[i - 1, o] += c * _BASIS_NORM[i - 1]
+    return theta.astype(np.float32)
+
+
 def mlp_unpack(params: np.ndarray, hidden: int):
     """Split a packed parameter vector into (W1, b1, W2, b2, W3, b3) views."""
     h = hidden
@@ -231,6 +259,7 @@ class Problem:
     seed: int = 0
     instance: int = 0
     explore: float = 0.0                 # fraction of zero-mean (exploration) samples
+    model: int = 0                       # 0: network (params = packed MLP), 1: basis functions (Theta)
     weighting: int = 0                   # 0: Algorithm 2 (information theoretic), 1: Algorithm 3 (CEM)
     elite: float = 0.8                   # Algorithm 3's eliteness threshold (percentile)
     cost: CostParams = field(default_factory=CostParams)
@@ -280,6 +309,12 @@ def c5_problem(seed: int = 0) -> Problem:
     return Problem(K=4096, T=100, hidden=32, dt=0.02, lam=1.0, sigma2=(0.3, 0.35),
                    sg_window=1, sg_order=0, seed=seed,
                    cost=CostParams(w_map=100.0, w_speed=1.0, v_des=6.0))
+
+
+def basis_problem(seed: int = 0, K: int = 1920) -> Problem:
+    """The paper-shaped problem (K=1920, T=100, elliptical map, impulses, SGF 9/2) with the
+    basis-function model in place of the network (params = basis_theta())."""
+    return replace(c2_problem(seed), K=K, model=1)
 
 
 def explore_problem(seed: int = 0, K: int = 1920, explore: float = 0.01) -> Problem:
