@@ -146,6 +146,16 @@ mppi_status mppi_set_costmap(mppi_ctx* ctx, const float* map, int32_t H, int32_t
  * non-finite parameters, or a precision the given h does not support. */
 mppi_status mppi_set_dynamics(mppi_ctx* ctx, const int32_t dims[4], const float* params);
 
+/* Basis-function dynamics model (Section VI-B-1 and the appendix), in place of the
+ * network: f(x_d, g(v)) = Theta^T phi(x_d, g(v)) with the appendix's 25 basis functions
+ * (its r is the heading rate theta_dot, its theta the roll).  theta = Theta[25][4]
+ * row-major: row i for basis function i + 1, column o for d/dt of (roll, v_x, v_y,
+ * theta_dot).  Copied.  Runs in FP32 on the LANE and WAVE schedules (AUTO: WAVE up to
+ * K = 12288, LANE above); the last set_*dynamics call chooses the model.
+ * INVAL: non-finite entries, precision other than FP32, schedule WIDE or QUAD.  The
+ * differentiation form (mppi_objective) and the batched form use the network only. */
+mppi_status mppi_set_basis_dynamics(mppi_ctx* ctx, const float* theta);
+
 /* Replace the nominal control sequence U ([T][2], steer/throttle per step).  Copied. */
 mppi_status mppi_set_controls(mppi_ctx* ctx, const float* U);
 

@@ -846,8 +846,9 @@ int orc_objective_grad(const orc_problem* p, const float* x0, const double* U, c
 }
 
 // Per sample, the smallest distance over t = 1..T of the map value to map_thresh
-// and of |zeta| to slip_thresh along the FP64 trajectory: samples that pass within
-// a rounding error of an impulse threshold can legitimately flip an indicator.
+// and of |zeta| to slip_thresh along the FP64 trajectory (and, with the basis-function
+// model, of v_x to its 0.1 branch point over t = 0..T-1): samples that pass within a
+// rounding error of such a threshold can legitimately take the other side of it.
 int orc_threshold_margins(const orc_problem* p, const float* x0, const float* U, const float* eps,
                           double* margin) {
   if (!valid_problem(p)) return ORC_E_INVAL;
@@ -857,6 +858,9 @@ int orc_threshold_margins(const orc_problem* p, const float* x0, const float* U,
     std::vector<double> tr((size_t)(T + 1) * 7);
     rollout_one(P, x0, U, eps + (size_t)k * T * 2, P.exploration(k), tr.data());
     double m = std::numeric_limits<double>::infinity();
+    // the basis-function model branches on v_x > 0.1 at the states entering each step
+    if (P.model == ORC_MODEL_BASIS)
+      for (int t = 0; t < T; ++t) m = std::min(m, std::fabs(tr[(size_t)t * 7 + 4] - 0.1));
     for (int t = 1; t <= T; ++t) {
       const double* x = &tr[(size_t)t * 7];
       const double h = costmap(P, x[0], x[1]);

@@ -125,6 +125,89 @@ __device__ __forceinline__ float tanh_f(float x) {
 }
 
 // ---------------------------------------------------------------------------
+// Basis-function dynamics model (appendix; Section VI-B-1)
+// ---------------------------------------------------------------------------
+// f(x_d, v) = Theta^T phi(x_d, v) with 25 basis functions; Theta is [25][4] row-major
+// (row = basis function, column = d/dt of roll, v_x, v_y, heading rate).  The appendix
+// names the heading (yaw) rate r and the roll theta; here they are x_d[3] and x_d[0].
+// u_delta = steering g(v)_1, u_F = throttle g(v)_2, sd = sin(u_delta),
+// td = tan(u_delta) (read only when v_x <= 0.1).  The tyre tangents tan(alpha) use
+// tan(arctan z) = z: above v_x = 0.1 they are z itself, so no arctan or tan is needed.
+constexpr int kNumBasis = 25;
+
+__device__ __forceinline__ void basis_phi(float roll, float vx, float vy, float om, float uF, float sd,
+                                          float td, float ud, float phi[kNumBasis]) {
+  float q = 0.0f, tf, tr = 0.0f;
+  if (vx > 0.1f) {
+    const float rv = 1.0f / vx;
+    q = vy * rv;
+    tf = (q + (0.45f * om) * rv) - ud;
+    tr = q - (0.35f * om) * rv;
+  } else {
+    tf = -td;
+  }
+  const float atf = fabsf(tf), atr = fabsf(tr);
+  const float sf = sd * tf;
+  phi[0] = uF;
+  phi[1] = vx * 0.1f;
+  phi[2] = sf * (1.0f / 1200.0f);
+  phi[3] = (sf * atf) * (1.0f / (1200.0f * 1200.0f));
+  phi[4] = (sf * (tf * tf)) * (1.0f / (1200.0f * 1200.0f * 1200.0f));
+  phi[5] = (om * vy) * (1.0f / 25.0f);
+  phi[6] = om * 0.1f;
+  phi[7] = vy * 0.1f;
+  phi[8] = sd;
+  phi[9] = q * (1.0f / 40.0f);
+  phi[10] = tf * (1.0f / 1400.0f);
+  phi[11] = (tf * atf) * (1.0f / (1400.0f * 1400.0f));
+  phi[12] = (tf * (tf * tf)) * (1.0f / (1400.0f * 1400.0f * 1400.0f));
+  phi[13] = tr * (1.0f / 40.0f);
+  phi[14] = (tr * atr) * (1.0f / (40.0f * 40.0f));
+  phi[15] = (tr * (tr * tr)) * (1.0f / (40.0f * 40.0f * 40.0f));
+  phi[16] = (om * vx) * (1.0f / 50.0f);
+  phi[17] = roll;
+  phi[18] = roll * om;
+  phi[19] = (roll * vx) * (1.0f / 3.0f);
+  phi[20] = ((roll * vx) * om) * 0.2f;
+  phi[21] = (vx * vx) * 0.01f;
+  phi[22] = (vx * (vx * vx)) * 0.001f;
+  phi[23] = uF * uF;
+  phi[24] = uF * (uF * uF);
+}
+
+// Output o of f (the sum over i of Theta[i][o] phi_i, in i order).
+__device__ __forceinline__ float basis_out(const float* __restrict__ th, const float xd[4], float ud, float uF,
+                                           int o) {
+  const float sd = sinf(ud);
+  float td = 0.0f;
+  if (!(xd[1] > 0.1f)) td = tanf(ud);
+  float phi[kNumBasis];
+  basis_phi(xd[0], xd[1], xd[2], xd[3], uF, sd, td, ud, phi);
+  float acc = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kNumBasis; ++i) acc = __builtin_fmaf(th[i * 4 + o], phi[i], acc);
+  return acc;
+}
+
+// All four outputs in one thread (the plant step and the lane schedule); each equals
+// basis_out() bit for bit.
+__device__ __forceinline__ void basis_f(const float* __restrict__ th, const float xd[4], float ud, float uF,
+                                        float f[4]) {
+  const float sd = sinf(ud);
+  float td = 0.0f;
+  if (!(xd[1] > 0.1f)) td = tanf(ud);
+  float phi[kNumBasis];
+  basis_phi(xd[0], xd[1], xd[2], xd[3], uF, sd, td, ud, phi);
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kNumBasis; ++i) acc = __builtin_fmaf(th[i * 4 + o], phi[i], acc);
+    f[o] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Cost map and state cost (Section VI-C)
 // ---------------------------------------------------------------------------
 

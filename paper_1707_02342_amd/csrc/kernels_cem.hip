@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
   const int nchunk = (K + kCemChunk - 1) / kCemChunk;
   const bool resident = nchunk == 1;
 
-  FinalStage<kCemBlock> fs;
+  FinalStage<kCemBlock, kModelAny> fs;
   fs.prefetch(a);
 
   unsigned key[kCemKeys];

@@ -196,8 +196,12 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
 // each neuron's sums in input order, so the new state equals a one-thread evaluation
 // bit for bit.  Every other block of the launch has read x0_dev before it published
 // its row, so x0_dev can be overwritten here.  lds (>= 2T floats) is free on entry.
-template <int NT, int kOut>
+// MODEL: the dynamics model the calling kernel serves (kModelAny: decided by a.model);
+// a kernel that serves one model compiles only that model's plant step.
+template <int NT, int kOut, int MODEL>
 __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float* lds) {
+  constexpr bool kMayBasis = MODEL != kModelNet;
+  constexpr bool kMayNet = MODEL != kModelBasis;
   __shared__ float s_h[2 * 64];
   __shared__ float s_f[4];
   const int tid = threadIdx.x;
@@ -224,20 +228,25 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   const float vc0 = fminf(fmaxf(lds[0], a.u_lo0), a.u_hi0);
   const float vc1 = fminf(fmaxf(lds[1], a.u_lo1), a.u_hi1);
   const float in[6] = {x[3], x[4], x[5], x[6], vc0, vc1};
-  if (tid < H) {
+  const bool net = kMayNet && (!kMayBasis || a.model != kModelBasis);
+  if constexpr (kMayBasis) {
+    // output tid in thread tid, with the plant step's arithmetic
+    if (!net && tid < 4) s_f[tid] = basis_out(a.params, in, vc0, vc1, tid);
+  }
+  if (kMayNet && net && tid < H) {
     float acc = b1[tid];
 #pragma unroll
     for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[tid * 6 + j], in[j], acc);
     s_h[tid] = tanh_f(acc);
   }
   __syncthreads();
-  if (tid < H) {
+  if (kMayNet && net && tid < H) {
     float acc = b2[tid];
     for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[tid * H + j], s_h[j], acc);
     s_h[64 + tid] = tanh_f(acc);
   }
   __syncthreads();
-  if (tid < 4) {
+  if (kMayNet && net && tid < 4) {
     float acc = b3[tid];
     for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[tid * H + j], s_h[64 + j], acc);
     s_f[tid] = acc;
@@ -266,7 +275,7 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
 // memory round trip with the merge's own; apply() then forms Delta = lds[0..2T) * scale,
 // smooths it, updates U, writes the statistics and the status, advances the iteration
 // counter and, in a receding step, shifts U and advances the plant.
-template <int NT>
+template <int NT, int MODEL = kModelNet>
 struct FinalStage {
   static constexpr int kOut = (2 * kTMax + NT - 1) / NT;
   static constexpr int kTapReg = 16;
@@ -330,7 +339,7 @@ struct FinalStage {
       a.stats[1] = stat1;
       if (a.iter_dev) *a.iter_dev = *a.iter_dev + 1u;
     }
-    if (a.recede) receding_step<NT, kOut>(a, u_new, lds);
+    if (a.recede) receding_step<NT, kOut, MODEL>(a, u_new, lds);
   }
 };
 
@@ -342,7 +351,7 @@ struct FinalStage {
 // U <- U + SG * Delta.  With a single group the second level is skipped (merging one
 // row with scale exp(0) = 1 would return it unchanged).  Every decision is uniform
 // over the block, so all barriers are reached by all threads.
-template <int NT>
+template <int NT, int MODEL = kModelNet>
 __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
                                  const float* N_lds /* [2T] */, float* lds /* >= 2T floats */) {
   __shared__ unsigned s_flag;
@@ -357,7 +366,7 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
   __syncthreads();
   if (publish_and_count<NT>(a.part + (size_t)tile * stride, rho_b, eta_b, N_lds, T2, a.cnt + grp,
                             (unsigned)n_in, &s_flag)) {
-    FinalStage<NT> fs;
+    FinalStage<NT, MODEL> fs;
     float rho, eta;
     bool final_merge = ngrp == 1;
     if (final_merge) fs.prefetch(a);

@@ -16,7 +16,9 @@
 //    k-dimension to match what each lane already holds.  Layer 3's rows are placed so
 //    that every lane receives the four outputs of its own sample.
 //
-// Cost, weights and the update stay FP32 in both.  This is the throughput schedule
+//  * NetBasis (FP32): the basis-function model, f = Theta^T phi(x_d, v).
+//
+// Cost, weights and the update stay FP32 in all.  This is the throughput schedule
 // for large K: one sample per lane keeps every lane busy.
 #include "kernels_common.hip.h"
 
@@ -30,6 +32,7 @@ constexpr int kLaneWaves = kLaneBlock / 64;
 // ---------------------------------------------------------------------------
 template <int HID>
 struct NetUniform {
+  static constexpr int kModel = kModelNet;
   const float* __restrict__ P;
   __device__ explicit NetUniform(const float* p) : P(p) {}
   __device__ __forceinline__ void eval(const float in[6], float f[4]) const {
@@ -63,6 +66,16 @@ struct NetUniform {
       f[o] = a;
     }
   }
+};
+
+// ---------------------------------------------------------------------------
+// Basis-function model, one per lane (Theta read with wave-uniform addresses)
+// ---------------------------------------------------------------------------
+struct NetBasis {
+  static constexpr int kModel = kModelBasis;
+  const float* __restrict__ P;
+  __device__ explicit NetBasis(const float* p) : P(p) {}
+  __device__ __forceinline__ void eval(const float in[6], float f[4]) const { basis_f(P, in, in[4], in[5], f); }
 };
 
 // ---------------------------------------------------------------------------
@@ -111,6 +124,7 @@ __device__ __forceinline__ int kslot_neuron(int kb, int g, int c) {
 
 template <int PREC, int HID>
 struct NetMfma {
+  static constexpr int kModel = kModelNet;
   typedef MfmaOps<PREC> Ops;
   typedef typename Ops::vec vec;
   static constexpr int NM = HID / 16;   // 16-neuron tiles
@@ -332,7 +346,7 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   }
   float rho, eta;
   lane_block_partial(a, Sv, valid, k, red, scratch, sU, sU, rho, eta);
-  finish_iteration<kLaneBlock>(a, tile, rho, eta, sU, red);
+  finish_iteration<kLaneBlock, Net::kModel>(a, tile, rho, eta, sU, red);
 }
 
 template <class Net>
@@ -387,6 +401,8 @@ hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream,
   } else if (precision == kPrecFP16) {
     if (hidden == 32) rollout_lane_kernel<NetMfma<kPrecFP16, 32>><<<grid, dim3(kLaneBlock), 0, stream>>>(a);
     else rollout_lane_kernel<NetMfma<kPrecFP16, 64>><<<grid, dim3(kLaneBlock), 0, stream>>>(a);
+  } else if (a.model == kModelBasis) {
+    rollout_lane_kernel<NetBasis><<<grid, dim3(kLaneBlock), 0, stream>>>(a);
   } else {
     if (hidden == 32) rollout_lane_kernel<NetUniform<32>><<<grid, dim3(kLaneBlock), 0, stream>>>(a);
     else rollout_lane_kernel<NetUniform<64>><<<grid, dim3(kLaneBlock), 0, stream>>>(a);

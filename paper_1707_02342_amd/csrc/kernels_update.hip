@@ -14,7 +14,8 @@ __global__ __launch_bounds__(512) void shift_kernel(float* U, int T, float* u0_o
   if (o < 2 * T) U[o] = v;
 }
 
-// Noise-free plant step x_out = F(x, g(u)) with the FP32 network (one thread).
+// Noise-free plant step x_out = F(x, g(u)) with the FP32 network, or with the
+// basis-function model when HID = 0 (one thread).
 // x_out may alias x_in; x_copy (nullable) receives a second copy of the result.
 template <int HID>
 __global__ void plant_kernel(const float* __restrict__ P, const float* x_in, const float* u,
@@ -26,27 +27,32 @@ __global__ void plant_kernel(const float* __restrict__ P, const float* x_in, con
   const float vc0 = fminf(fmaxf(u[0], lo0), hi0);
   const float vc1 = fminf(fmaxf(u[1], lo1), hi1);
   const float in[6] = {x[3], x[4], x[5], x[6], vc0, vc1};
-  const float* W1 = P;
-  const float* b1 = W1 + HID * 6;
-  const float* W2 = b1 + HID;
-  const float* b2 = W2 + HID * HID;
-  const float* W3 = b2 + HID;
-  const float* b3 = W3 + 4 * HID;
-  float h1[HID], h2[HID], f[4];
-  for (int i = 0; i < HID; ++i) {
-    float acc = b1[i];
-    for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[i * 6 + j], in[j], acc);
-    h1[i] = tanh_f(acc);
-  }
-  for (int i = 0; i < HID; ++i) {
-    float acc = b2[i];
-    for (int j = 0; j < HID; ++j) acc = __builtin_fmaf(W2[i * HID + j], h1[j], acc);
-    h2[i] = tanh_f(acc);
-  }
-  for (int o = 0; o < 4; ++o) {
-    float acc = b3[o];
-    for (int j = 0; j < HID; ++j) acc = __builtin_fmaf(W3[o * HID + j], h2[j], acc);
-    f[o] = acc;
+  float f[4];
+  if constexpr (HID == 0) {
+    basis_f(P, in, vc0, vc1, f);
+  } else {
+    const float* W1 = P;
+    const float* b1 = W1 + HID * 6;
+    const float* W2 = b1 + HID;
+    const float* b2 = W2 + HID * HID;
+    const float* W3 = b2 + HID;
+    const float* b3 = W3 + 4 * HID;
+    float h1[HID], h2[HID];
+    for (int i = 0; i < HID; ++i) {
+      float acc = b1[i];
+      for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[i * 6 + j], in[j], acc);
+      h1[i] = tanh_f(acc);
+    }
+    for (int i = 0; i < HID; ++i) {
+      float acc = b2[i];
+      for (int j = 0; j < HID; ++j) acc = __builtin_fmaf(W2[i * HID + j], h1[j], acc);
+      h2[i] = tanh_f(acc);
+    }
+    for (int o = 0; o < 4; ++o) {
+      float acc = b3[o];
+      for (int j = 0; j < HID; ++j) acc = __builtin_fmaf(W3[o * HID + j], h2[j], acc);
+      f[o] = acc;
+    }
   }
   float sth, cth;
   sincosf(x[2], &sth, &cth);
@@ -61,6 +67,8 @@ __global__ void plant_kernel(const float* __restrict__ P, const float* x_in, con
   }
 }
 
+template __global__ void plant_kernel<0>(const float*, const float*, const float*, float*, float*,
+                                         float, float, float, float, float);
 template __global__ void plant_kernel<32>(const float*, const float*, const float*, float*, float*,
                                           float, float, float, float, float);
 template __global__ void plant_kernel<64>(const float*, const float*, const float*, float*, float*,

@@ -23,6 +23,10 @@
 //                and 2) leaves output (lane & 3) in every lane, and a second
 //                permlane16 swap adds the two rows;
 //       update:  x_d += dt f in compensated (two-sum) form, one component per lane;
+//     with the basis-function model (MODEL = kModelBasis) the four components reach
+//     every lane of the quad through quad_perm DPP moves, every lane forms the 25
+//     basis functions and lane (component c) sums Theta[i][c] phi_i for its own
+//     output: no cross-lane reduction is needed;
 //  C. kinematics and cost, lane-parallel over t: theta and the position are prefix
 //     sums of their Euler increments (scans across the 32 lanes), then the cost at
 //     every post-step state and the control-cost term, summed over t;
@@ -34,7 +38,7 @@
 
 namespace mppi {
 
-template <int HID, int NQ>
+template <int HID, int NQ, int MODEL>
 __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a) {
   if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   static_assert(HID == 32, "the wave schedule maps 32 hidden units onto 32 lanes");
@@ -64,7 +68,9 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
 
   for (int i = threadIdx.x; i < 2 * T; i += kWaveBlock) sU[i] = a.U[i];
 
-  // ---- per-lane network constants --------------------------------------------------
+  // ---- per-lane network constants (network model only: with the basis-function
+  // model params holds Theta, and none of these is read) --------------------------
+  constexpr bool kNet = MODEL == kModelNet;
   const float* W1 = a.params;
   const float* b1 = W1 + HID * 6;
   const float* W2 = b1 + HID;
@@ -74,8 +80,8 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   const int j = 16 * r + col;
   float w1[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) w1[i] = W1[j * 6 + i];
-  const float bb1 = b1[j];
+  for (int i = 0; i < 6; ++i) w1[i] = kNet ? W1[j * 6 + i] : 0.0f;
+  const float bb1 = kNet ? b1[j] : 0.0f;
   float wP[16], wQ[16];
   int src[16];
   src[0] = col;
@@ -86,15 +92,19 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   src[13] = ror_src<13>(col); src[14] = ror_src<14>(col); src[15] = ror_src<15>(col);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    wP[s] = W2[col * HID + 16 * r + src[s]];
-    wQ[s] = W2[(16 + col) * HID + 16 * r + src[s]];
+    wP[s] = kNet ? W2[col * HID + 16 * r + src[s]] : 0.0f;
+    wQ[s] = kNet ? W2[(16 + col) * HID + 16 * r + src[s]] : 0.0f;
   }
-  const float bP = (r == 0) ? b2[col] : 0.0f;
-  const float bQ = (r == 1) ? b2[16 + col] : 0.0f;
+  const float bP = (kNet && r == 0) ? b2[col] : 0.0f;
+  const float bQ = (kNet && r == 1) ? b2[16 + col] : 0.0f;
   float w3[4];
 #pragma unroll
-  for (int o = 0; o < 4; ++o) w3[o] = W3[o * HID + j];
-  const float b3c = b3[comp];
+  for (int o = 0; o < 4; ++o) w3[o] = kNet ? W3[o * HID + j] : 0.0f;
+  const float b3c = kNet ? b3[comp] : 0.0f;
+  // basis-function model: this lane's column of Theta
+  float thc[kNumBasis];
+#pragma unroll
+  for (int i = 0; i < kNumBasis; ++i) thc[i] = kNet ? 0.0f : a.params[i * 4 + comp];
   const bool bit0 = (lane & 1) != 0;
   const bool bit1 = (lane & 2) != 0;
 
@@ -141,74 +151,95 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     const float2 e_next = *reinterpret_cast<const float2*>(myE + 2 * tn);
     const float vc0 = fminf(fmaxf(zm ? e.x : u.x + e.x, a.u_lo0), a.u_hi0);
     const float vc1 = fminf(fmaxf(zm ? e.y : u.y + e.y, a.u_lo1), a.u_hi1);
-    // layer 1
-    float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
-    acc1 = __builtin_fmaf(w1[5], vc1, acc1);
-    const float xh = xd.hi;
-    // one asm block, so that no wait states are inserted between the four
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_fmac_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0] row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1] row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2] row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %1, %5 quad_perm:[3,3,3,3] row_mask:0xf bank_mask:0xf"
-        : "+v"(acc1) : "v"(xh), "v"(w1[0]), "v"(w1[1]), "v"(w1[2]), "v"(w1[3]));
-    const float h1 = tanh_f(acc1);
-    // layer 2: four interleaved chains (P, Q for even and odd rotations) so that no
-    // accumulator is read by the instruction right after the one that wrote it
-    float P = __builtin_fmaf(wP[0], h1, bP);
-    float Q = __builtin_fmaf(wQ[0], h1, bQ);
-    float P2 = wP[1] * dpp_f<kRowRor + 1>(h1);
-    float Q2 = wQ[1] * dpp_f<kRowRor + 1>(h1);
-    // rotations 2..15 in one asm block (no wait states inserted between them); the
-    // DPP source h1 was written two instructions before (the nop covers the hazard)
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_fmac_f32_dpp %0, %4, %5 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %6 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %7 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %8 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %4, %9 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %10 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %11 row_ror:5 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %12 row_ror:5 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %4, %13 row_ror:6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %14 row_ror:6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %15 row_ror:7 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %16 row_ror:7 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %4, %17 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %18 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %19 row_ror:9 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %20 row_ror:9 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %4, %21 row_ror:10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %22 row_ror:10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %23 row_ror:11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %24 row_ror:11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %4, %25 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %26 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %27 row_ror:13 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %28 row_ror:13 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %4, %29 row_ror:14 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %30 row_ror:14 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %4, %31 row_ror:15 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %4, %32 row_ror:15 row_mask:0xf bank_mask:0xf"
-        : "+v"(P), "+v"(Q), "+v"(P2), "+v"(Q2)
-        : "v"(h1), "v"(wP[2]), "v"(wQ[2]), "v"(wP[3]), "v"(wQ[3]), "v"(wP[4]), "v"(wQ[4]), "v"(wP[5]), "v"(wQ[5]), "v"(wP[6]), "v"(wQ[6]), "v"(wP[7]), "v"(wQ[7]), "v"(wP[8]), "v"(wQ[8]), "v"(wP[9]), "v"(wQ[9]), "v"(wP[10]), "v"(wQ[10]), "v"(wP[11]), "v"(wQ[11]), "v"(wP[12]), "v"(wQ[12]), "v"(wP[13]), "v"(wQ[13]), "v"(wP[14]), "v"(wQ[14]), "v"(wP[15]), "v"(wQ[15]));
-    P = P + P2;
-    Q = Q + Q2;
-    swap_rows(P, Q);                    // row 0: (P0, P1) -> out c;  row 1: (Q0, Q1) -> out 16+c
-    const float h2 = tanh_f(P + Q);
-    // layer 3: reduce-scatter of the four outputs over the row
-    const float a0 = w3[0] * h2, a1 = w3[1] * h2, a2 = w3[2] * h2, a3 = w3[3] * h2;
-    const float send0 = bit0 ? a0 : a1, keep0 = bit0 ? a1 : a0;
-    const float send1 = bit0 ? a2 : a3, keep1 = bit0 ? a3 : a2;
-    const float g0 = keep0 + dpp_f<kQuadXor1>(send0);        // output bit0
-    const float g1 = keep1 + dpp_f<kQuadXor1>(send1);        // output 2 + bit0
-    const float send2 = bit1 ? g0 : g1, keep2 = bit1 ? g1 : g0;
-    float f = keep2 + dpp_f<kQuadXor2>(send2);               // output lane & 3
-    f = f + dpp_f<kRowRor + 8>(f);
-    f = f + dpp_f<kRowRor + 4>(f);
-    f = add_rows(f) + b3c;
+    float f;
+    if constexpr (MODEL == kModelBasis) {
+      const float xh = xd.hi;
+      const float roll = dpp_f<0x00>(xh), vx = dpp_f<0x55>(xh);   // quad_perm:[i,i,i,i]
+      const float vy = dpp_f<0xAA>(xh), om = dpp_f<0xFF>(xh);
+      const float sd = sinf(vc0);
+      float td = 0.0f;
+      if (!(vx > 0.1f)) td = tanf(vc0);
+      float phi[kNumBasis];
+      basis_phi(roll, vx, vy, om, vc1, sd, td, vc0, phi);
+      float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kNumBasis; i += 4) {
+        p0 = __builtin_fmaf(thc[i], phi[i], p0);
+        if (i + 1 < kNumBasis) p1 = __builtin_fmaf(thc[i + 1], phi[i + 1], p1);
+        if (i + 2 < kNumBasis) p2 = __builtin_fmaf(thc[i + 2], phi[i + 2], p2);
+        if (i + 3 < kNumBasis) p3 = __builtin_fmaf(thc[i + 3], phi[i + 3], p3);
+      }
+      f = (p0 + p1) + (p2 + p3);
+    } else {
+      // layer 1
+      float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
+      acc1 = __builtin_fmaf(w1[5], vc1, acc1);
+      const float xh = xd.hi;
+      // one asm block, so that no wait states are inserted between the four
+      asm volatile(
+          "s_nop 1\n\t"
+          "v_fmac_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0] row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1] row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2] row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %1, %5 quad_perm:[3,3,3,3] row_mask:0xf bank_mask:0xf"
+          : "+v"(acc1) : "v"(xh), "v"(w1[0]), "v"(w1[1]), "v"(w1[2]), "v"(w1[3]));
+      const float h1 = tanh_f(acc1);
+      // layer 2: four interleaved chains (P, Q for even and odd rotations) so that no
+      // accumulator is read by the instruction right after the one that wrote it
+      float P = __builtin_fmaf(wP[0], h1, bP);
+      float Q = __builtin_fmaf(wQ[0], h1, bQ);
+      float P2 = wP[1] * dpp_f<kRowRor + 1>(h1);
+      float Q2 = wQ[1] * dpp_f<kRowRor + 1>(h1);
+      // rotations 2..15 in one asm block (no wait states inserted between them); the
+      // DPP source h1 was written two instructions before (the nop covers the hazard)
+      asm volatile(
+          "s_nop 1\n\t"
+          "v_fmac_f32_dpp %0, %4, %5 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %6 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %7 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %8 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %4, %9 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %10 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %11 row_ror:5 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %12 row_ror:5 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %4, %13 row_ror:6 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %14 row_ror:6 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %15 row_ror:7 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %16 row_ror:7 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %4, %17 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %18 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %19 row_ror:9 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %20 row_ror:9 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %4, %21 row_ror:10 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %22 row_ror:10 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %23 row_ror:11 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %24 row_ror:11 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %4, %25 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %26 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %27 row_ror:13 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %28 row_ror:13 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %0, %4, %29 row_ror:14 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %1, %4, %30 row_ror:14 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %2, %4, %31 row_ror:15 row_mask:0xf bank_mask:0xf\n\t"
+          "v_fmac_f32_dpp %3, %4, %32 row_ror:15 row_mask:0xf bank_mask:0xf"
+          : "+v"(P), "+v"(Q), "+v"(P2), "+v"(Q2)
+          : "v"(h1), "v"(wP[2]), "v"(wQ[2]), "v"(wP[3]), "v"(wQ[3]), "v"(wP[4]), "v"(wQ[4]), "v"(wP[5]), "v"(wQ[5]), "v"(wP[6]), "v"(wQ[6]), "v"(wP[7]), "v"(wQ[7]), "v"(wP[8]), "v"(wQ[8]), "v"(wP[9]), "v"(wQ[9]), "v"(wP[10]), "v"(wQ[10]), "v"(wP[11]), "v"(wQ[11]), "v"(wP[12]), "v"(wQ[12]), "v"(wP[13]), "v"(wQ[13]), "v"(wP[14]), "v"(wQ[14]), "v"(wP[15]), "v"(wQ[15]));
+      P = P + P2;
+      Q = Q + Q2;
+      swap_rows(P, Q);                    // row 0: (P0, P1) -> out c;  row 1: (Q0, Q1) -> out 16+c
+      const float h2 = tanh_f(P + Q);
+      // layer 3: reduce-scatter of the four outputs over the row
+      const float a0 = w3[0] * h2, a1 = w3[1] * h2, a2 = w3[2] * h2, a3 = w3[3] * h2;
+      const float send0 = bit0 ? a0 : a1, keep0 = bit0 ? a1 : a0;
+      const float send1 = bit0 ? a2 : a3, keep1 = bit0 ? a3 : a2;
+      const float g0 = keep0 + dpp_f<kQuadXor1>(send0);        // output bit0
+      const float g1 = keep1 + dpp_f<kQuadXor1>(send1);        // output 2 + bit0
+      const float send2 = bit1 ? g0 : g1, keep2 = bit1 ? g1 : g0;
+      f = keep2 + dpp_f<kQuadXor2>(send2);                     // output lane & 3
+      f = f + dpp_f<kRowRor + 8>(f);
+      f = f + dpp_f<kRowRor + 4>(f);
+      f = add_rows(f) + b3c;
+    }
     xd.add(a.dt * f);
     if (c32 < 4) sX[slot * T4 * 4 + (t + 1) * 4 + c32] = xd.value();
     u = u_next;
@@ -389,11 +420,13 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   for (int o = threadIdx.x; o < 2 * T; o += kWaveBlock)
     N_lds[o] = ((red[o] + red[eStrideRed + o]) + red[2 * eStrideRed + o]) + red[3 * eStrideRed + o];
   const float eta = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
-  finish_iteration<kWaveBlock>(a, blockIdx.x, rho, eta, N_lds, red);
+  finish_iteration<kWaveBlock, MODEL>(a, blockIdx.x, rho, eta, N_lds, red);
 }
 
-template __global__ void rollout_wave_kernel<32, 4>(RolloutArgs);
-template __global__ void rollout_wave_kernel<32, 8>(RolloutArgs);
+template __global__ void rollout_wave_kernel<32, 4, kModelNet>(RolloutArgs);
+template __global__ void rollout_wave_kernel<32, 8, kModelNet>(RolloutArgs);
+template __global__ void rollout_wave_kernel<32, 4, kModelBasis>(RolloutArgs);
+template __global__ void rollout_wave_kernel<32, 8, kModelBasis>(RolloutArgs);
 
 // Dynamic LDS bytes the wave kernel needs for horizon T.
 size_t wave_smem_bytes(int T) {

@@ -20,7 +20,7 @@
 
 namespace mppi {
 hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
-template <int HID, int NQ> __global__ void rollout_wave_kernel(RolloutArgs);
+template <int HID, int NQ, int MODEL> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T);
 size_t wide_smem_bytes(int T);
 template <int NQ> __global__ void rollout_wide_kernel(RolloutArgs);
@@ -57,6 +57,7 @@ constexpr int32_t kMaxK = 1 << 22;
 // Automatic schedule: 32 lanes per sample while that still fits the chip in a few
 // waves per SIMD (latency-bound regime), one lane per sample beyond.
 constexpr int32_t kWaveAutoMaxK = 12288;   // AUTO: WAVE up to here, QUAD above
+constexpr int kNumBasisHost = 25;          // basis functions of the basis-function model
 
 struct PendingTiming {
   hipEvent_t e0, e1;
@@ -70,6 +71,8 @@ struct mppi_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int hidden = 0;
+  int model = kModelNet;     // kModelNet or kModelBasis (set by the last set_*dynamics call)
+  size_t n_params = 0;       // floats in d_params
   bool have_map = false, have_dyn = false;
   int H = 0, W = 0;
   float ox = 0, oy = 0, res = 1;
@@ -274,10 +277,18 @@ int blocks_for(const mppi_ctx* c, int sched) {
 // The wave kernel keeps each lane's share of the steps (ceil(T/32) of them) in
 // registers; it is compiled for up to 4 (T <= 128) and up to 8 (T <= 256).
 void launch_wave(int G, int T, hipStream_t stream, const RolloutArgs& a) {
-  if (T <= 128)
-    hipLaunchKernelGGL((rollout_wave_kernel<32, 4>), dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), stream, a);
-  else
-    hipLaunchKernelGGL((rollout_wave_kernel<32, 8>), dim3(G), dim3(kWaveBlockThreads), wave_smem_bytes(T), stream, a);
+  const size_t smem = wave_smem_bytes(T);
+  if (a.model == kModelBasis) {
+    if (T <= 128)
+      hipLaunchKernelGGL((rollout_wave_kernel<32, 4, kModelBasis>), dim3(G), dim3(kWaveBlockThreads), smem, stream, a);
+    else
+      hipLaunchKernelGGL((rollout_wave_kernel<32, 8, kModelBasis>), dim3(G), dim3(kWaveBlockThreads), smem, stream, a);
+  } else {
+    if (T <= 128)
+      hipLaunchKernelGGL((rollout_wave_kernel<32, 4, kModelNet>), dim3(G), dim3(kWaveBlockThreads), smem, stream, a);
+    else
+      hipLaunchKernelGGL((rollout_wave_kernel<32, 8, kModelNet>), dim3(G), dim3(kWaveBlockThreads), smem, stream, a);
+  }
 }
 
 // The wide kernel keeps ceil(T/64) steps per lane in registers: up to 2 (T <= 128)
@@ -343,6 +354,7 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   a.nk.iter = c->iter;
   a.iter_dev = c->d_iter;
   a.hidden = c->hidden;
+  a.model = c->model;
   a.recede = 0;
   a.u0_out = nullptr;
   a.x_copy = nullptr;
@@ -390,12 +402,15 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
     HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
   }
   if (sched == MPPI_SCHED_WAVE) {
-    if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
+    if (c->model == kModelNet && c->hidden != 32)
+      return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
     launch_wave(G, c->cfg.T, c->stream, a);
   } else if (sched == MPPI_SCHED_WIDE) {
-    if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "wide schedule supports hidden 32 only");
+    if (c->model != kModelNet || c->hidden != 32)
+      return fail(c, MPPI_E_INVAL, "wide schedule supports the h = 32 network only");
     launch_wide(G, c->cfg.T, c->stream, a);
   } else if (sched == MPPI_SCHED_QUAD) {
+    if (c->model != kModelNet) return fail(c, MPPI_E_INVAL, "quad schedule supports the network only");
     launch_quad(c->cfg.precision, c->hidden, G, c->stream, a);
   } else {
     HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
@@ -443,13 +458,33 @@ mppi_status guarded(mppi_ctx* c, F&& fn) {
 mppi_status launch_plant(mppi_ctx* c, const float* x_in_dev, const float* u_dev, float* x_out_dev,
                          float* x_copy_dev) {
   const mppi_config& g = c->cfg;
-  if (c->hidden == 32)
+  if (c->model == kModelBasis)
+    hipLaunchKernelGGL(plant_kernel<0>, dim3(1), dim3(64), 0, c->stream, c->d_params, x_in_dev, u_dev,
+                       x_out_dev, x_copy_dev, g.dt, g.u_lo[0], g.u_lo[1], g.u_hi[0], g.u_hi[1]);
+  else if (c->hidden == 32)
     hipLaunchKernelGGL(plant_kernel<32>, dim3(1), dim3(64), 0, c->stream, c->d_params, x_in_dev, u_dev,
                        x_out_dev, x_copy_dev, g.dt, g.u_lo[0], g.u_lo[1], g.u_hi[0], g.u_hi[1]);
   else
     hipLaunchKernelGGL(plant_kernel<64>, dim3(1), dim3(64), 0, c->stream, c->d_params, x_in_dev, u_dev,
                        x_out_dev, x_copy_dev, g.dt, g.u_lo[0], g.u_lo[1], g.u_hi[0], g.u_hi[1]);
   HIP_TRY(c, hipGetLastError());
+  return MPPI_OK;
+}
+
+// Copies n parameter floats to the device (reallocating when the count changes) and
+// marks the dynamics as set.  Synchronises.
+mppi_status upload_params(mppi_ctx* c, const float* params, size_t n) {
+  if (c->d_params && c->n_params != n) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipFree(c->d_params));
+    c->d_params = nullptr;
+  }
+  if (!c->d_params) HIP_TRY(c, hipMalloc(&c->d_params, sizeof(float) * n));
+  c->n_params = n;
+  HIP_TRY(c, hipMemcpyAsync(c->d_params, params, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->objective_ready = false;
+  c->have_dyn = true;
   return MPPI_OK;
 }
 
@@ -590,6 +625,27 @@ mppi_status mppi_set_costmap(mppi_ctx* c, const float* map, int32_t H, int32_t W
   });
 }
 
+mppi_status mppi_set_basis_dynamics(mppi_ctx* c, const float* theta) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!theta) return fail(c, MPPI_E_INVAL, "theta is NULL");
+    if (c->cfg.precision != MPPI_PREC_FP32)
+      return fail(c, MPPI_E_INVAL, "the basis-function model runs in FP32 (precision must be FP32)");
+    if (c->cfg.schedule == MPPI_SCHED_WIDE || c->cfg.schedule == MPPI_SCHED_QUAD)
+      return fail(c, MPPI_E_INVAL, "the basis-function model runs on the lane and wave schedules");
+    const size_t n = (size_t)kNumBasisHost * 4;
+    for (size_t i = 0; i < n; ++i)
+      if (!finite(theta[i])) return fail(c, MPPI_E_INVAL, "Theta entry %zu is not finite", i);
+    HIP_TRY(c, hipSetDevice(c->device));
+    mppi_status st = upload_params(c, theta, n);
+    if (st != MPPI_OK) return st;
+    c->model = kModelBasis;
+    if (c->cfg.schedule == MPPI_SCHED_AUTO)
+      c->schedule = c->cfg.K <= kWaveAutoMaxK ? MPPI_SCHED_WAVE : MPPI_SCHED_LANE;
+    return MPPI_OK;
+  });
+}
+
 mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* params) {
   if (!c) return MPPI_E_INVAL;
   return guarded(c, [&]() -> mppi_status {
@@ -605,17 +661,10 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     for (size_t i = 0; i < n; ++i)
       if (!finite(params[i])) return fail(c, MPPI_E_INVAL, "parameter %zu is not finite", i);
     HIP_TRY(c, hipSetDevice(c->device));
-    if (c->d_params && c->hidden != h) {
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      HIP_TRY(c, hipFree(c->d_params));
-      c->d_params = nullptr;
-    }
-    if (!c->d_params) HIP_TRY(c, hipMalloc(&c->d_params, sizeof(float) * n));
-    HIP_TRY(c, hipMemcpyAsync(c->d_params, params, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->objective_ready = false;
+    mppi_status st = upload_params(c, params, n);
+    if (st != MPPI_OK) return st;
     c->hidden = h;
-    c->have_dyn = true;
+    c->model = kModelNet;
     if (c->cfg.schedule == MPPI_SCHED_AUTO) {
       // measured on MI355X at T = 100: the 32-lane schedule is fastest while the chains
       // are few (latency-bound), the matrix-core quad schedule once K fills the device
@@ -863,7 +912,8 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
       if (!finite(x0[i])) return fail(c, MPPI_E_INVAL, "x0[%d] is not finite", i);
     if (ckpt_every < 1 || ckpt_every > 16) return fail(c, MPPI_E_INVAL, "ckpt_every=%d outside [1, 16]", ckpt_every);
     if (!c->have_map || !c->have_dyn) return fail(c, MPPI_E_STATE, "set the cost map and the dynamics first");
-    if (c->hidden != 32) return fail(c, MPPI_E_INVAL, "the objective gradient supports h = 32 only");
+    if (c->model != kModelNet || c->hidden != 32)
+      return fail(c, MPPI_E_INVAL, "the objective gradient supports the h = 32 network only");
     if (c->cfg.explore != 0.0f)
       return fail(c, MPPI_E_INVAL, "the objective is defined for importance samples only (explore = 0)");
     if (c->cfg.weighting != MPPI_WEIGHTS_IT)
@@ -1057,6 +1107,7 @@ std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
     a.sg_window = b->cfg.sg_window;
     a.update_U = 1;
     a.hidden = 32;
+    a.model = kModelNet;
     a.iter_dev = b->d_iter + i;
     a.ckpt = nullptr;
     a.ckpt_every = 1;

@@ -45,6 +45,11 @@ struct CostArgs {
 };
 
 // One rollout launch: K samples, T steps, from x0 (by value, or read from x0_dev).
+// Dynamics models: the 6-h-h-4 tanh network, or the basis-function model.
+constexpr int kModelNet = 0;
+constexpr int kModelBasis = 1;
+constexpr int kModelAny = -1;   // a kernel that serves either model (chosen by RolloutArgs::model)
+
 struct RolloutArgs {
   const float* U;          // [T][2] nominal controls
   const float* map;        // [H][W]
@@ -79,6 +84,7 @@ struct RolloutArgs {
   NoiseKey nk;
   CostArgs cost;
   int hidden;              // network width (32 or 64)
+  int model;               // kModelNet (params = packed network) or kModelBasis (params = Theta[25][4])
   // Receding-horizon step (recede = 1): after the update the final merge also shifts U
   // (u_0 out, u_{t-1} <- u_t, u_{T-1} <- 0) and advances the plant x <- F(x, g(u_0)) in
   // place in x0_dev.

@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_N
 # Every function the header declares; tests check that the library exports each.
 EXPORTED = [
     "mppi_create", "mppi_destroy", "mppi_last_error", "mppi_set_costmap", "mppi_set_dynamics",
+    "mppi_set_basis_dynamics",
     "mppi_set_controls", "mppi_iterate", "mppi_iterate_device", "mppi_get_controls", "mppi_shift",
     "mppi_plant_step", "mppi_run_receding", "mppi_step_device", "mppi_get_stats", "mppi_get_noise",
     "mppi_get_iteration", "mppi_set_iteration", "mppi_get_schedule", "mppi_set_timing",
@@ -78,6 +79,7 @@ def lib() -> C.CDLL:
         L.mppi_last_error.restype = C.c_char_p
         L.mppi_set_costmap.argtypes = [vp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float]
         L.mppi_set_dynamics.argtypes = [vp, C.POINTER(C.c_int32), fp]
+        L.mppi_set_basis_dynamics.argtypes = [vp, fp]
         L.mppi_set_controls.argtypes = [vp, fp]
         L.mppi_iterate.argtypes = [vp, fp, fp]
         L.mppi_iterate_device.argtypes = [vp, vp]
@@ -165,6 +167,13 @@ def mppi_set_dynamics(ctx, hidden: int, params) -> None:
     dims = (C.c_int32 * 4)(6, hidden, hidden, 4)
     p = _f32(params)
     _check(ctx, lib().mppi_set_dynamics(ctx, dims, _fp(p)))
+
+
+def mppi_set_basis_dynamics(ctx, theta) -> None:
+    t = _f32(theta).reshape(-1)
+    if t.size != 100:
+        raise ValueError("Theta must hold 25 x 4 entries")
+    _check(ctx, lib().mppi_set_basis_dynamics(ctx, _fp(t)))
 
 
 def mppi_set_controls(ctx, U) -> None:
@@ -447,7 +456,11 @@ class Controller:
                                current_stream() if stream is None else stream)
         try:
             mppi_set_costmap(self.ctx, cmap.data, cmap.origin_x, cmap.origin_y, cmap.resolution)
-            mppi_set_dynamics(self.ctx, self.hidden, params)
+            self.model = int(getattr(prob, "model", 0))
+            if self.model == 1:
+                mppi_set_basis_dynamics(self.ctx, params)
+            else:
+                mppi_set_dynamics(self.ctx, self.hidden, params)
         except Exception:
             self.close()
             raise
@@ -505,6 +518,11 @@ class Controller:
 
     def set_dynamics(self, params):
         mppi_set_dynamics(self.ctx, self.hidden, params)
+        self.model = 0
+
+    def set_basis_dynamics(self, theta):
+        mppi_set_basis_dynamics(self.ctx, theta)
+        self.model = 1
 
     def objective(self, x0, it: int, ckpt_every: int = 10, want_costs: bool = False):
         return mppi_objective(self.ctx, x0, it, ckpt_every, self.K if want_costs else None)
