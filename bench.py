@@ -34,11 +34,13 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector (and FP32 matri
 PEAK_BF16_TFLOPS = 2500.0         # MI355X published dense BF16/FP16 matrix peak
 VALU_LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one FP32 op per lane per cycle
 TRAFFIC_FILE = ROOT / "profiles" / "rollout_wave_k1920_t100_traffic.json"
-# the sources the benchmarked kernel (rollout_wave_kernel<32, 4>) is built from: stored
+# the sources the benchmarked kernel (rollout_wave_kernel<32, 4, 0>) is built from: stored
 # counter readings are used only while these files are unchanged
 KERNEL_SOURCES = ["kernels_wave.hip", "wave_common.hip.h", "kernels_common.hip.h", "device_common.h",
                   "mppi_types.h"]
 NET_FLOP_PER_STEP = {32: 2 * (6 * 32 + 32 * 32 + 32 * 4), 64: 2 * (6 * 64 + 64 * 64 + 64 * 4)}
+# basis-function model: Theta^T phi (25 x 4 multiply-adds) plus about 40 operations forming phi
+BASIS_FLOP_PER_STEP = 2 * 25 * 4 + 40
 
 
 def parse():
@@ -109,7 +111,7 @@ def write_traffic(pmc_dir: str):
         vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(f)) if match(r["Kernel_Name"])]
         return float(np.median(vals)), len(vals)
 
-    is_roll = lambda n: "rollout_wave_kernel<32, 4>" in n
+    is_roll = lambda n: "rollout_wave_kernel<32, 4, 0>" in n
     is_copy = lambda n: "copyBuffer" in n or "elementwise" in n
     fetch, nf = per_dispatch("FETCH_SIZE", is_roll)
     write, nw = per_dispatch("WRITE_SIZE", is_roll)
@@ -120,16 +122,16 @@ def write_traffic(pmc_dir: str):
     kib = COPY_BYTES / 1024.0
     fetch_scale = kib / largest("FETCH_SIZE_copy")
     write_scale = kib / largest("WRITE_SIZE_copy")
-    rec = {"kernel": "rollout_wave_kernel<32, 4>",
+    rec = {"kernel": "rollout_wave_kernel<32, 4, 0>",
            "workload": "K=1920, T=100, 6-32-32-4 network, 2048x2048 map (bench.py default)",
            "sources_sha256": kernel_sources_sha256(),
            "fetch_size_kib_per_launch_median": fetch, "fetch_dispatches": nf, "fetch_scale": fetch_scale,
            "write_size_kib_per_launch_median": write, "write_dispatches": nw, "write_scale": write_scale,
            "traffic_bytes_per_launch": (fetch * fetch_scale + write * write_scale) * 1024.0,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/FETCH_SIZE -o c2 -- "
-                        "python3 bench.py --steps 20 --warmup 5 --no-cpu --no-forms --latency-iters 5",
+                        "python3 bench.py --steps 100 --warmup 5 --no-cpu --no-forms --latency-iters 5",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/WRITE_SIZE -o c2 -- "
-                        "python3 bench.py --steps 20 --warmup 5 --no-cpu --no-forms --latency-iters 5",
+                        "python3 bench.py --steps 100 --warmup 5 --no-cpu --no-forms --latency-iters 5",
                         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/FETCH_SIZE_copy -o copy -- "
                         "python3 bench.py --calibrate-copy",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/WRITE_SIZE_copy -o copy -- "
@@ -183,7 +185,8 @@ def measure_forms(M, stream, iters: int = 30):
       with checkpoints every 10 steps;
     exploration: the paper-shaped receding-horizon step with the parameter table's
       lambda, gamma and Sigma and 1 % of the samples drawn around zero;
-    cem: the same step with Algorithm 3's weights (the best 20 % averaged)."""
+    cem: the same step with Algorithm 3's weights (the best 20 % averaged);
+    basis: the paper-shaped step with the basis-function model."""
     import torch
     import synth
     out = {}
@@ -259,8 +262,12 @@ def measure_forms(M, stream, iters: int = 30):
              "receding horizon, 2048x2048 map"),
             ("cem", synth.cem_problem(seed=0),
              "Algorithm 3 weights (384 elite of K=1920), T=100, gamma=0.1, Sigma=Diag(0.0306, 0.0506), "
+             "receding horizon, 2048x2048 map"),
+            ("basis", synth.basis_problem(seed=0),
+             "basis-function model (25 bases, synthetic Theta) in place of the network, K=1920, T=100, "
              "receding horizon, 2048x2048 map")):
-        with M.Controller(prob, emap, synth.mlp_params(32, 0), stream=int(stream.cuda_stream)) as c:
+        params = synth.basis_theta(0) if prob.model == 1 else synth.mlp_params(32, 0)
+        with M.Controller(prob, emap, params, stream=int(stream.cuda_stream)) as c:
             M.mppi_run_receding(c.ctx, synth.C2_X0, 20)
             torch.cuda.synchronize()
             n_blk = 3
@@ -276,7 +283,8 @@ def measure_forms(M, stream, iters: int = 30):
             M.mppi_set_timing(c.ctx, False)
         st = prob.K * prob.T / (ms * 1e-3)
         launch_ms = float(np.mean(launch))
-        tf = NET_FLOP_PER_STEP[32] * prob.K * prob.T / (launch_ms * 1e-3) / 1e12
+        flop = BASIS_FLOP_PER_STEP if prob.model == 1 else NET_FLOP_PER_STEP[32]
+        tf = flop * prob.K * prob.T / (launch_ms * 1e-3) / 1e12
         out[name] = {"ms_per_step": ms, "steps_per_s": st, "schedule": sched,
                      "launch_us": {"mean": launch_ms * 1e3, "p50": float(np.percentile(launch, 50)) * 1e3,
                                    "p99": float(np.percentile(launch, 99)) * 1e3},
