@@ -23,10 +23,13 @@
 //                and 2) leaves output (lane & 3) in every lane, and a second
 //                permlane16 swap adds the two rows;
 //       update:  x_d += dt f in compensated (two-sum) form, one component per lane;
-//     with the basis-function model (MODEL = kModelBasis) the four components reach
-//     every lane of the quad through quad_perm DPP moves, every lane forms the 25
-//     basis functions and lane (component c) sums Theta[i][c] phi_i for its own
-//     output: no cross-lane reduction is needed;
+//     with the basis-function model (MODEL = kModelBasis) phase A also forms, for
+//     each of the lane's steps, everything that depends on the control alone (sin and
+//     tan of the steering and the four basis functions of the throttle and steering
+//     only, times Theta) into LDS; in the chain the four state components reach every
+//     lane of the quad through quad_perm DPP moves, every lane forms the 21 raw products
+//     of the state (normalisers folded into its column of Theta) and lane (component c)
+//     sums its own output: no cross-lane reduction and no transcendental on the chain;
 //  C. kinematics and cost, lane-parallel over t: theta and the position are prefix
 //     sums of their Euler increments (scans across the 32 lanes), then the cost at
 //     every post-step state and the control-cost term, summed over t;
@@ -50,6 +53,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   float* sX = sE + kWaveSlots * ((2 * T + 3) & ~3);  // [8][T4][4]
   float* red = sX + kWaveSlots * T4 * 4;             // [4][2T]
   float* scratch = red + 4 * ((2 * T + 3) & ~3);     // [16]
+  float* sB = scratch + 16;                          // basis model: [8][T][8] control terms
   const int eStride = (2 * T + 3) & ~3;
 
   const int lane = threadIdx.x & 63;
@@ -101,10 +105,19 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
 #pragma unroll
   for (int o = 0; o < 4; ++o) w3[o] = kNet ? W3[o * HID + j] : 0.0f;
   const float b3c = kNet ? b3[comp] : 0.0f;
-  // basis-function model: this lane's column of Theta
-  float thc[kNumBasis];
+  // basis-function model: this lane's column of Theta with each basis function's
+  // normaliser folded in (the chain multiplies raw products such as sin(u_delta) tan(alpha_f))
+  constexpr int kRaw = 21;
+  constexpr int kRawIdx[kRaw] = {1, 2, 3, 4, 5, 6, 7, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22};
+  constexpr float kRawScale[kRaw] = {0.1f, 1.0f / 1200.0f, 1.0f / (1200.0f * 1200.0f),
+                                     1.0f / (1200.0f * 1200.0f * 1200.0f), 1.0f / 25.0f, 0.1f, 0.1f,
+                                     1.0f / 40.0f, 1.0f / 1400.0f, 1.0f / (1400.0f * 1400.0f),
+                                     1.0f / (1400.0f * 1400.0f * 1400.0f), 1.0f / 40.0f,
+                                     1.0f / (40.0f * 40.0f), 1.0f / (40.0f * 40.0f * 40.0f), 1.0f / 50.0f,
+                                     1.0f, 1.0f, 1.0f / 3.0f, 0.2f, 0.01f, 0.001f};
+  float kc[kRaw];
 #pragma unroll
-  for (int i = 0; i < kNumBasis; ++i) thc[i] = kNet ? 0.0f : a.params[i * 4 + comp];
+  for (int i = 0; i < kRaw; ++i) kc[i] = kNet ? 0.0f : a.params[kRawIdx[i] * 4 + comp] * kRawScale[i];
   const bool bit0 = (lane & 1) != 0;
   const bool bit1 = (lane & 2) != 0;
 
@@ -134,6 +147,34 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       myE[2 * t + 1] = eb[i];
     }
   }
+  if constexpr (MODEL == kModelBasis) {
+    // the terms of each of the lane's steps that depend on the control alone:
+    // {sin u_delta, -tan u_delta, u_delta, 0} and, per output o, Theta[1][o] u_F
+    // + Theta[9][o] sin u_delta + Theta[24][o] u_F^2 + Theta[25][o] u_F^3
+    float* myB = sB + slot * T * 8;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int t = 32 * i + c32;
+      if (i < NT && t < T) {
+        const float u0 = a.U[2 * t], u1 = a.U[2 * t + 1];
+        const float vc0 = fminf(fmaxf(zm ? ea[i] : u0 + ea[i], a.u_lo0), a.u_hi0);
+        const float vc1 = fminf(fmaxf(zm ? eb[i] : u1 + eb[i], a.u_lo1), a.u_hi1);
+        const float sd = sinf(vc0);
+        const float ntd = -tanf(vc0);
+        const float u2 = vc1 * vc1, u3 = vc1 * u2;
+        float c[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          float acc = a.params[0 * 4 + o] * vc1;
+          acc = __builtin_fmaf(a.params[8 * 4 + o], sd, acc);
+          acc = __builtin_fmaf(a.params[23 * 4 + o], u2, acc);
+          c[o] = __builtin_fmaf(a.params[24 * 4 + o], u3, acc);
+        }
+        *reinterpret_cast<float4*>(myB + 8 * t) = make_float4(sd, ntd, vc0, 0.0f);
+        *reinterpret_cast<float4*>(myB + 8 * t + 4) = make_float4(c[0], c[1], c[2], c[3]);
+      }
+    }
+  }
   Acc xd{x0v[3 + comp], 0.0f};
   if (c32 < 4) sX[slot * T4 * 4 + c32] = x0v[3 + c32];
   if (a.ckpt && valid && c32 < kStateDim)
@@ -144,6 +185,14 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   {
   float2 u = *reinterpret_cast<const float2*>(sU);
   float2 e = *reinterpret_cast<const float2*>(myE);
+  // basis model: this step's control terms, also read one step ahead
+  const float* myB = sB + slot * T * 8;
+  float4 bq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float cq = 0.0f;
+  if constexpr (MODEL == kModelBasis) {
+    bq = *reinterpret_cast<const float4*>(myB);
+    cq = myB[4 + comp];
+  }
   for (int t = 0; t < T; ++t) {
     // next step's control and noise are read one step ahead (LDS latency off the chain)
     const int tn = min(t + 1, T - 1);
@@ -153,23 +202,35 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     const float vc1 = fminf(fmaxf(zm ? e.y : u.y + e.y, a.u_lo1), a.u_hi1);
     float f;
     if constexpr (MODEL == kModelBasis) {
+      // bq = {sin u_delta, -tan u_delta, u_delta, 0}, cq = the control-only terms
+      const float4 bq_next = *reinterpret_cast<const float4*>(myB + 8 * tn);
+      const float cq_next = myB[8 * tn + 4 + comp];
       const float xh = xd.hi;
       const float roll = dpp_f<0x00>(xh), vx = dpp_f<0x55>(xh);   // quad_perm:[i,i,i,i]
       const float vy = dpp_f<0xAA>(xh), om = dpp_f<0xFF>(xh);
-      const float sd = sinf(vc0);
-      float td = 0.0f;
-      if (!(vx > 0.1f)) td = tanf(vc0);
-      float phi[kNumBasis];
-      basis_phi(roll, vx, vy, om, vc1, sd, td, vc0, phi);
-      float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+      // tyre tangents: tan(arctan z) = z above v_x = 0.1, the steering alone below
+      const bool mv = vx > 0.1f;
+      const float rv = __builtin_amdgcn_rcpf(vx);
+      const float q = vy * rv, w = om * rv;
+      const float tf = mv ? __builtin_fmaf(0.45f, w, q) - bq.z : bq.y;
+      const float tr = mv ? __builtin_fmaf(-0.35f, w, q) : 0.0f;
+      const float qq = mv ? q : 0.0f;
+      const float sf = bq.x * tf, tf2 = tf * tf, tr2 = tr * tr;
+      const float atf = fabsf(tf), atr = fabsf(tr);
+      const float rx = roll * vx, vx2 = vx * vx;
+      const float raw[kRaw] = {vx, sf, sf * atf, sf * tf2, om * vy, om, vy, qq, tf, tf * atf, tf * tf2,
+                               tr, tr * atr, tr * tr2, om * vx, roll, roll * om, rx, rx * om, vx2, vx * vx2};
+      float p0 = cq, p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
 #pragma unroll
-      for (int i = 0; i < kNumBasis; i += 4) {
-        p0 = __builtin_fmaf(thc[i], phi[i], p0);
-        if (i + 1 < kNumBasis) p1 = __builtin_fmaf(thc[i + 1], phi[i + 1], p1);
-        if (i + 2 < kNumBasis) p2 = __builtin_fmaf(thc[i + 2], phi[i + 2], p2);
-        if (i + 3 < kNumBasis) p3 = __builtin_fmaf(thc[i + 3], phi[i + 3], p3);
+      for (int i = 0; i < kRaw; i += 4) {
+        p0 = __builtin_fmaf(kc[i], raw[i], p0);
+        if (i + 1 < kRaw) p1 = __builtin_fmaf(kc[i + 1], raw[i + 1], p1);
+        if (i + 2 < kRaw) p2 = __builtin_fmaf(kc[i + 2], raw[i + 2], p2);
+        if (i + 3 < kRaw) p3 = __builtin_fmaf(kc[i + 3], raw[i + 3], p3);
       }
       f = (p0 + p1) + (p2 + p3);
+      bq = bq_next;
+      cq = cq_next;
     } else {
       // layer 1
       float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
@@ -429,10 +490,11 @@ template __global__ void rollout_wave_kernel<32, 4, kModelBasis>(RolloutArgs);
 template __global__ void rollout_wave_kernel<32, 8, kModelBasis>(RolloutArgs);
 
 // Dynamic LDS bytes the wave kernel needs for horizon T.
-size_t wave_smem_bytes(int T) {
+size_t wave_smem_bytes(int T, int model) {
   const size_t e = (size_t)((2 * T + 3) & ~3);
   const size_t T4 = (size_t)((T + 4) & ~3);
-  return sizeof(float) * (e + kWaveSlots * e + kWaveSlots * T4 * 4 + 4 * e + 16);
+  const size_t basis = model == kModelBasis ? (size_t)kWaveSlots * T * 8 : 0;
+  return sizeof(float) * (e + kWaveSlots * e + kWaveSlots * T4 * 4 + 4 * e + 16 + basis);
 }
 
 }  // namespace mppi

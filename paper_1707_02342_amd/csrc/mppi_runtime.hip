@@ -21,7 +21,7 @@
 namespace mppi {
 hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
 template <int HID, int NQ, int MODEL> __global__ void rollout_wave_kernel(RolloutArgs);
-size_t wave_smem_bytes(int T);
+size_t wave_smem_bytes(int T, int model);
 size_t wide_smem_bytes(int T);
 template <int NQ> __global__ void rollout_wide_kernel(RolloutArgs);
 template <int PREC, int HID> __global__ void rollout_quad_kernel(RolloutArgs);
@@ -277,7 +277,7 @@ int blocks_for(const mppi_ctx* c, int sched) {
 // The wave kernel keeps each lane's share of the steps (ceil(T/32) of them) in
 // registers; it is compiled for up to 4 (T <= 128) and up to 8 (T <= 256).
 void launch_wave(int G, int T, hipStream_t stream, const RolloutArgs& a) {
-  const size_t smem = wave_smem_bytes(T);
+  const size_t smem = wave_smem_bytes(T, a.model);
   if (a.model == kModelBasis) {
     if (T <= 128)
       hipLaunchKernelGGL((rollout_wave_kernel<32, 4, kModelBasis>), dim3(G), dim3(kWaveBlockThreads), smem, stream, a);
