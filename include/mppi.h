@@ -156,6 +156,12 @@ mppi_status mppi_set_dynamics(mppi_ctx* ctx, const int32_t dims[4], const float*
  * differentiation form (mppi_objective) and the batched form use the network only. */
 mppi_status mppi_set_basis_dynamics(mppi_ctx* ctx, const float* theta);
 
+/* The cost map h at n world positions xy ([n][2] (p_x, p_y), host) into h_out ([n],
+ * host), with the rollout kernels' bilinear interpolation (for closed-loop evaluation:
+ * where an executed trajectory left the track).  Synchronises.  INVAL: NULL pointers,
+ * n outside [0, 1<<24] or a non-finite position.  STATE: no cost map set. */
+mppi_status mppi_costmap_values(mppi_ctx* ctx, const float* xy, int32_t n, float* h_out);
+
 /* Replace the nominal control sequence U ([T][2], steer/throttle per step).  Copied. */
 mppi_status mppi_set_controls(mppi_ctx* ctx, const float* U);
 

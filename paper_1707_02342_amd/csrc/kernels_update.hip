@@ -74,6 +74,14 @@ template __global__ void plant_kernel<32>(const float*, const float*, const floa
 template __global__ void plant_kernel<64>(const float*, const float*, const float*, float*, float*,
                                           float, float, float, float, float);
 
+// The cost map h at n world positions xy[n][2], with the rollout kernels' interpolation.
+__global__ __launch_bounds__(256) void costmap_kernel(CostArgs c, const float* __restrict__ map,
+                                                      const float* __restrict__ xy, int n, float* h) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  h[i] = costmap_at2(c, map, xy[2 * i], 0.0f, xy[2 * i + 1], 0.0f);
+}
+
 // The rollout kernels' perturbations for one iteration, written out ([K][T][2]).
 __global__ __launch_bounds__(256) void noise_kernel(NoiseKey nk, int K, int T, float* eps) {
   const int idx = blockIdx.x * 256 + threadIdx.x;

@@ -30,6 +30,7 @@ template <int HID>
 __global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
                              float, float, float);
 __global__ void noise_kernel(NoiseKey, int, int, float*);
+__global__ void costmap_kernel(CostArgs, const float*, const float*, int, float*);
 __global__ void adjoint_wave_kernel(AdjointArgs);
 template <int NCOL> __global__ void cem_update_kernel(RolloutArgs);
 constexpr int kCemBlockThreads = 1024;
@@ -753,6 +754,33 @@ mppi_status mppi_plant_step(mppi_ctx* c, const float x[7], const float u[2], flo
     if (st != MPPI_OK) return st;
     HIP_TRY(c, hipMemcpyAsync(x_out, c->d_x, 7 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_costmap_values(mppi_ctx* c, const float* xy, int32_t n, float* h_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!xy || !h_out || n < 0 || n > (1 << 24)) return fail(c, MPPI_E_INVAL, "bad xy, h_out or n");
+    if (!c->have_map) return fail(c, MPPI_E_STATE, "set the cost map first");
+    for (int i = 0; i < 2 * n; ++i)
+      if (!finite(xy[i])) return fail(c, MPPI_E_INVAL, "position %d is not finite", i / 2);
+    if (n == 0) return MPPI_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    float* d = nullptr;
+    HIP_TRY(c, hipMalloc(&d, sizeof(float) * 3 * (size_t)n));
+    const RolloutArgs a = rollout_args(c, nullptr, nullptr);
+    hipError_t e = hipMemcpyAsync(d, xy, sizeof(float) * 2 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(costmap_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, a.cost, c->d_map, d, n,
+                         d + 2 * (size_t)n);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_out, d + 2 * (size_t)n, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(c, MPPI_E_DEVICE, "cost map lookup: %s", hipGetErrorString(e));
     return MPPI_OK;
   });
 }

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "MPPI_OK", 1: "MPPI_E_INVAL", 2: "MPPI_E_STATE", 3: "MPPI_E_N
 # Every function the header declares; tests check that the library exports each.
 EXPORTED = [
     "mppi_create", "mppi_destroy", "mppi_last_error", "mppi_set_costmap", "mppi_set_dynamics",
-    "mppi_set_basis_dynamics",
+    "mppi_set_basis_dynamics", "mppi_costmap_values",
     "mppi_set_controls", "mppi_iterate", "mppi_iterate_device", "mppi_get_controls", "mppi_shift",
     "mppi_plant_step", "mppi_run_receding", "mppi_step_device", "mppi_get_stats", "mppi_get_noise",
     "mppi_get_iteration", "mppi_set_iteration", "mppi_get_schedule", "mppi_set_timing",
@@ -80,6 +80,7 @@ def lib() -> C.CDLL:
         L.mppi_set_costmap.argtypes = [vp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float]
         L.mppi_set_dynamics.argtypes = [vp, C.POINTER(C.c_int32), fp]
         L.mppi_set_basis_dynamics.argtypes = [vp, fp]
+        L.mppi_costmap_values.argtypes = [vp, fp, C.c_int32, fp]
         L.mppi_set_controls.argtypes = [vp, fp]
         L.mppi_iterate.argtypes = [vp, fp, fp]
         L.mppi_iterate_device.argtypes = [vp, vp]
@@ -174,6 +175,13 @@ def mppi_set_basis_dynamics(ctx, theta) -> None:
     if t.size != 100:
         raise ValueError("Theta must hold 25 x 4 entries")
     _check(ctx, lib().mppi_set_basis_dynamics(ctx, _fp(t)))
+
+
+def mppi_costmap_values(ctx, xy) -> np.ndarray:
+    p = _f32(xy).reshape(-1, 2)
+    h = np.zeros(p.shape[0], dtype=np.float32)
+    _check(ctx, lib().mppi_costmap_values(ctx, _fp(p), p.shape[0], _fp(h)))
+    return h
 
 
 def mppi_set_controls(ctx, U) -> None:

@@ -62,9 +62,12 @@ def mlp_params(hidden: int = 32, seed: int = 0, bias_scale: float = 0.0) -> np.n
 # Basis-function model (appendix): Theta is [25][4], row i for basis function i + 1,
 # column o for d/dt of (roll, v_x, v_y, heading rate).  No system-identification data is
 # available, so Theta is synthetic: a damped, steerable base written in the appendix's
-# own terms (throttle drives v_x, the front and rear tyre terms tan(alpha) drive v_y and
-# the heading rate, rates are damped, roll relaxes) plus seeded N(0, noise^2) entries
-# scaled by each basis function's normaliser, so that every basis function contributes.
+# own terms (throttle drives v_x against linear and quadratic drag, the front and rear
+# tyre terms tan(alpha) drive v_y and the heading rate, rates are damped, roll relaxes)
+# plus seeded N(0, noise^2) entries scaled by each basis function's normaliser, so that
+# every basis function contributes.  The drag polynomial of v_x (basis functions 2, 22,
+# 23 in the v_x column) carries no noise, so that the top speed stays set by throttle
+# and drag (about 11 m/s at full throttle).
 N_BASIS = 25
 _BASIS_NORM = [1.0, 10.0, 1200.0, 1200.0 ** 2, 1200.0 ** 3, 25.0, 10.0, 10.0, 1.0, 40.0, 1400.0,
                1400.0 ** 2, 1400.0 ** 3, 40.0, 40.0 ** 2, 40.0 ** 3, 50.0, 1.0, 1.0, 3.0, 5.0, 100.0,
@@ -75,6 +78,7 @@ _BASIS_BASE = [(18, 0, -4.0), (17, 0, 0.04),
                (1, 1, 6.0), (2, 1, -0.3), (22, 1, -0.02), (6, 1, 1.0),
                (17, 2, -1.0), (8, 2, -2.0), (11, 2, -4.0), (14, 2, -3.0),
                (11, 3, -5.0), (14, 3, 3.0), (7, 3, -1.0)]
+_BASIS_QUIET = [(2, 1), (22, 1), (23, 1)]
 
 
 def basis_theta(seed: int = 0, noise: float = 0.05) -> np.ndarray:
@@ -82,6 +86,8 @@ def basis_theta(seed: int = 0, noise: float = 0.05) -> np.ndarray:
     rng = np.random.default_rng(20_000 + seed)
     norm = np.array(_BASIS_NORM)[:, None]
     theta = noise * rng.standard_normal((N_BASIS, 4)) * norm
+    for i, o in _BASIS_QUIET:
+        theta[i - 1, o] = 0.0
     for i, o, c in _BASIS_BASE:
         theta[i - 1, o] += c * _BASIS_NORM[i - 1]
     return theta.astype(np.float32)
