@@ -175,7 +175,7 @@ def _timed_iterations(ctl, x0, n, stream):
     return e0.elapsed_time(e1) / n          # ms per iteration
 
 
-def measure_forms(M, stream, iters: int = 30):
+def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
     """The three added forms on their own workloads (synthetic, seeded):
     precision: K=16384, T=100, 6-64-64-4 network, one iteration in FP32 (lane schedule)
       and with BF16 / FP16 matrix-core operands (FP32 accumulation);
@@ -186,7 +186,8 @@ def measure_forms(M, stream, iters: int = 30):
     exploration: the paper-shaped receding-horizon step with the parameter table's
       lambda, gamma and Sigma and 1 % of the samples drawn around zero;
     cem: the same step with Algorithm 3's weights (the best 20 % averaged);
-    basis: the paper-shaped step with the basis-function model."""
+    basis: the paper-shaped step with the basis-function model;
+    laps: closed-loop lap statistics (measure_laps)."""
     import torch
     import synth
     out = {}
@@ -291,7 +292,41 @@ def measure_forms(M, stream, iters: int = 30):
                      "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
                                   "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS},
                      "workload": desc}
+    out["laps"] = measure_laps(M, emap, n_counted=laps_per_setting)
     return out
+
+
+def measure_laps(M, emap, n_counted: int = 3):
+    """Table 3 in the synthetic setting: the IT and CEM controllers (parameter table,
+    basis-function model as both the controller's model and the plant) at speed targets
+    6, 8.5 and 11 m/s, counter-clockwise (CC) and clockwise (C), n_counted laps each
+    after a discarded first lap."""
+    import synth
+    from paper_1707_02342_amd import laps
+    rows = []
+    t0 = time.perf_counter()
+    steps = 0
+    for weighting, wname in ((0, "IT-MPC-BF"), (1, "CEM-BF")):
+        for v_des in (6.0, 8.5, 11.0):
+            for direction, dname in ((1, "CC"), (-1, "C")):
+                cost = synth.c2_cost()
+                cost.v_des = v_des
+                prob = synth.with_(synth.explore_problem(0), model=1, weighting=weighting, elite=0.8, cost=cost)
+                x0 = synth.ellipse_pose(0.0, 4.0)
+                if direction < 0:
+                    x0[2] += np.pi
+                with M.Controller(prob, emap, synth.basis_theta(0)) as c:
+                    m = laps.evaluate(c, x0, n_counted + 1, prob.dt, laps.Track(), direction,
+                                      prob.cost.map_thresh, max_steps=60_000)
+                steps += m["steps"]
+                rows.append({"setting": f"{wname} {v_des:g} m/s {dname}", "laps": m["laps"],
+                             "success_pct": m["success_pct"], "lap_time_s": m["lap_time_mean"],
+                             "lap_time_std_s": m["lap_time_std"], "speed_min": m["speed_min"],
+                             "speed_max": m["speed_max"]})
+    wall = time.perf_counter() - t0
+    return {"rows": rows, "control_steps": steps, "wall_s": wall,
+            "workload": "synthetic plant = the basis-function model, 2048x2048 elliptical track, K=1920, T=100, "
+                        "parameter table (lambda 12.5, gamma 0.1, Sigma Diag(0.0306, 0.0506), 1 % exploration)"}
 
 
 def main():
