@@ -58,11 +58,12 @@ __device__ __forceinline__ int cem_excl_sum(int v, int* s_w, int& total) {
 // NCOL: float2 columns per lane, 2 for T <= 128, 4 for T <= 256.
 template <int NCOL>
 __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
-  constexpr int kBatch = 16 / NCOL;   // rows per wave whose loads are in flight together
+  constexpr int kBatch = NCOL == 2 ? 12 : 4;   // rows per wave whose loads are in flight together
   __shared__ unsigned s_hist[256];
   __shared__ int s_w[kCemWaves];
   __shared__ unsigned s_red[3 * kCemWaves];
-  __shared__ unsigned s_sel[2];
+  __shared__ unsigned s_sel[4];
+  __shared__ unsigned s_cand[64];
   __shared__ int s_list[kCemChunk];
   __shared__ float s_part[kCemWaves][2 * kTMax];
   __shared__ float s_delta[2 * kTMax];
@@ -122,6 +123,7 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
   // 2. radix select of the zeff-th smallest key
   unsigned zkey = kInfKey;
   int need_eq = 0;
+  unsigned eq_total = 0u;   // keys equal to the threshold key
   if (zeff > 0) {
     const unsigned diff = kmin ^ kmax;
     int nb = diff ? 32 - __clz(diff) : 0;            // bits below the shared prefix
@@ -168,6 +170,8 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
           }
           s_sel[0] = b;
           s_sel[1] = r - before;
+          s_sel[2] = b == 4u * tid ? c0 : (b == 4u * tid + 1u ? c1 : (b == 4u * tid + 2u ? c2 : c3));
+          s_sel[3] = 0u;
         }
       }
       __syncthreads();
@@ -175,9 +179,42 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
       mask |= dmask << shift;
       r = s_sel[1];
       nb = shift;
+      if (nb > 0 && s_sel[2] <= 64u) {
+        // few keys left in the selected bin: rank them directly instead of more passes
+        for (int c = 0; c < nchunk; ++c) {
+          if (!resident) load_keys(c * kCemChunk);
+#pragma unroll
+          for (int i = 0; i < kCemKeys; ++i)
+            if ((key[i] & mask) == prefix) s_cand[atomicAdd(&s_sel[3], 1u)] = key[i];
+        }
+        __syncthreads();
+        if (tid < 64) {
+          const unsigned n = s_sel[3];
+          const unsigned my = tid < (int)n ? s_cand[tid] : kPadKey;
+          unsigned lt = 0u, le = 0u;
+          for (unsigned j = 0; j < n; ++j) {
+            const unsigned c = s_cand[j];
+            lt += c < my ? 1u : 0u;
+            le += c <= my ? 1u : 0u;
+          }
+          // every lane holding the selected key writes the same two values
+          if (tid < (int)n && lt < r && r <= le) {
+            s_sel[0] = my;
+            s_sel[1] = r - lt;
+            s_sel[2] = le - lt;
+          }
+        }
+        __syncthreads();
+        prefix = s_sel[0];
+        r = s_sel[1];
+        nb = 0;
+      }
     }
     zkey = prefix;
     need_eq = (int)r;
+    // the last pass (or the direct ranking) left the count of keys equal to zkey in s_sel[2];
+    // when the first pass already isolated one key value (nb = 0 from the start) count them
+    eq_total = diff ? s_sel[2] : nf;
   }
 
   // 3. elite rows, summed in list order per wave (compensated), chunk by chunk
@@ -192,15 +229,19 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
       int n_eq = 0;
 #pragma unroll
       for (int i = 0; i < kCemKeys; ++i) n_eq += key[i] == zkey ? 1 : 0;
-      int tot_eq, tot_el;
-      int eq_rank = eq_taken + cem_excl_sum(n_eq, s_w, tot_eq);
+      int tot_eq = 0, tot_el;
+      // when every key equal to the threshold is elite, no ranking among them is needed
+      int eq_rank = 0;
+      if (need_eq >= (int)eq_total) tot_eq = 0;
+      else eq_rank = eq_taken + cem_excl_sum(n_eq, s_w, tot_eq);
+      const bool all_eq = need_eq >= (int)eq_total;
       int n_el = 0;
       unsigned take = 0u;
 #pragma unroll
       for (int i = 0; i < kCemKeys; ++i) {
         bool el = key[i] < zkey;
         if (key[i] == zkey) {
-          el = eq_rank < need_eq;
+          el = all_eq || eq_rank < need_eq;
           ++eq_rank;
         }
         take |= el ? (1u << i) : 0u;
