@@ -275,7 +275,8 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
 // memory round trip with the merge's own; apply() then forms Delta = lds[0..2T) * scale,
 // smooths it, updates U, writes the statistics and the status, advances the iteration
 // counter and, in a receding step, shifts U and advances the plant.
-template <int NT, int MODEL = kModelNet>
+// RECEDE = false: a kernel that never runs a receding step (compiled out).
+template <int NT, int MODEL = kModelNet, bool RECEDE = true>
 struct FinalStage {
   static constexpr int kOut = (2 * kTMax + NT - 1) / NT;
   static constexpr int kTapReg = 16;
@@ -339,7 +340,9 @@ struct FinalStage {
       a.stats[1] = stat1;
       if (a.iter_dev) *a.iter_dev = *a.iter_dev + 1u;
     }
-    if (a.recede) receding_step<NT, kOut, MODEL>(a, u_new, lds);
+    if constexpr (RECEDE) {
+      if (a.recede) receding_step<NT, kOut, MODEL>(a, u_new, lds);
+    }
   }
 };
 
@@ -351,7 +354,7 @@ struct FinalStage {
 // U <- U + SG * Delta.  With a single group the second level is skipped (merging one
 // row with scale exp(0) = 1 would return it unchanged).  Every decision is uniform
 // over the block, so all barriers are reached by all threads.
-template <int NT, int MODEL = kModelNet>
+template <int NT, int MODEL = kModelNet, bool RECEDE = true>
 __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
                                  const float* N_lds /* [2T] */, float* lds /* >= 2T floats */) {
   __shared__ unsigned s_flag;
@@ -366,7 +369,7 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
   __syncthreads();
   if (publish_and_count<NT>(a.part + (size_t)tile * stride, rho_b, eta_b, N_lds, T2, a.cnt + grp,
                             (unsigned)n_in, &s_flag)) {
-    FinalStage<NT, MODEL> fs;
+    FinalStage<NT, MODEL, RECEDE> fs;
     float rho, eta;
     bool final_merge = ngrp == 1;
     if (final_merge) fs.prefetch(a);

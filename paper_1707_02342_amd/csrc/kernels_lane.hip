@@ -279,7 +279,7 @@ __device__ __forceinline__ void lane_block_partial(const RolloutArgs& a, float S
 }
 
 // One tile of 256 samples of one problem (samples tile*256 ... tile*256 + 255).
-template <class Net>
+template <class Net, bool RECEDE = true>
 __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, float* red, float* scratch) {
   for (int i = threadIdx.x; i < 2 * a.T; i += kLaneBlock) sU[i] = a.U[i];
   __syncthreads();
@@ -346,7 +346,7 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   }
   float rho, eta;
   lane_block_partial(a, Sv, valid, k, red, scratch, sU, sU, rho, eta);
-  finish_iteration<kLaneBlock, Net::kModel>(a, tile, rho, eta, sU, red);
+  finish_iteration<kLaneBlock, Net::kModel, RECEDE>(a, tile, rho, eta, sU, red);
 }
 
 template <class Net>
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kLaneBlock) void rollout_batch_kernel(const Rollout
     a.params = params;
     a.decay = decay;
     a.nk.iter = *a.iter_dev;
-    lane_rollout_tile<NetUniform<32>>(a, it.y, sU, red, scratch);
+    lane_rollout_tile<NetUniform<32>, false>(a, it.y, sU, red, scratch);
   }
 }
 

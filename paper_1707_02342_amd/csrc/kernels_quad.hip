@@ -271,7 +271,7 @@ struct QuadNet {
 };
 
 // One tile of 64 samples (tile * 64 ... + 63) of one problem; lds_f: the block's LDS.
-template <int PREC, int HID>
+template <int PREC, int HID, bool RECEDE = true>
 __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, float* sE, float* sX,
                                   float* red) {
   const int T = a.T;
@@ -545,7 +545,7 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   for (int o = threadIdx.x; o < 2 * T; o += kQuadBlock)
     N_lds[o] = ((red[o] + red[2 * kTMax + o]) + red[2 * 2 * kTMax + o]) + red[3 * 2 * kTMax + o];
   const float eta = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
-  finish_iteration<kQuadBlock>(a, tile, rho, eta, N_lds, red);
+  finish_iteration<kQuadBlock, kModelNet, RECEDE>(a, tile, rho, eta, N_lds, red);
 }
 
 // h = 32 fits three waves per SIMD without spilling (168 registers); h = 64 keeps the
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kQuadBlock) void rollout_batch_quad_kernel(const Ro
     a.params = params;
     a.decay = decay;
     a.nk.iter = *a.iter_dev;
-    quad_rollout_tile<kQPrecFP32, 32>(a, it.y, sU, sE, sX, red);
+    quad_rollout_tile<kQPrecFP32, 32, false>(a, it.y, sU, sE, sX, red);
   }
 }
 
