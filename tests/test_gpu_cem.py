@@ -15,12 +15,9 @@ import numpy as np
 import pytest
 
 import synth
+from parity_checks import check_cem as _check_cem
 
 pytestmark = pytest.mark.gpu
-
-COST_RTOL = 1e-5
-U_ATOL = 1e-5
-
 
 @pytest.fixture(scope="module")
 def M():
@@ -34,59 +31,6 @@ def M():
 
 def _say(*a):
     print(*a, flush=True)
-
-
-def _deltas(prob, eps, U0):
-    d = eps.astype(np.float64).copy()
-    alpha = float(np.float32(prob.explore))
-    zero_mean = ~(np.arange(d.shape[0]) < (1.0 - alpha) * d.shape[0])
-    d[zero_mean] -= U0.astype(np.float64)[None]
-    return d
-
-
-def _check_cem(M, orc, prob, cmap, params, x0, U0, schedule, it=0, impulses=False):
-    with M.Controller(prob, cmap, params, schedule=schedule) as c:
-        c.set_controls(U0)
-        c.iteration = it
-        S, st = c.iterate(x0, want_costs=True)
-        Ug = c.controls()
-        z_g, n_g, delta_g = c.stats()
-    op = orc.OracleProblem(prob, cmap, params)
-    eps = orc.noise(op, it)
-    ref = orc.iterate(op, x0, U0, it)
-    zeta = orc.cem_zeta(prob.K, prob.elite)
-    assert st == M.MPPI_OK and ref.status == orc.OK
-    fin = np.isfinite(ref.S)
-    assert np.array_equal(np.isfinite(S), fin), "non-finite samples differ"
-    Sf, Rf = np.where(fin, S.astype(np.float64), 0.0), np.where(fin, ref.S, 0.0)
-    err = np.abs(Sf - Rf) / np.maximum(np.abs(Rf), 1.0)
-    if impulses:
-        margin = orc.threshold_margins(op, x0, U0, eps)
-        near = margin < 1e-4
-        assert near.mean() < 1e-3
-        err = np.where(near, 0.0, err)
-    assert err.max() <= COST_RTOL, f"max rel dS {err.max():.3e}"
-    d = _deltas(prob, eps, U0)
-    Mx = orc.sgf_matrix(prob.T, prob.sg_window, prob.sg_order)
-    # stage-isolated: the oracle's Algorithm 3 on the GPU's costs
-    st2, w_iso, z_iso, n_iso = orc.weights_cem(S.astype(np.float64), zeta)
-    delta_iso = np.tensordot(w_iso, d, axes=(0, 0))
-    e_iso = np.abs(Ug - (U0.astype(np.float64) + Mx @ delta_iso)).max()
-    assert e_iso <= U_ATOL, f"stage-isolated |dU| {e_iso:.3e}"
-    np.testing.assert_allclose(delta_g, delta_iso, rtol=0, atol=1e-6)
-    assert n_g == n_iso and z_g == np.float32(z_iso), (n_g, n_iso, z_g, z_iso)
-    # end to end: the two elite sets differ only at the threshold, and U by that swap
-    E_g, E_r = set(np.nonzero(w_iso)[0]), set(np.nonzero(ref.w)[0])
-    swapped = sorted(E_g ^ E_r)
-    z_r = ref.rho
-    for k in swapped:
-        assert abs(ref.S[k] - z_r) <= 1e-5 * max(abs(z_r), 1.0), (k, ref.S[k], z_r)
-    pred = Mx @ ((d[sorted(E_g - E_r)].sum(axis=0) - d[sorted(E_r - E_g)].sum(axis=0)) / n_iso) if swapped else 0.0
-    resid = np.abs(Ug - ref.U - pred).max()
-    _say(f"CEM K={prob.K} T={prob.T} sched={schedule} zeta={zeta}: rel dS {err.max():.2e}, |dU| iso "
-         f"{e_iso:.2e}, swapped {len(swapped)}, e2e residual {resid:.2e}")
-    assert resid <= U_ATOL
-    return S, Ug
 
 
 def _schedules():
