@@ -60,6 +60,19 @@ __device__ __forceinline__ float rel_weight(float S, float rho, float inv_lambda
   return (S < kInf && rho < kInf) ? expf(-(S - rho) * inv_lambda) : 0.0f;
 }
 
+// A store that writes through the XCD's L2 (device-scope relaxed atomic store).  Data
+// that other blocks read in the same launch, and results read by the host, are
+// written this way.
+__device__ __forceinline__ void store_through(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A load that sees every store_through completed before it (device-scope relaxed
+// atomic load: it does not return a stale line of the XCD's L2).
+__device__ __forceinline__ float load_through(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kMergeChunk = 64;
 constexpr int kStatusNonfinite = 5;
 
@@ -85,8 +98,8 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
     // one round trip: every load of the n rows is issued before the first use
     float rg = kInf, eg = 0.0f;
     if (tid < n) {
-      rg = __builtin_nontemporal_load(rows + (size_t)tid * stride);
-      eg = __builtin_nontemporal_load(rows + (size_t)tid * stride + 1);
+      rg = load_through(rows + (size_t)tid * stride);
+      eg = load_through(rows + (size_t)tid * stride + 1);
     }
     float v[kOut][kFast];
 #pragma unroll
@@ -94,7 +107,7 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
       const int o = tid + j * NT;
 #pragma unroll
       for (int g = 0; g < kFast; ++g)
-        v[j][g] = (o < T2 && g < n) ? __builtin_nontemporal_load(rows + (size_t)g * stride + 2 + o) : 0.0f;
+        v[j][g] = (o < T2 && g < n) ? load_through(rows + (size_t)g * stride + 2 + o) : 0.0f;
     }
     if (tid < n) {
       s_small[tid] = rg;
@@ -115,14 +128,14 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
     __syncthreads();
   } else {
     float r = kInf;
-    for (int g = tid; g < n; g += NT) r = fminf(r, __builtin_nontemporal_load(rows + (size_t)g * stride));
+    for (int g = tid; g < n; g += NT) r = fminf(r, load_through(rows + (size_t)g * stride));
     rho = block_min<NT / 64>(r, s_small);
     for (int c0 = 0; c0 < n; c0 += kMergeChunk) {
       const int m = min(kMergeChunk, n - c0);
       if (tid < m) {
         const float* row = rows + (size_t)(c0 + tid) * stride;
-        const float eg = __builtin_nontemporal_load(row + 1);
-        s_small[tid] = (eg > 0.0f) ? expf(-(__builtin_nontemporal_load(row) - rho) * inv_lambda) : 0.0f;
+        const float eg = load_through(row + 1);
+        s_small[tid] = (eg > 0.0f) ? expf(-(load_through(row) - rho) * inv_lambda) : 0.0f;
         s_small[kMergeChunk + tid] = eg;
       }
       __syncthreads();
@@ -136,12 +149,12 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
           for (; g + 16 <= m; g += 16) {
             float v[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(col + (size_t)(g + i) * stride);
+            for (int i = 0; i < 16; ++i) v[i] = load_through(col + (size_t)(g + i) * stride);
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[j] = __builtin_fmaf(s_small[g + i], v[i], acc[j]);
           }
           for (; g < m; ++g)
-            acc[j] = __builtin_fmaf(s_small[g], __builtin_nontemporal_load(col + (size_t)g * stride), acc[j]);
+            acc[j] = __builtin_fmaf(s_small[g], load_through(col + (size_t)g * stride), acc[j]);
         }
       }
       __syncthreads();
@@ -156,20 +169,14 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
   eta_out = eta;
 }
 
-// A store that writes through the XCD's L2 (device-scope relaxed atomic store).  Data
-// that other blocks read after a device-scope release is written this way, so the
-// release finds few dirty L2 lines to write back.
-__device__ __forceinline__ void store_through(float* p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Wave 0 publishes a row (rho, eta, N[T2]) to global memory and counts its arrival
 // at *cnt; returns, in every thread after the barrier, whether this block was the
-// last of `expected` arrivals.  Only wave 0 writes global data that other blocks
-// read, so only wave 0 needs the device-scope release; the last arrival takes the
-// matching acquire.  (A full fence in every wave would also invalidate the XCD's L2
-// once per block.)  The row is written through L2, so the release has little to
-// write back.
+// last of `expected` arrivals.  The row is written through L2, and the wave waits
+// until those stores have completed (reached the device's point of coherence) before
+// it counts, so the last block, which reads the rows with load_through after the
+// count, sees every row.  This orders exactly the row's stores, where a device-scope
+// release fence would also write back every dirty line of the XCD's L2, and the
+// reads need no device-scope acquire (which would invalidate the L2).
 template <int NT>
 __device__ bool publish_and_count(float* dst, float rho, float eta, const float* N_lds, int T2,
                                   unsigned* cnt, unsigned expected, unsigned* s_flag) {
@@ -180,13 +187,11 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
       store_through(dst + 1, eta);
     }
     for (int o = lane; o < T2; o += 64) store_through(dst + 2 + o, N_lds[o]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (lane == 0) *s_flag = (atomicAdd(cnt, 1u) == expected - 1u) ? 1u : 0u;
   }
   __syncthreads();
-  const bool last = *s_flag != 0u;
-  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return last;
+  return *s_flag != 0u;
 }
 
 // The receding-horizon part of a control step (Algorithm 1's last block and the
