@@ -436,9 +436,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   float S_h = Sacc.hi, S_l = Sacc.lo;
   sum32_2(S_h, S_l);
   float S = S_h + S_l;
-  int okc = ok ? 1 : 0;
-#pragma unroll
-  for (int m = 16; m >= 1; m >>= 1) okc &= __shfl_xor(okc, m, 32);
+  const bool okc = all32(ok);
   if (!valid || !okc || !finite_f(S)) S = kInf;
   if (valid && c32 == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's update
 
@@ -452,12 +450,12 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   }
 
   // ---- D: softmin partial of the block's samples ------------------------------------
-  const float wmin = fminf(S, __shfl_xor(S, 32, 64));
+  const float wmin = fminf(S, other_half(S));
   if (lane == 0) scratch[wv] = wmin;
   __syncthreads();
   const float rho = fminf(fminf(scratch[0], scratch[1]), fminf(scratch[2], scratch[3]));
   const float e = rel_weight(S, rho, a.inv_lambda);
-  const float epair = e + __shfl_xor(e, 32, 64);
+  const float epair = e + other_half(e);
   if (lane == 0) scratch[4 + wv] = epair;
   const int eStrideRed = eStride;
 #pragma unroll
@@ -468,8 +466,8 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       const float d0 = zm ? ea[i] - sU[2 * tc] : ea[i];
       const float d1 = zm ? eb[i] - sU[2 * tc + 1] : eb[i];
       const float n0 = e * d0, n1 = e * d1;
-      const float p0 = n0 + __shfl_xor(n0, 32, 64);
-      const float p1 = n1 + __shfl_xor(n1, 32, 64);
+      const float p0 = n0 + other_half(n0);
+      const float p1 = n1 + other_half(n1);
       if (half == 0 && t < T) {
         red[wv * eStrideRed + 2 * t] = p0;
         red[wv * eStrideRed + 2 * t + 1] = p1;

@@ -57,51 +57,81 @@ __device__ __forceinline__ float add_rows(float v) {
   return x + y;
 }
 
-__device__ __forceinline__ float scan32_incl(float v, int c32) {
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const float o = __shfl_up(v, d, 32);
-    if (c32 >= d) v += o;
-  }
-  return v;
+constexpr int kRowShr = 0x110;        // row_shr:s = 0x110 + s
+constexpr int kRowBcast15 = 0x142;    // lane 15 of each row to every lane of the next row
+
+// DPP move with a row mask: lanes of the rows in ROWMASK whose source lane exists take
+// v from it; every other lane keeps `old`.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dpp_upd(float old, float v) {
+  return as_f((uint32_t)__builtin_amdgcn_update_dpp((int)as_u(old), (int)as_u(v), CTRL, ROWMASK, 0xF, false));
 }
 
-// Compensated exclusive scan of (hi, lo) pairs over the 32 lanes of a half-wave.
+// Compensated exclusive scan of (hi, lo) pairs over the 32 lanes of a half-wave
+// (lane 0 of each half gets (0, 0)), in DPP moves: the pairs are shifted up one lane,
+// scanned within each 16-lane row (shifts 1, 2, 4, 8), and the first row's total is
+// added to the second row.
 __device__ __forceinline__ void scan32_excl2(float& hi, float& lo, int c32) {
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const float oh = __shfl_up(hi, d, 32);
-    const float ol = __shfl_up(lo, d, 32);
-    if (c32 >= d) {
-      float s_, e_;
-      two_sum(hi, oh, s_, e_);
-      hi = s_;
-      lo = lo + (ol + e_);
-    }
+  const bool col0 = (c32 & 15) == 0;
+  {
+    const float sh = dpp_upd<kRowShr + 1>(0.0f, hi), sl = dpp_upd<kRowShr + 1>(0.0f, lo);
+    const float bh = dpp_upd<kRowBcast15, 0xA>(0.0f, hi), bl = dpp_upd<kRowBcast15, 0xA>(0.0f, lo);
+    hi = col0 ? bh : sh;
+    lo = col0 ? bl : sl;
   }
-  const float ph = __shfl_up(hi, 1, 32);
-  const float pl = __shfl_up(lo, 1, 32);
-  hi = c32 == 0 ? 0.0f : ph;
-  lo = c32 == 0 ? 0.0f : pl;
+#define MPPI_SCAN_STEP(CTRL, MASK)                                        \
+  {                                                                       \
+    const float oh = dpp_upd<CTRL, MASK>(0.0f, hi);                       \
+    const float ol = dpp_upd<CTRL, MASK>(0.0f, lo);                       \
+    float s_, e_;                                                         \
+    two_sum(hi, oh, s_, e_);                                              \
+    hi = s_;                                                              \
+    lo = lo + (ol + e_);                                                  \
+  }
+  MPPI_SCAN_STEP(kRowShr + 1, 0xF)
+  MPPI_SCAN_STEP(kRowShr + 2, 0xF)
+  MPPI_SCAN_STEP(kRowShr + 4, 0xF)
+  MPPI_SCAN_STEP(kRowShr + 8, 0xF)
+  MPPI_SCAN_STEP(kRowBcast15, 0xA)
+#undef MPPI_SCAN_STEP
 }
 
-// Compensated sum of (hi, lo) over the 32 lanes, the same bits in every lane.
+// Compensated sum of (hi, lo) over the 32 lanes, the same bits in every lane (the
+// error-free two-sum is symmetric in its operands): butterflies within each row, then
+// the two rows.
 __device__ __forceinline__ void sum32_2(float& hi, float& lo) {
-#pragma unroll
-  for (int m = 16; m >= 1; m >>= 1) {
-    const float oh = __shfl_xor(hi, m, 32);
-    const float ol = __shfl_xor(lo, m, 32);
+  auto step = [&](float oh, float ol) {
     float s_, e_;
     two_sum(hi, oh, s_, e_);
     hi = s_;
     lo = (lo + ol) + e_;
-  }
+  };
+  step(dpp_f<kRowRor + 8>(hi), dpp_f<kRowRor + 8>(lo));
+  step(dpp_f<kRowRor + 4>(hi), dpp_f<kRowRor + 4>(lo));
+  step(dpp_f<kQuadXor2>(hi), dpp_f<kQuadXor2>(lo));
+  step(dpp_f<kQuadXor1>(hi), dpp_f<kQuadXor1>(lo));
+  float xh = hi, yh = hi, xl = lo, yl = lo;
+  swap_rows(xh, yh);
+  swap_rows(xl, yl);
+  // each lane now holds its own row's (hi, lo) in one operand and the other row's in the other
+  const bool r1 = (threadIdx.x & 16) != 0;
+  hi = r1 ? yh : xh;
+  lo = r1 ? yl : xl;
+  step(r1 ? xh : yh, r1 ? xl : yl);
 }
 
-__device__ __forceinline__ float sum32(float v) {
-#pragma unroll
-  for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
-  return v;
+// The value of v in the lane 32 apart (the other half of the wave).
+__device__ __forceinline__ float other_half(float v) {
+  auto r = __builtin_amdgcn_permlane32_swap(as_u(v), as_u(v), false, false);
+  // r[0] holds the first half's values in both halves, r[1] the second half's
+  return as_f((threadIdx.x & 32) ? r[0] : r[1]);
+}
+
+// Whether p holds in every lane of the calling lane's 32-lane half.
+__device__ __forceinline__ bool all32(bool p) {
+  const unsigned long long m = __ballot(p);
+  const unsigned half = (threadIdx.x & 32) ? (unsigned)(m >> 32) : (unsigned)m;
+  return half == 0xFFFFFFFFu;
 }
 
 }  // namespace mppi
