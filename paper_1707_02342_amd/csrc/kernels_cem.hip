@@ -58,6 +58,7 @@ __device__ __forceinline__ int cem_excl_sum(int v, int* s_w, int& total) {
 // NCOL: float2 columns per lane, 2 for T <= 128, 4 for T <= 256.
 template <int NCOL>
 __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
+  if (a.iter_dev) a.nk.iter = *a.iter_dev;   // advanced by the final stage
   constexpr int kBatch = NCOL == 2 ? 12 : 4;   // rows per wave whose loads are in flight together
   __shared__ unsigned s_hist[256];
   __shared__ int s_w[kCemWaves];

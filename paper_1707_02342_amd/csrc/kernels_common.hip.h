@@ -199,18 +199,21 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
 // u_{t-1} <- u_t, u_{T-1} <- (0, 0)), and the plant state in x0_dev advances by one
 // noise-free step x <- F(x, g(u_0)).  The network runs one neuron per lane of wave 0,
 // each neuron's sums in input order, so the new state equals a one-thread evaluation
-// bit for bit.  Every other block of the launch has read x0_dev before it published
-// its row, so x0_dev can be overwritten here.  lds (>= 2T floats) is free on entry.
+// bit for bit.  x_lane: component tid of the plant state before the step (threads
+// tid < 7), loaded by the merging block before its merge; every other block of the launch has read x0_dev before it published its
+// row, so x0_dev can be overwritten here.  lds (>= 2T floats) is free on entry.
 // MODEL: the dynamics model the calling kernel serves (kModelAny: decided by a.model);
 // a kernel that serves one model compiles only that model's plant step.
 template <int NT, int kOut, int MODEL>
-__device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float* lds) {
+__device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float x_lane, float* lds) {
   constexpr bool kMayBasis = MODEL != kModelNet;
   constexpr bool kMayNet = MODEL != kModelBasis;
   __shared__ float s_h[2 * 64];
   __shared__ float s_f[4];
+  __shared__ float s_x[kStateDim];
   const int tid = threadIdx.x;
   const int T2 = 2 * a.T;
+  if (tid < kStateDim) s_x[tid] = x_lane;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kOut; ++j) {
@@ -220,6 +223,9 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   __syncthreads();
   for (int o = tid; o < T2; o += NT) a.Uout[o] = (o + 2 < T2) ? lds[o + 2] : 0.0f;
   if (tid < 2 && a.u0_out) a.u0_out[tid] = lds[tid];
+  float x[kStateDim];
+#pragma unroll
+  for (int i = 0; i < kStateDim; ++i) x[i] = s_x[i];
   const int H = a.hidden;
   const float* W1 = a.params;
   const float* b1 = W1 + H * 6;
@@ -227,9 +233,6 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   const float* b2 = W2 + H * H;
   const float* W3 = b2 + H;
   const float* b3 = W3 + 4 * H;
-  float x[kStateDim];
-#pragma unroll
-  for (int i = 0; i < kStateDim; ++i) x[i] = a.x0_dev[i];
   const float vc0 = fminf(fmaxf(lds[0], a.u_lo0), a.u_hi0);
   const float vc1 = fminf(fmaxf(lds[1], a.u_lo1), a.u_hi1);
   const float in[6] = {x[3], x[4], x[5], x[6], vc0, vc1};
@@ -275,9 +278,10 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   }
 }
 
-// The final stage of an iteration, run by the one block that merges: the old controls
-// and the Savitzky-Golay taps are loaded early (prefetch), so that these loads share a
-// memory round trip with the merge's own; apply() then forms Delta = lds[0..2T) * scale,
+// The final stage of an iteration, run by the one block that merges: the old controls,
+// the Savitzky-Golay taps and (receding step) the plant state are loaded early
+// (prefetch), so that these loads share a memory round trip with a merge's own;
+// apply() then forms Delta = lds[0..2T) * scale,
 // smooths it, updates U, writes the statistics and the status, advances the iteration
 // counter and, in a receding step, shifts U and advances the plant.
 // RECEDE = false: a kernel that never runs a receding step (compiled out).
@@ -287,9 +291,15 @@ struct FinalStage {
   static constexpr int kTapReg = 16;
   float u_old[kOut];
   float taps[kOut][kTapReg];
+  float x_old = 0.0f;   // component tid of the plant state (receding step, threads tid < 7)
 
   __device__ __forceinline__ void prefetch(const RolloutArgs& a) {
     const int tid = threadIdx.x, T2 = 2 * a.T, w = a.sg_window;
+    if constexpr (RECEDE) {
+      // one component per thread: vector loads, which unlike a uniform (scalar) load do
+      // not hold up the LDS waits of the merge that follows
+      x_old = (a.recede && tid < kStateDim) ? a.x0_dev[tid] : 0.0f;
+    }
 #pragma unroll
     for (int j = 0; j < kOut; ++j) {
       const int o = tid + j * NT;
@@ -343,10 +353,10 @@ struct FinalStage {
       *a.status = fin ? 0 : kStatusNonfinite;
       a.stats[0] = stat0;
       a.stats[1] = stat1;
-      if (a.iter_dev) *a.iter_dev = *a.iter_dev + 1u;
+      if (a.iter_dev) *a.iter_dev = a.nk.iter + 1u;   // nk.iter: the counter read at the start of the launch
     }
     if constexpr (RECEDE) {
-      if (a.recede) receding_step<NT, kOut, MODEL>(a, u_new, lds);
+      if (a.recede) receding_step<NT, kOut, MODEL>(a, u_new, x_old, lds);
     }
   }
 };
@@ -374,10 +384,13 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
   __syncthreads();
   if (publish_and_count<NT>(a.part + (size_t)tile * stride, rho_b, eta_b, N_lds, T2, a.cnt + grp,
                             (unsigned)n_in, &s_flag)) {
+    // every group merger loads what the final stage needs (the old controls, the
+    // smoothing taps, the plant state) before its merge, so that these loads share a
+    // round trip with the group's rows; the one that ends up merging the groups uses them
     FinalStage<NT, MODEL, RECEDE> fs;
     float rho, eta;
     bool final_merge = ngrp == 1;
-    if (final_merge) fs.prefetch(a);
+    fs.prefetch(a);
     merge_rows<NT>(a.part + (size_t)grp * gsz * stride, n_in, stride, T2, a.inv_lambda, lds, s_small,
                    rho, eta);
     if (tid == 0) a.cnt[grp] = 0u;
@@ -386,7 +399,6 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
       final_merge = publish_and_count<NT>(a.part2 + (size_t)grp * stride, rho, eta, lds, T2, a.cnt + ngrp,
                                           (unsigned)ngrp, &s_flag);
       if (final_merge) {
-        fs.prefetch(a);
         merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, lds, s_small, rho, eta);
         if (tid == 0) a.cnt[ngrp] = 0u;
       }
