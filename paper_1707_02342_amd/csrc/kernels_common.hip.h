@@ -177,9 +177,12 @@ __device__ void merge_rows(const float* rows, int n, int stride, int T2, float i
 // count, sees every row.  This orders exactly the row's stores, where a device-scope
 // release fence would also write back every dirty line of the XCD's L2, and the
 // reads need no device-scope acquire (which would invalidate the L2).
-template <int NT>
+// meanwhile() runs in every thread while the count is in flight (waves 1.. before the
+// barrier, wave 0 once its atomic has been issued), so loads it makes overlap the
+// count's round trip.
+template <int NT, class Meanwhile>
 __device__ bool publish_and_count(float* dst, float rho, float eta, const float* N_lds, int T2,
-                                  unsigned* cnt, unsigned expected, unsigned* s_flag) {
+                                  unsigned* cnt, unsigned expected, unsigned* s_flag, Meanwhile&& meanwhile) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     if (lane == 0) {
@@ -188,10 +191,21 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
     }
     for (int o = lane; o < T2; o += 64) store_through(dst + 2 + o, N_lds[o]);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (lane == 0) *s_flag = (atomicAdd(cnt, 1u) == expected - 1u) ? 1u : 0u;
+    unsigned old = 0u;
+    if (lane == 0) old = atomicAdd(cnt, 1u);
+    meanwhile();
+    if (lane == 0) *s_flag = (old == expected - 1u) ? 1u : 0u;
+  } else {
+    meanwhile();
   }
   __syncthreads();
   return *s_flag != 0u;
+}
+
+template <int NT>
+__device__ bool publish_and_count(float* dst, float rho, float eta, const float* N_lds, int T2,
+                                  unsigned* cnt, unsigned expected, unsigned* s_flag) {
+  return publish_and_count<NT>(dst, rho, eta, N_lds, T2, cnt, expected, s_flag, [] {});
 }
 
 // The receding-horizon part of a control step (Algorithm 1's last block and the
@@ -384,20 +398,21 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
   __syncthreads();
   if (publish_and_count<NT>(a.part + (size_t)tile * stride, rho_b, eta_b, N_lds, T2, a.cnt + grp,
                             (unsigned)n_in, &s_flag)) {
-    // every group merger loads what the final stage needs (the old controls, the
-    // smoothing taps, the plant state) before its merge, so that these loads share a
-    // round trip with the group's rows; the one that ends up merging the groups uses them
+    // what the final stage needs (the old controls, the smoothing taps, the plant state)
+    // is loaded by every group merger while its group row's count is in flight (or
+    // before the merge when there is a single group), so that the final merge finds it
+    // in registers
     FinalStage<NT, MODEL, RECEDE> fs;
     float rho, eta;
     bool final_merge = ngrp == 1;
-    fs.prefetch(a);
+    if (final_merge) fs.prefetch(a);
     merge_rows<NT>(a.part + (size_t)grp * gsz * stride, n_in, stride, T2, a.inv_lambda, lds, s_small,
                    rho, eta);
     if (tid == 0) a.cnt[grp] = 0u;
     if (ngrp > 1) {
       __syncthreads();
       final_merge = publish_and_count<NT>(a.part2 + (size_t)grp * stride, rho, eta, lds, T2, a.cnt + ngrp,
-                                          (unsigned)ngrp, &s_flag);
+                                          (unsigned)ngrp, &s_flag, [&] { fs.prefetch(a); });
       if (final_merge) {
         merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, lds, s_small, rho, eta);
         if (tid == 0) a.cnt[ngrp] = 0u;
