@@ -124,6 +124,22 @@ def test_sgf_and_impulses_small(M, orc, schedule):
 
 
 @pytest.mark.parametrize("schedule", _schedules())
+@pytest.mark.parametrize("T", [129, 256])
+def test_long_horizons_to_the_maximum(M, orc, schedule, T):
+    """Horizons past 128 steps up to MPPI_T_MAX (the wave schedule's 8-chunk variant): more
+    than 256 controls, so each merging thread also merges a second column and the final
+    stage smooths and updates a second control per thread.  Over 129-256 steps many
+    more trajectories pass within 1e-4 of an impulse threshold (a few percent of them);
+    those are left out of the cost comparison, as everywhere, and the cap on their
+    share is raised accordingly."""
+    assert T <= M.MPPI_T_MAX
+    prob = synth.with_(synth.c2_problem(seed=T), K=300, T=T)
+    _say("long horizon", schedule, T)
+    _check_iteration(M, orc, prob, synth.ellipse_map(), synth.mlp_params(32, 0), synth.C2_X0,
+                     synth.random_controls(T, 11, scale=0.2), schedule, impulses=True, near_cap=0.15)
+
+
+@pytest.mark.parametrize("schedule", _schedules())
 def test_paper_shaped_full_iteration(M, orc, schedule):
     """K=1920, T=100, 2048^2 elliptical map, SGF window 9 (the benchmark's configuration)."""
     prob = synth.c2_problem(seed=0)
