@@ -177,8 +177,8 @@ def _timed_iterations(ctl, x0, n, stream):
 
 def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
     """The three added forms on their own workloads (synthetic, seeded):
-    precision: K=16384, T=100, 6-64-64-4 network, one iteration in FP32 (lane schedule)
-      and with BF16 / FP16 matrix-core operands (FP32 accumulation);
+    precision: K=16384 and K=65536, T=100, 6-64-64-4 network, one iteration in FP32 and
+      with BF16 / FP16 matrix-core operands (FP32 accumulation);
     batched: 512 instances (K_i in 512..4096, T_i in 50..150) advanced by one replayed
       graph launch per iteration;
     differentiation: K=4096, T=100, free-energy objective plus its adjoint gradient
@@ -191,34 +191,42 @@ def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
     import torch
     import synth
     out = {}
-    prob = synth.c3_problem(K=16384, seed=0)
     params = synth.mlp_params(64, 0)
     cmap = synth.ring_map()
-    prec = {}
-    for name, p in (("fp32", M.MPPI_PREC_FP32), ("bf16", M.MPPI_PREC_BF16), ("fp16", M.MPPI_PREC_FP16)):
-        ctl = M.Controller(prob, cmap, params, stream=int(stream.cuda_stream), precision=p)
-        for _ in range(3):
-            ctl.iterate(synth.C1_X0)
-        ms = _timed_iterations(ctl, synth.C1_X0, iters, stream)
-        ctl.close()
-        prec[name] = {"ms_per_iteration": ms, "steps_per_s": prob.K * prob.T / (ms * 1e-3)}
+    flop = NET_FLOP_PER_STEP[64]
     # rooflines: FP32 on the matrix cores against the FP32 matrix peak; BF16/FP16 are
     # bound by the vector ALU (tanh: exp and rcp at quarter rate + 3 FMA = 11 slots, 128
     # per step at h = 64, plus ~150 other slots) -- reported against that bound and,
     # for reference, as a fraction of the BF16/FP16 matrix peak
-    flop = NET_FLOP_PER_STEP[64]
     valu_steps_peak = VALU_LANE_SLOTS_PER_S / (128 * 11 + 150)
-    f32_tflops = prec["fp32"]["steps_per_s"] * flop / 1e12
-    prec["fp32"]["roofline"] = {"bound": "mfma", "achieved": f32_tflops, "peak": PEAK_FP32_TFLOPS,
-                                "unit": "TFLOP/s", "frac": f32_tflops / PEAK_FP32_TFLOPS}
-    for name in ("bf16", "fp16"):
-        st = prec[name]["steps_per_s"]
-        prec[name]["roofline"] = {"bound": "alu", "achieved": st / 1e9, "peak": valu_steps_peak / 1e9,
-                                  "unit": "Gsteps/s", "frac": st / valu_steps_peak,
-                                  "mfma_frac": st * flop / 1e12 / PEAK_BF16_TFLOPS}
-    prec["bf16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["bf16"]["ms_per_iteration"]
-    prec["fp16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["fp16"]["ms_per_iteration"]
-    prec["workload"] = "K=16384, T=100, 6-64-64-4 network, 256x256 ring map"
+
+    def precision_at(K):
+        prob = synth.c3_problem(K=K, seed=0)
+        prec = {}
+        for name, p in (("fp32", M.MPPI_PREC_FP32), ("bf16", M.MPPI_PREC_BF16), ("fp16", M.MPPI_PREC_FP16)):
+            ctl = M.Controller(prob, cmap, params, stream=int(stream.cuda_stream), precision=p)
+            for _ in range(3):
+                ctl.iterate(synth.C1_X0)
+            ms = _timed_iterations(ctl, synth.C1_X0, iters, stream)
+            ctl.close()
+            prec[name] = {"ms_per_iteration": ms, "steps_per_s": prob.K * prob.T / (ms * 1e-3)}
+        f32_tflops = prec["fp32"]["steps_per_s"] * flop / 1e12
+        prec["fp32"]["roofline"] = {"bound": "mfma", "achieved": f32_tflops, "peak": PEAK_FP32_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": f32_tflops / PEAK_FP32_TFLOPS}
+        for name in ("bf16", "fp16"):
+            st = prec[name]["steps_per_s"]
+            prec[name]["roofline"] = {"bound": "alu", "achieved": st / 1e9, "peak": valu_steps_peak / 1e9,
+                                      "unit": "Gsteps/s", "frac": st / valu_steps_peak,
+                                      "mfma_frac": st * flop / 1e12 / PEAK_BF16_TFLOPS}
+        prec["bf16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["bf16"]["ms_per_iteration"]
+        prec["fp16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["fp16"]["ms_per_iteration"]
+        prec["workload"] = f"K={K}, T=100, 6-64-64-4 network, 256x256 ring map"
+        return prec
+
+    # K = 16384 at the top level (one wave of 16 samples per SIMD), K = 65536 (four
+    # per SIMD) under "k65536"
+    prec = precision_at(16384)
+    prec["k65536"] = precision_at(65536)
     out["precision"] = prec
 
     inst = synth.c4_instances(512, seed=0)

@@ -302,7 +302,9 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       f = add_rows(f) + b3c;
     }
     xd.add(a.dt * f);
-    if (c32 < 4) sX[slot * T4 * 4 + (t + 1) * 4 + c32] = xd.value();
+    // every lane of a component holds the same bits (f and the update are formed alike
+    // in all of them), so all lanes store: no branch in the step loop
+    sX[slot * T4 * 4 + (t + 1) * 4 + comp] = xd.value();
     u = u_next;
     e = e_next;
   }
