@@ -67,6 +67,18 @@ __device__ __forceinline__ float dpp_upd(float old, float v) {
   return as_f((uint32_t)__builtin_amdgcn_update_dpp((int)as_u(old), (int)as_u(v), CTRL, ROWMASK, 0xF, false));
 }
 
+// One step of a compensated scan: (hi, lo) += the pair that DPP control CTRL brings in
+// (lanes outside ROWMASK, or without a source lane, add (0, 0)).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void scan_step2(float& hi, float& lo) {
+  const float oh = dpp_upd<CTRL, ROWMASK>(0.0f, hi);
+  const float ol = dpp_upd<CTRL, ROWMASK>(0.0f, lo);
+  float s_, e_;
+  two_sum(hi, oh, s_, e_);
+  hi = s_;
+  lo = lo + (ol + e_);
+}
+
 // Compensated exclusive scan of (hi, lo) pairs over the 32 lanes of a half-wave
 // (lane 0 of each half gets (0, 0)), in DPP moves: the pairs are shifted up one lane,
 // scanned within each 16-lane row (shifts 1, 2, 4, 8), and the first row's total is
@@ -79,21 +91,11 @@ __device__ __forceinline__ void scan32_excl2(float& hi, float& lo, int c32) {
     hi = col0 ? bh : sh;
     lo = col0 ? bl : sl;
   }
-#define MPPI_SCAN_STEP(CTRL, MASK)                                        \
-  {                                                                       \
-    const float oh = dpp_upd<CTRL, MASK>(0.0f, hi);                       \
-    const float ol = dpp_upd<CTRL, MASK>(0.0f, lo);                       \
-    float s_, e_;                                                         \
-    two_sum(hi, oh, s_, e_);                                              \
-    hi = s_;                                                              \
-    lo = lo + (ol + e_);                                                  \
-  }
-  MPPI_SCAN_STEP(kRowShr + 1, 0xF)
-  MPPI_SCAN_STEP(kRowShr + 2, 0xF)
-  MPPI_SCAN_STEP(kRowShr + 4, 0xF)
-  MPPI_SCAN_STEP(kRowShr + 8, 0xF)
-  MPPI_SCAN_STEP(kRowBcast15, 0xA)
-#undef MPPI_SCAN_STEP
+  scan_step2<kRowShr + 1, 0xF>(hi, lo);
+  scan_step2<kRowShr + 2, 0xF>(hi, lo);
+  scan_step2<kRowShr + 4, 0xF>(hi, lo);
+  scan_step2<kRowShr + 8, 0xF>(hi, lo);
+  scan_step2<kRowBcast15, 0xA>(hi, lo);
 }
 
 // Compensated sum of (hi, lo) over the 32 lanes, the same bits in every lane (the
