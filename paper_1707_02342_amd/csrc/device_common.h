@@ -244,15 +244,19 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 // Grid coordinate (p - o) / res of a position given as hi + lo, split into an integer
 // cell and a fraction in [0, 1) that keeps the low part: the quotient's rounding
 // remainder is exact (fma), so the fraction is good to ~1e-7 of a cell even where
-// the coordinate itself needs all 24 bits.  Clamped to [-1, n] like costmap_at.
-__device__ __forceinline__ void grid_coord(float ph, float pl, float o, float res, int n, int& i0,
-                                           float& f) {
+// the coordinate itself needs all 24 bits.  Clamped to [-1, n] like costmap_at.  The
+// quotient comes from the reciprocal inv_res = fl(1/res) and one correction with the
+// residual (within an ulp of d / res, which keeps the next residual exact), not from
+// a division.
+__device__ __forceinline__ void grid_coord(float ph, float pl, float o, float res, float inv_res, int n,
+                                           int& i0, float& f) {
   float d, dl;
   two_sum(ph, -o, d, dl);
   dl = dl + pl;
-  float q = d / res;
+  float q = d * inv_res;
+  q = __builtin_fmaf(__builtin_fmaf(-q, res, d), inv_res, q);
   const float rem = __builtin_fmaf(-q, res, d);
-  float ql = (rem + dl) / res;
+  float ql = (rem + dl) * inv_res;
   if (!(q >= -1.0f)) { q = -1.0f; ql = 0.0f; }
   if (!(q <= (float)n)) { q = (float)n; ql = 0.0f; }
   const float fl = floorf(q);
@@ -267,8 +271,9 @@ __device__ __forceinline__ void grid_coord(float ph, float pl, float o, float re
 __device__ __forceinline__ void map_taps(const CostArgs& c, float pxh, float pxl, float pyh, float pyl,
                                          int idx[4], float& fx, float& fy) {
   int j0, i0;
-  grid_coord(pxh, pxl, c.ox, c.res, c.W, j0, fx);
-  grid_coord(pyh, pyl, c.oy, c.res, c.H, i0, fy);
+  const float inv_res = 1.0f / c.res;
+  grid_coord(pxh, pxl, c.ox, c.res, inv_res, c.W, j0, fx);
+  grid_coord(pyh, pyl, c.oy, c.res, inv_res, c.H, i0, fy);
   const int ja = min(max(j0, 0), c.W - 1), jb = min(max(j0 + 1, 0), c.W - 1);
   const int ia = min(max(i0, 0), c.H - 1), ib = min(max(i0 + 1, 0), c.H - 1);
   idx[0] = ia * c.W + ja;
