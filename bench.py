@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision/batched/differentiation forms")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only time the precision form (K=16384 and 65536), print its JSON and exit")
     ap.add_argument("--write-traffic", metavar="PMC_DIR",
                     help="reduce rocprofv3 FETCH_SIZE/WRITE_SIZE runs under PMC_DIR to the stored traffic "
                          "record under profiles/ and exit")
@@ -175,22 +177,11 @@ def _timed_iterations(ctl, x0, n, stream):
     return e0.elapsed_time(e1) / n          # ms per iteration
 
 
-def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
-    """The three added forms on their own workloads (synthetic, seeded):
-    precision: K=16384 and K=65536, T=100, 6-64-64-4 network, one iteration in FP32 and
-      with BF16 / FP16 matrix-core operands (FP32 accumulation);
-    batched: 512 instances (K_i in 512..4096, T_i in 50..150) advanced by one replayed
-      graph launch per iteration;
-    differentiation: K=4096, T=100, free-energy objective plus its adjoint gradient
-      with checkpoints every 10 steps;
-    exploration: the paper-shaped receding-horizon step with the parameter table's
-      lambda, gamma and Sigma and 1 % of the samples drawn around zero;
-    cem: the same step with Algorithm 3's weights (the best 20 % averaged);
-    basis: the paper-shaped step with the basis-function model;
-    laps: closed-loop lap statistics (measure_laps)."""
-    import torch
+def measure_precision(M, stream, iters: int = 30):
+    """The precision form: K=16384 (top level; one wave of 16 samples per SIMD) and
+    K=65536 ("k65536"; four per SIMD), T=100, 6-64-64-4 network, FP32 and BF16 / FP16
+    matrix-core operands with FP32 accumulation."""
     import synth
-    out = {}
     params = synth.mlp_params(64, 0)
     cmap = synth.ring_map()
     flop = NET_FLOP_PER_STEP[64]
@@ -223,11 +214,27 @@ def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
         prec["workload"] = f"K={K}, T=100, 6-64-64-4 network, 256x256 ring map"
         return prec
 
-    # K = 16384 at the top level (one wave of 16 samples per SIMD), K = 65536 (four
-    # per SIMD) under "k65536"
     prec = precision_at(16384)
     prec["k65536"] = precision_at(65536)
-    out["precision"] = prec
+    return prec
+
+
+def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
+    """The three added forms on their own workloads (synthetic, seeded):
+    precision: K=16384 and K=65536, T=100, 6-64-64-4 network, one iteration in FP32 and
+      with BF16 / FP16 matrix-core operands (FP32 accumulation);
+    batched: 512 instances (K_i in 512..4096, T_i in 50..150) advanced by one replayed
+      graph launch per iteration;
+    differentiation: K=4096, T=100, free-energy objective plus its adjoint gradient
+      with checkpoints every 10 steps;
+    exploration: the paper-shaped receding-horizon step with the parameter table's
+      lambda, gamma and Sigma and 1 % of the samples drawn around zero;
+    cem: the same step with Algorithm 3's weights (the best 20 % averaged);
+    basis: the paper-shaped step with the basis-function model;
+    laps: closed-loop lap statistics (measure_laps)."""
+    import torch
+    import synth
+    out = {"precision": measure_precision(M, stream, iters)}
 
     inst = synth.c4_instances(512, seed=0)
     Ks, Ts = [b.K for b in inst], [b.T for b in inst]
@@ -356,6 +363,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.precision_only:
+        print(json.dumps({"precision": measure_precision(M, stream, iters=10)}), flush=True)
+        return
     cmap = synth.ellipse_map()
     prob = synth.c2_problem(seed=0)
     params = synth.mlp_params(prob.hidden, 0)
