@@ -9,6 +9,11 @@
 //      lower sample index), and sums their delta rows with compensated additions,
 //   4. applies U <- U + SGF * (sum / zeta') and, in a receding step, the shift and the
 //      plant step (the same final stage as Algorithm 2's merge).
+// With several blocks (gridDim.x > 1) every block takes steps 1-3 in full except that it
+// sums only its share of the elite rows (global wave w of the launch takes list entries
+// w, w + W, ...); the blocks publish their partial sums as Algorithm 2's merge publishes
+// its rows, and the last to arrive adds them in block order and takes step 4.  One CU
+// alone cannot pull the elite rows quickly (about 307 KB at K = 1920).
 // The costs stay in registers when K <= 8192 (one memory round trip); larger K is
 // processed in chunks of 8192 samples.
 #include "kernels_common.hip.h"
@@ -68,6 +73,7 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
   __shared__ int s_list[kCemChunk];
   __shared__ float s_part[kCemWaves][2 * kTMax];
   __shared__ float s_delta[2 * kTMax];
+  __shared__ unsigned s_flag;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K = a.K, T2 = 2 * a.T;
   const int nchunk = (K + kCemChunk - 1) / kCemChunk;
@@ -254,12 +260,13 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
         if (take & (1u << i)) s_list[pos++] = c0 + tid * kCemKeys + i;
       eq_taken += tot_eq;
       __syncthreads();
-      // wave wv sums list entries wv, wv + 16, ...; lane owns float2 columns lane + 64 j
-      for (int e0 = wv; e0 < tot_el; e0 += kCemWaves * kBatch) {
+      // global wave gw sums list entries gw, gw + W, ...; lane owns float2 columns lane + 64 j
+      const int gw = blockIdx.x * kCemWaves + wv, W = gridDim.x * kCemWaves;
+      for (int e0 = gw; e0 < tot_el; e0 += W * kBatch) {
         float2 v[kBatch][NCOL];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-          const int e = e0 + b * kCemWaves;
+          const int e = e0 + b * W;
           const float2* row = reinterpret_cast<const float2*>(a.D + (size_t)s_list[min(e, tot_el - 1)] * T2);
 #pragma unroll
           for (int j = 0; j < NCOL; ++j) {
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-          if (e0 + b * kCemWaves < tot_el) {
+          if (e0 + b * W < tot_el) {
 #pragma unroll
             for (int j = 0; j < NCOL; ++j) {
               acc[j][0].add(v[b][j].x);
@@ -296,6 +303,21 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
 #pragma unroll
     for (int w = 0; w < kCemWaves; ++w) s += s_part[w][tid];
     s_delta[tid] = s;
+  }
+  if (gridDim.x > 1) {
+    // the block's share, published like a rollout block's row (a.part, a.cnt[0]: unused
+    // by a rollout launch that stores delta rows); the last block adds the shares
+    const int stride = 2 + T2;
+    __syncthreads();
+    if (!publish_and_count<kCemBlock>(a.part + (size_t)blockIdx.x * stride, 0.0f, 0.0f, s_delta, T2, a.cnt,
+                                      gridDim.x, &s_flag))
+      return;
+    if (tid == 0) a.cnt[0] = 0u;
+    if (tid < T2) {
+      float s = 0.0f;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += load_through(a.part + (size_t)b * stride + 2 + tid);
+      s_delta[tid] = s;
+    }
   }
   fs.apply(a, s_delta, zeff > 0, zeff > 0 ? 1.0f / (float)zeff : 0.0f, key_cost(zkey), (float)zeff);
 }

@@ -419,10 +419,13 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   HIP_TRY(c, hipGetLastError());
   // Algorithm 3: the rollout launch leaves costs and delta rows; the update follows
   if (a.cem_zeta > 0) {
+    // blocks sharing the elite-row sum: one per ~48 elite rows, at most 8, and never more
+    // than the partial rows allocated (their counter a.cnt[0] is zero between launches)
+    const int nb = std::max(1, std::min({8, (a.cem_zeta + 47) / 48, c->part_cap}));
     if (c->cfg.T <= 128)
-      hipLaunchKernelGGL(cem_update_kernel<2>, dim3(1), dim3(kCemBlockThreads), 0, c->stream, a);
+      hipLaunchKernelGGL(cem_update_kernel<2>, dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
     else
-      hipLaunchKernelGGL(cem_update_kernel<4>, dim3(1), dim3(kCemBlockThreads), 0, c->stream, a);
+      hipLaunchKernelGGL(cem_update_kernel<4>, dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
     HIP_TRY(c, hipGetLastError());
   }
   if (c->timing) {
