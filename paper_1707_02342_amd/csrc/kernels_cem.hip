@@ -60,8 +60,9 @@ __device__ __forceinline__ int cem_excl_sum(int v, int* s_w, int& total) {
   return base + incl - v;
 }
 
-// NCOL: float2 columns per lane, 2 for T <= 128, 4 for T <= 256.
-template <int NCOL>
+// NCOL: float2 columns per lane, 2 for T <= 128, 4 for T <= 256.  HC: the network width
+// when the context's network is 32 wide (unrolled plant step), else 0.
+template <int NCOL, int HC>
 __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
   if (a.iter_dev) a.nk.iter = *a.iter_dev;   // advanced by the final stage
   constexpr int kBatch = NCOL == 2 ? 12 : 4;   // rows per wave whose loads are in flight together
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
   const int nchunk = (K + kCemChunk - 1) / kCemChunk;
   const bool resident = nchunk == 1;
 
-  FinalStage<kCemBlock, kModelAny> fs;
+  FinalStage<kCemBlock, kModelAny, true, HC> fs;
   fs.prefetch(a);
 
   unsigned key[kCemKeys];
@@ -322,7 +323,9 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
   fs.apply(a, s_delta, zeff > 0, zeff > 0 ? 1.0f / (float)zeff : 0.0f, key_cost(zkey), (float)zeff);
 }
 
-template __global__ void cem_update_kernel<2>(RolloutArgs);
-template __global__ void cem_update_kernel<4>(RolloutArgs);
+template __global__ void cem_update_kernel<2, 0>(RolloutArgs);
+template __global__ void cem_update_kernel<4, 0>(RolloutArgs);
+template __global__ void cem_update_kernel<2, 32>(RolloutArgs);
+template __global__ void cem_update_kernel<4, 32>(RolloutArgs);
 
 }  // namespace mppi

@@ -217,8 +217,10 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
 // tid < 7), loaded by the merging block before its merge; every other block of the launch has read x0_dev before it published its
 // row, so x0_dev can be overwritten here.  lds (>= 2T floats) is free on entry.
 // MODEL: the dynamics model the calling kernel serves (kModelAny: decided by a.model);
-// a kernel that serves one model compiles only that model's plant step.
-template <int NT, int kOut, int MODEL>
+// a kernel that serves one model compiles only that model's plant step.  HC: the
+// network width when the calling kernel fixes it (0: a.hidden), so that every sum is
+// unrolled and its weight loads issued together (the arithmetic is the same).
+template <int NT, int kOut, int MODEL, int HC = 0>
 __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float x_lane, float* lds) {
   constexpr bool kMayBasis = MODEL != kModelNet;
   constexpr bool kMayNet = MODEL != kModelBasis;
@@ -240,7 +242,7 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   float x[kStateDim];
 #pragma unroll
   for (int i = 0; i < kStateDim; ++i) x[i] = s_x[i];
-  const int H = a.hidden;
+  const int H = HC > 0 ? HC : a.hidden;
   const float* W1 = a.params;
   const float* b1 = W1 + H * 6;
   const float* W2 = b1 + H;
@@ -264,13 +266,23 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   __syncthreads();
   if (kMayNet && net && tid < H) {
     float acc = b2[tid];
-    for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[tid * H + j], s_h[j], acc);
+    if constexpr (HC > 0) {
+#pragma unroll
+      for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W2[tid * HC + j], s_h[j], acc);
+    } else {
+      for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[tid * H + j], s_h[j], acc);
+    }
     s_h[64 + tid] = tanh_f(acc);
   }
   __syncthreads();
   if (kMayNet && net && tid < 4) {
     float acc = b3[tid];
-    for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[tid * H + j], s_h[64 + j], acc);
+    if constexpr (HC > 0) {
+#pragma unroll
+      for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W3[tid * HC + j], s_h[64 + j], acc);
+    } else {
+      for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[tid * H + j], s_h[64 + j], acc);
+    }
     s_f[tid] = acc;
   }
   __syncthreads();
@@ -298,8 +310,9 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
 // apply() then forms Delta = lds[0..2T) * scale,
 // smooths it, updates U, writes the statistics and the status, advances the iteration
 // counter and, in a receding step, shifts U and advances the plant.
-// RECEDE = false: a kernel that never runs a receding step (compiled out).
-template <int NT, int MODEL = kModelNet, bool RECEDE = true>
+// RECEDE = false: a kernel that never runs a receding step (compiled out).  HC: see
+// receding_step.
+template <int NT, int MODEL = kModelNet, bool RECEDE = true, int HC = 0>
 struct FinalStage {
   static constexpr int kOut = (2 * kTMax + NT - 1) / NT;
   static constexpr int kTapReg = 16;
@@ -370,7 +383,7 @@ struct FinalStage {
       if (a.iter_dev) *a.iter_dev = a.nk.iter + 1u;   // nk.iter: the counter read at the start of the launch
     }
     if constexpr (RECEDE) {
-      if (a.recede) receding_step<NT, kOut, MODEL>(a, u_new, x_old, lds);
+      if (a.recede) receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds);
     }
   }
 };
@@ -383,7 +396,7 @@ struct FinalStage {
 // U <- U + SG * Delta.  With a single group the second level is skipped (merging one
 // row with scale exp(0) = 1 would return it unchanged).  Every decision is uniform
 // over the block, so all barriers are reached by all threads.
-template <int NT, int MODEL = kModelNet, bool RECEDE = true>
+template <int NT, int MODEL = kModelNet, bool RECEDE = true, int HC = 0>
 __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
                                  const float* N_lds /* [2T] */, float* lds /* >= 2T floats */) {
   __shared__ unsigned s_flag;
@@ -402,7 +415,7 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
     // is loaded by every group merger while its group row's count is in flight (or
     // before the merge when there is a single group), so that the final merge finds it
     // in registers
-    FinalStage<NT, MODEL, RECEDE> fs;
+    FinalStage<NT, MODEL, RECEDE, HC> fs;
     float rho, eta;
     bool final_merge = ngrp == 1;
     if (final_merge) fs.prefetch(a);

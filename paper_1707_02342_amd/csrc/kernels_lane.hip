@@ -33,6 +33,7 @@ constexpr int kLaneWaves = kLaneBlock / 64;
 template <int HID>
 struct NetUniform {
   static constexpr int kModel = kModelNet;
+  static constexpr int kHidden = HID;
   const float* __restrict__ P;
   __device__ explicit NetUniform(const float* p) : P(p) {}
   __device__ __forceinline__ void eval(const float in[6], float f[4]) const {
@@ -73,6 +74,7 @@ struct NetUniform {
 // ---------------------------------------------------------------------------
 struct NetBasis {
   static constexpr int kModel = kModelBasis;
+  static constexpr int kHidden = 0;
   const float* __restrict__ P;
   __device__ explicit NetBasis(const float* p) : P(p) {}
   __device__ __forceinline__ void eval(const float in[6], float f[4]) const { basis_f(P, in, in[4], in[5], f); }
@@ -125,6 +127,7 @@ __device__ __forceinline__ int kslot_neuron(int kb, int g, int c) {
 template <int PREC, int HID>
 struct NetMfma {
   static constexpr int kModel = kModelNet;
+  static constexpr int kHidden = HID;
   typedef MfmaOps<PREC> Ops;
   typedef typename Ops::vec vec;
   static constexpr int NM = HID / 16;   // 16-neuron tiles
@@ -346,7 +349,7 @@ __device__ void lane_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   }
   float rho, eta;
   lane_block_partial(a, Sv, valid, k, red, scratch, sU, sU, rho, eta);
-  finish_iteration<kLaneBlock, Net::kModel, RECEDE>(a, tile, rho, eta, sU, red);
+  finish_iteration<kLaneBlock, Net::kModel, RECEDE, Net::kHidden>(a, tile, rho, eta, sU, red);
 }
 
 template <class Net>

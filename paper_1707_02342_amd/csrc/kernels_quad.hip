@@ -545,7 +545,7 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   for (int o = threadIdx.x; o < 2 * T; o += kQuadBlock)
     N_lds[o] = ((red[o] + red[2 * kTMax + o]) + red[2 * 2 * kTMax + o]) + red[3 * 2 * kTMax + o];
   const float eta = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
-  finish_iteration<kQuadBlock, kModelNet, RECEDE>(a, tile, rho, eta, N_lds, red);
+  finish_iteration<kQuadBlock, kModelNet, RECEDE, HID>(a, tile, rho, eta, N_lds, red);
 }
 
 // h = 32 fits three waves per SIMD without spilling (168 registers); h = 64 keeps the

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   for (int o = threadIdx.x; o < 2 * T; o += kWaveBlock)
     N_lds[o] = ((red[o] + red[eStrideRed + o]) + red[2 * eStrideRed + o]) + red[3 * eStrideRed + o];
   const float eta = ((scratch[4] + scratch[5]) + scratch[6]) + scratch[7];
-  finish_iteration<kWaveBlock, MODEL>(a, blockIdx.x, rho, eta, N_lds, red);
+  finish_iteration<kWaveBlock, MODEL, true, HID>(a, blockIdx.x, rho, eta, N_lds, red);
 }
 
 template __global__ void rollout_wave_kernel<32, 4, kModelNet>(RolloutArgs);

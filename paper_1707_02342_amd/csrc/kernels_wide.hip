@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kWideBlock) void rollout_wide_kernel(RolloutArgs a)
   float eta = scratch[kWideSlots];
 #pragma unroll
   for (int w = 1; w < kWideSlots; ++w) eta += scratch[kWideSlots + w];
-  finish_iteration<kWideBlock>(a, blockIdx.x, rho, eta, N_lds, red);
+  finish_iteration<kWideBlock, kModelNet, true, 32>(a, blockIdx.x, rho, eta, N_lds, red);
 }
 
 template __global__ void rollout_wide_kernel<2>(RolloutArgs);

@@ -32,7 +32,7 @@ __global__ void plant_kernel(const float*, const float*, const float*, float*, f
 __global__ void noise_kernel(NoiseKey, int, int, float*);
 __global__ void costmap_kernel(CostArgs, const float*, const float*, int, float*);
 __global__ void adjoint_wave_kernel(AdjointArgs);
-template <int NCOL> __global__ void cem_update_kernel(RolloutArgs);
+template <int NCOL, int HC> __global__ void cem_update_kernel(RolloutArgs);
 constexpr int kCemBlockThreads = 1024;
 __global__ void adjoint_reduce_partial_kernel(const float*, int, int, int, float*);
 __global__ void adjoint_reduce_final_kernel(const float*, int, int, const float*, float, float, float*);
@@ -422,10 +422,14 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
     // blocks sharing the elite-row sum: one per ~48 elite rows, at most 8, and never more
     // than the partial rows allocated (their counter a.cnt[0] is zero between launches)
     const int nb = std::max(1, std::min({8, (a.cem_zeta + 47) / 48, c->part_cap}));
-    if (c->cfg.T <= 128)
-      hipLaunchKernelGGL(cem_update_kernel<2>, dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL(cem_update_kernel<4>, dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
+    const bool h32 = c->model == kModelNet && c->hidden == 32;   // plant step unrolled
+    if (c->cfg.T <= 128) {
+      if (h32) hipLaunchKernelGGL((cem_update_kernel<2, 32>), dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
+      else hipLaunchKernelGGL((cem_update_kernel<2, 0>), dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
+    } else {
+      if (h32) hipLaunchKernelGGL((cem_update_kernel<4, 32>), dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
+      else hipLaunchKernelGGL((cem_update_kernel<4, 0>), dim3(nb), dim3(kCemBlockThreads), 0, c->stream, a);
+    }
     HIP_TRY(c, hipGetLastError());
   }
   if (c->timing) {
