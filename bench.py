@@ -7,8 +7,9 @@ lambda = 6.7, Savitzky-Golay window 9; 100 warm-started iterations per Philox se
 0..9 on a synthetic plant (the same network, noise-free).  One step = one control
 step: an MPPI iteration (noise, rollouts, weights, weighted perturbation sum,
 smoothing, update), the shift of U and the plant step, fused in one kernel launch
-and driven through the C ABI (mppi_run_receding); all inputs are resident in HBM
-before timing.
+and driven through the C ABI (mppi_step_device on a device-resident plant state); all
+inputs are resident in HBM before timing, and the timed region allocates nothing and
+copies nothing to the host.
 
 Prints one JSON line with the throughput, launch and host latencies (eager and
 HIP-graph-replayed), the launch's roofline figures (algorithmic FLOP of the dynamics
@@ -81,12 +82,39 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
 
 
-def kernel_sources_sha256() -> str:
+# the sources of the precision form's kernel (rollout_quad_kernel): stored error records
+# are shown beside the measured speedups only while these files are unchanged
+QUAD_SOURCES = ["kernels_quad.hip", "kernels_common.hip.h", "device_common.h", "mppi_types.h"]
+PARITY_RECORDS = ROOT / "profiles" / "parity_records.jsonl"
+
+
+def kernel_sources_sha256(names=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in (KERNEL_SOURCES if names is None else names):
         h.update((ROOT / "paper_1707_02342_amd" / "csrc" / name).read_bytes())
     return h.hexdigest()
+
+
+def precision_errors(K: int):
+    """The precision form's error against the FP64 oracle per seed (max relative S error
+    and max |dU|, total and with the weights rounded to the operand type), from the
+    records the GPU parity tests write (tests/test_gpu_forms.py, kept under profiles/),
+    or None when the quad kernel's sources changed after they were taken."""
+    if not PARITY_RECORDS.exists():
+        return None
+    sha = kernel_sources_sha256(QUAD_SOURCES)
+    out = {}
+    for line in PARITY_RECORDS.read_text().splitlines():
+        r = json.loads(line)
+        if r.get("check") != "precision" or r.get("K") != K or r.get("schedule") != 4:
+            continue
+        if r.get("sources_sha256") != sha:
+            continue
+        name = {1: "bf16", 2: "fp16"}[r["precision"]]
+        out.setdefault(name, {})[str(r["seed"])] = {k: r[k] for k in (
+            "S_rel_max", "S_rel_max_rounded_weights", "dU_max", "dU_max_rounded_weights")}
+    return out or None
 
 
 def stored_traffic():
@@ -144,11 +172,32 @@ def write_traffic(pmc_dir: str):
     print(json.dumps(rec), flush=True)
 
 
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo) and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count() or 1
+    return model, visible
+
+
 def cpu_baseline(prob, cmap, params, x0, budget_s: float):
     """The CPU oracle (FP64, threads over samples) on full-size iterations of the same
-    workload, repeated until about budget_s seconds have been spent."""
+    workload, repeated until about budget_s seconds have been spent.  Threads: the
+    process's CPU share (OMP_NUM_THREADS when set -- 16 per GPU on the GPU hosts --
+    capped by the cores it may run on)."""
     import oracle
-    nthreads = min(16, os.cpu_count() or 1)
+    model, visible = host_cpu()
+    share = int(os.environ.get("OMP_NUM_THREADS", visible) or visible)
+    nthreads = max(1, min(share, visible))
     op = oracle.OracleProblem(prob, cmap, params, nthreads=nthreads)
     U = np.zeros((prob.T, 2), np.float32)
     t0 = time.perf_counter()
@@ -161,8 +210,9 @@ def cpu_baseline(prob, cmap, params, x0, budget_s: float):
         if el >= budget_s or n >= 1000:
             break
     return {"value": prob.K * prob.T * n / el, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": model, "host_cores_visible": visible,
             "sample": f"{n} full iterations (K={prob.K}, T={prob.T}), FP64, {nthreads} threads over samples, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s, on {model}"}
 
 
 def _timed_iterations(ctl, x0, n, stream):
@@ -212,6 +262,7 @@ def measure_precision(M, stream, iters: int = 30):
         prec["bf16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["bf16"]["ms_per_iteration"]
         prec["fp16_speedup_vs_fp32"] = prec["fp32"]["ms_per_iteration"] / prec["fp16"]["ms_per_iteration"]
         prec["workload"] = f"K={K}, T=100, 6-64-64-4 network, 256x256 ring map"
+        prec["error_vs_fp64_per_seed"] = precision_errors(K)
         return prec
 
     prec = precision_at(16384)
@@ -377,28 +428,42 @@ def main():
     ctls = [M.Controller(synth.c2_problem(seed=s), cmap, params, stream=sid, schedule=args.schedule)
             for s in range(10)]
     schedule = ctls[0].schedule
-    warm = M.Controller(synth.c2_problem(seed=99), cmap, params, stream=sid, schedule=args.schedule)
+    # each controller's plant state lives on the device; a control step is
+    # mppi_step_device (iteration, shift and plant step in one launch, no host copy)
+    xdev = [torch.tensor(x0, device="cuda") for _ in ctls]
+    x0_t = torch.from_numpy(x0.copy())
 
     def reset_all():
-        for c in ctls:
+        for c, xd in zip(ctls, xdev):
             c.set_controls(np.zeros((T, 2), np.float32))
             c.iteration = 0
+            xd.copy_(x0_t)
+        torch.cuda.synchronize()
 
     def receding(n_steps):
+        """n_steps control steps: blocks of up to 100 warm-started steps, one Philox seed
+        per block in turn, all enqueued back to back."""
         done, blk = 0, 0
         while done < n_steps:
             n = min(100, n_steps - done)
-            M.mppi_run_receding(ctls[blk % 10].ctx, x0, n)
+            ctx, ptr = ctls[blk % 10].ctx, xdev[blk % 10].data_ptr()
+            for _ in range(n):
+                M.mppi_step_device(ctx, ptr)
             done += n
             blk += 1
 
-    if args.warmup:
-        M.mppi_run_receding(warm.ctx, x0, args.warmup)
+    # warm-up: every controller runs steps of its own (its cost map, network and
+    # buffers are touched once), then all restart from x0, U = 0, iteration 0
+    for c, xd in zip(ctls, xdev):
+        for _ in range(max(1, -(-args.warmup // len(ctls)))):
+            M.mppi_step_device(c.ctx, xd.data_ptr())
     torch.cuda.synchronize()
+    reset_all()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     # timed region: `steps` receding-horizon control steps (iteration, shift and plant
-    # step fused in one launch each), no per-launch events
+    # step fused in one launch each), no per-launch events, no allocation, no host copy
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     receding(args.steps)
@@ -489,7 +554,6 @@ def main():
     }
     for cc in ctls:
         cc.close()
-    warm.close()
     if not args.no_forms:
         out["forms"] = measure_forms(M, stream)
     if not args.no_cpu:

@@ -92,6 +92,9 @@ def lib():
                                       C.c_double, dp]
         L.orc_threshold_margins.argtypes = [pp, fp, fp, fp, dp]
         L.orc_threshold_margins.restype = C.c_int
+        i32p = C.POINTER(C.c_int32)
+        L.orc_threshold_events.argtypes = [pp, fp, fp, fp, C.c_double, C.c_int32, i32p, i32p, i32p, dp, i32p]
+        L.orc_threshold_events.restype = C.c_int
         L.orc_mlp_forward.argtypes = [pp, dp, dp]
         L.orc_basis_phi.argtypes = [dp, dp, dp]
         L.orc_costmap.argtypes = [pp, C.c_double, C.c_double, dp]
@@ -363,3 +366,38 @@ def threshold_margins(op: OracleProblem, x0, U, eps) -> np.ndarray:
     if st != OK:
         raise ValueError("oracle margins status")
     return m
+
+
+class ThresholdEvents:
+    """The impulse terms a sample's FP64 trajectory decides within `window` of their
+    threshold (oracle.cpp, orc_threshold_events): per sample k, the lists t[k], kind[k]
+    (0 crash, 1 slip), value[k] (the term's size) and on[k] (whether the oracle's
+    trajectory takes it)."""
+
+    def __init__(self, n, t, kind, value, on):
+        self.n, self.t, self.kind, self.value, self.on = n, t, kind, value, on
+
+    def taken(self) -> np.ndarray:
+        """Per sample, the sum of the listed terms the oracle takes."""
+        return np.array([float(np.sum(v[o.astype(bool)])) for v, o in zip(self.value, self.on)])
+
+
+def threshold_events(op: OracleProblem, x0, U, eps, window: float = 1e-4, cap: int = 64) -> ThresholdEvents:
+    x0 = _f32(x0)
+    U = _f32(U)
+    eps = _f32(eps)
+    K = op.K
+    n = np.zeros(K, np.int32)
+    t = np.zeros((K, cap), np.int32)
+    kind = np.zeros((K, cap), np.int32)
+    val = np.zeros((K, cap), np.float64)
+    on = np.zeros((K, cap), np.int32)
+    st = lib().orc_threshold_events(op.ref(), _ptr(x0, C.c_float), _ptr(U, C.c_float), _ptr(eps, C.c_float),
+                                    float(window), int(cap), _ptr(n, C.c_int32), _ptr(t, C.c_int32),
+                                    _ptr(kind, C.c_int32), _ptr(val, C.c_double), _ptr(on, C.c_int32))
+    if st != OK:
+        raise ValueError("oracle threshold events status")
+    if n.max(initial=0) > cap:
+        raise ValueError(f"a sample has {n.max()} near-threshold terms, more than cap={cap}")
+    return ThresholdEvents(n, [t[k, :n[k]] for k in range(K)], [kind[k, :n[k]] for k in range(K)],
+                           [val[k, :n[k]] for k in range(K)], [on[k, :n[k]] for k in range(K)])

@@ -873,6 +873,50 @@ int orc_threshold_margins(const orc_problem* p, const float* x0, const float* U,
   return ORC_OK;
 }
 
+// The impulse terms of the state cost (Section VI-C) whose indicator the FP64 trajectory
+// of a sample decides within `window` of its threshold: the crash term
+// crash_cost * decay_t * [h > map_thresh] (kind 0) and the slip term
+// slip_cost * [|zeta| > slip_thresh] (kind 1), at post-step states t = 1..T.  A
+// computation whose trajectory differs from this one by rounding may take either side of
+// such an indicator; every other indicator it must take as here.  The indicators do not
+// feed back into the trajectory, so the costs such a computation may legitimately report
+// are exactly S_ref - sum(on * value) + (any subset sum of the values).  Per sample k:
+// n_out[k] = the number of such terms (all of them are counted; the first `cap` are
+// listed in t_out / kind_out / value_out / on_out [k][cap], in t order, crash before slip).
+int orc_threshold_events(const orc_problem* p, const float* x0, const float* U, const float* eps,
+                         double window, int32_t cap, int32_t* n_out, int32_t* t_out, int32_t* kind_out,
+                         double* value_out, int32_t* on_out) {
+  if (!valid_problem(p) || cap < 0 || !(window >= 0)) return ORC_E_INVAL;
+  Prob<double> P = make_prob<double>(p);
+  const int T = P.T;
+  parallel_for(P.K, p->nthreads, [&](int k) {
+    std::vector<double> tr((size_t)(T + 1) * 7);
+    rollout_one(P, x0, U, eps + (size_t)k * T * 2, P.exploration(k), tr.data());
+    int n = 0;
+    auto add = [&](int t, int kind, double value, bool on) {
+      if (n < cap) {
+        const size_t i = (size_t)k * cap + n;
+        t_out[i] = t;
+        kind_out[i] = kind;
+        value_out[i] = value;
+        on_out[i] = on ? 1 : 0;
+      }
+      ++n;
+    };
+    for (int t = 1; t <= T; ++t) {
+      const double* x = &tr[(size_t)t * 7];
+      const double h = costmap(P, x[0], x[1]);
+      const double zeta = -std::atan2(x[5], std::fabs(x[4]));
+      if (std::isfinite((double)P.map_thresh) && std::fabs(h - P.map_thresh) < window)
+        add(t, 0, P.crash_cost * P.decay[t], h > P.map_thresh);
+      if (std::isfinite((double)P.slip_thresh) && std::fabs(std::fabs(zeta) - P.slip_thresh) < window)
+        add(t, 1, P.slip_cost, std::fabs(zeta) > P.slip_thresh);
+    }
+    n_out[k] = n;
+  });
+  return ORC_OK;
+}
+
 // Single-step pieces, exported so each can be pinned on its own.
 int orc_mlp_forward(const orc_problem* p, const double* in, double* out) {
   if (!p || !p->params || p->hidden <= 0) return ORC_E_INVAL;

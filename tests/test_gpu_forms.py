@@ -17,12 +17,11 @@ import os
 import numpy as np
 import pytest
 
+import bench
+import parity_checks as pc
 import synth
 
 pytestmark = pytest.mark.gpu
-
-# error records of the precision form are appended here when the variable is set
-OUT = os.environ.get("MPPI_REPORT_DIR")
 
 
 @pytest.fixture(scope="module")
@@ -46,17 +45,8 @@ def _f16_round(a):
     return np.asarray(a, np.float32).astype(np.float16).astype(np.float32)
 
 
-def _record(name, payload):
-    if not OUT:
-        return
-    os.makedirs(OUT, exist_ok=True)
-    path = os.path.join(OUT, "forms_report.jsonl")
-    with open(path, "a") as f:
-        f.write(json.dumps({"case": name, **payload}) + "\n")
-
-
-@pytest.mark.parametrize("prec,schedule,seed,K", [(p, 4, s, 16384) for p in (1, 2) for s in range(5)] +
-                         [(p, 1, 0, 16384) for p in (1, 2)] + [(p, 4, 0, 65536) for p in (1, 2)])
+@pytest.mark.parametrize("prec,schedule,seed,K", [(p, 4, s, K) for K in (16384, 65536) for p in (1, 2)
+                                                  for s in range(5)] + [(p, 1, 0, 16384) for p in (1, 2)])
 def test_precision_form_error_vs_fp64(M, orc, prec, schedule, seed, K):
     """K=16384 (and 65536), T=100, 6-64-64-4 network, ring map, C1 cost; BF16 (1) or FP16
     (2) operands on the quad schedule (4 lanes per sample, the default) and on the lane
@@ -79,9 +69,10 @@ def test_precision_form_error_vs_fp64(M, orc, prec, schedule, seed, K):
     dU_r = np.abs(U - ref_r.U).max()
     print(f"  S rel max {rel.max():.2e} (rounded weights {rel_r.max():.2e}); |dU| {dU:.2e} ({dU_r:.2e})",
           flush=True)
-    _record(f"precision{prec}_sched{schedule}_seed{seed}_K{K}", {"S_rel_max": float(rel.max()), "S_rel_median": float(np.median(rel)),
-                                            "S_rel_max_rounded_weights": float(rel_r.max()),
-                                            "dU_max": float(dU), "dU_max_rounded_weights": float(dU_r)})
+    pc.record(check="precision", precision=prec, schedule=schedule, seed=seed, K=K, T=prob.T,
+              S_rel_max=float(rel.max()), S_rel_median=float(np.median(rel)),
+              S_rel_max_rounded_weights=float(rel_r.max()), dU_max=float(dU),
+              dU_max_rounded_weights=float(dU_r), sources_sha256=bench.kernel_sources_sha256(bench.QUAD_SOURCES))
     assert st == M.MPPI_OK
     assert rel.max() < (0.05 if prec == 1 else 0.01)
     # U is reported, not gated: at lambda = 1 the weights sit on a handful of samples, and a
