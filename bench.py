@@ -85,7 +85,7 @@ def calibrate_copy():
 # the sources of the precision form's kernel (rollout_quad_kernel): stored error records
 # are shown beside the measured speedups only while these files are unchanged
 QUAD_SOURCES = ["kernels_quad.hip", "kernels_common.hip.h", "device_common.h", "mppi_types.h"]
-PARITY_RECORDS = ROOT / "profiles" / "parity_records.jsonl"
+PARITY_RECORDS = ROOT / "profiles" / "precision_errors.jsonl"
 
 
 def kernel_sources_sha256(names=None) -> str:
@@ -452,35 +452,14 @@ def main():
             done += n
             blk += 1
 
-    # warm-up: every controller runs steps of its own (its cost map, network and
-    # buffers are touched once), then all restart from x0, U = 0, iteration 0
-    for c, xd in zip(ctls, xdev):
-        for _ in range(max(1, -(-args.warmup // len(ctls)))):
-            M.mppi_step_device(c.ctx, xd.data_ptr())
-    torch.cuda.synchronize()
-    reset_all()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    # timed region: `steps` receding-horizon control steps (iteration, shift and plant
-    # step fused in one launch each), no per-launch events, no allocation, no host copy
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    receding(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    dev_ms = ev0.elapsed_time(ev1)
-    ms_per_step = wall * 1e3 / args.steps
-    value = K * T * args.steps / wall
-
     # per-launch device time: HIP events around every launch on the library's stream,
-    # over the same steps again from the same start (the events add stream markers, so
-    # this pass is not the throughput one)
+    # over the same steps from the same start (the events add stream markers, so this
+    # pass is not the throughput one).  These passes run before the timed region, so that
+    # it starts on a device already at its steady clocks and caches.
     reset_all()
     for c in ctls:
         M.mppi_set_timing(c.ctx, True)
-    receding(args.steps)
+    receding(max(args.steps, 500))
     samples = np.concatenate([M.mppi_get_timing_samples(c.ctx) for c in ctls])
     for c in ctls:
         M.mppi_set_timing(c.ctx, False)
@@ -517,6 +496,28 @@ def main():
             lat_graph.append((time.perf_counter() - t1) * 1e6)
         del g
     lat_eager, lat_graph = np.array(lat_eager), np.array(lat_graph)
+
+    # warm-up: `warmup` untimed control steps, spread over the controllers in turn, then
+    # all restart from x0, U = 0, iteration 0
+    reset_all()
+    for i in range(args.warmup):
+        M.mppi_step_device(ctls[i % len(ctls)].ctx, xdev[i % len(ctls)].data_ptr())
+    torch.cuda.synchronize()
+    reset_all()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    # timed region: `steps` receding-horizon control steps (iteration, shift and plant
+    # step fused in one launch each), no per-launch events, no allocation, no host copy
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    receding(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / args.steps
+    value = K * T * args.steps / wall
 
     roll_ms = t_roll / max(n_roll, 1)
     flop = NET_FLOP_PER_STEP[prob.hidden] * K * T

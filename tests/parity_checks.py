@@ -47,14 +47,55 @@ def record(**fields):
     RECORDS.append(rec)
 
 
+def _compact(v):
+    """Floats to 4 significant digits (the records are read by eye and kept small)."""
+    if isinstance(v, float) and np.isfinite(v):
+        return float(f"{v:.4g}")
+    return v
+
+
+SUMMARY_FIELDS = ("max_rel_dS", "dU_iso", "dU_e2e", "dU_e2e_bound", "n_near_threshold", "n_other_side",
+                  "n_branch_excluded")
+
+
+def summary_markdown(records) -> str:
+    """Per test function (all its parameter sets) and check: the number of checked
+    iterations, their shapes, and the largest value of every field in SUMMARY_FIELDS."""
+    groups = {}
+    for r in records:
+        test = (r.get("test") or "").split("[")[0]
+        groups.setdefault((test, r.get("check")), []).append(r)
+    lines = ["| test | check | n | K | T | " + " | ".join(SUMMARY_FIELDS) + " |",
+             "|---|---|---|---|---|" + "---|" * len(SUMMARY_FIELDS)]
+    for (test, check), rs in groups.items():
+        cells = []
+        for f in SUMMARY_FIELDS:
+            vals = [r[f] for r in rs if isinstance(r.get(f), (int, float))]
+            cells.append(f"{max(vals):.3g}" if vals else "")
+        Ks = sorted({r.get("K") for r in rs if r.get("K") is not None})
+        Ts = sorted({r.get("T") for r in rs if r.get("T") is not None})
+        lines.append(f"| {test} | {check} | {len(rs)} | {','.join(map(str, Ks))} | {','.join(map(str, Ts))} | "
+                     + " | ".join(cells) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def write_records(root: Path):
+    """Appends this session's records to MPPI_PARITY_RECORD (default
+    gpurun_out/parity_records.jsonl) and writes beside it their per-test summary
+    (parity_summary.md) and the precision form's records (precision_errors.jsonl)."""
     if not RECORDS:
         return None
     path = Path(os.environ.get("MPPI_PARITY_RECORD", root / "gpurun_out" / "parity_records.jsonl"))
     path.parent.mkdir(parents=True, exist_ok=True)
     with open(path, "a") as f:
         for r in RECORDS:
-            f.write(json.dumps(r) + "\n")
+            f.write(json.dumps({k: _compact(v) for k, v in r.items()}) + "\n")
+    (path.parent / "parity_summary.md").write_text(summary_markdown(RECORDS))
+    prec = [r for r in RECORDS if r.get("check") == "precision"]
+    if prec:
+        with open(path.parent / "precision_errors.jsonl", "w") as f:
+            for r in prec:
+                f.write(json.dumps({k: _compact(v) for k, v in r.items()}) + "\n")
     return path
 
 
