@@ -260,6 +260,36 @@ mppi_status mppi_objective(mppi_ctx* ctx, const float x0[7], uint32_t iter, int3
  * network, the map or the last mppi_iterate. */
 mppi_status mppi_objective_backward(mppi_ctx* ctx, float* dJdU, float* dJdtheta);
 
+/* Allocation-free form of mppi_iterate_device, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It needs no context and calls no hipMalloc, hipFree or other allocating
+ * routine: one MPPI iteration (the same kernels, launch shape and results, bit for bit,
+ * as a context with this cfg, cost, map and network whose iteration counter is `iter`)
+ * reads the caller's device buffers and keeps everything else -- the per-block partial
+ * rows, the arrival counters, the statistics, the crash-decay and smoothing tables, and
+ * S or the status when their pointers are NULL -- in one static device array of the
+ * library (about 4.3 MiB on each device it runs on, held until the process ends).
+ * Arguments: cfg and cost as for mppi_create (cfg->schedule AUTO resolves as in
+ * mppi_set_dynamics); map_dev [H][W] row-major floats with the geometry of
+ * mppi_set_costmap; dims / params_dev the network as for mppi_set_dynamics (params_dev
+ * is read as given, not checked for finiteness); x0_dev [7]; iter the Philox counter's
+ * third word; U_dev [T][2] in/out, updated in place; S_dev [K] out (NULL: not returned);
+ * status_dev [1] out, 0 or MPPI_E_NONFINITE (NULL: not returned).  Every pointer except
+ * cfg, cost and dims is a device pointer on `device`, owned by the caller, and must
+ * stay valid until the launch has run.  The launch is enqueued on hip_stream and the call
+ * returns; only the first call on a device and a call whose (T, sg_window, sg_order,
+ * crash_decay) differs from the previous call's synchronise the device (to load the
+ * tables).  Every call on a device shares that device's array: calls whose launches
+ * overlap in time (other streams, other host threads) race; calls enqueued on one
+ * stream in turn do not.  Errors are reported by mppi_last_error(NULL).
+ * INVAL: as mppi_create and mppi_set_dynamics, plus K > 16384, sg_window > 31,
+ * weighting MPPI_WEIGHTS_CEM, or a NULL map_dev, dims, params_dev, x0_dev or U_dev. */
+mppi_status mppi_iterate_noalloc(const mppi_config* cfg, const mppi_cost* cost, int device, void* hip_stream,
+                                 const float* map_dev, int32_t H, int32_t W, float origin_x, float origin_y,
+                                 float resolution, const int32_t dims[4], const float* params_dev,
+                                 const float* x0_dev, uint32_t iter, float* U_dev, float* S_dev,
+                                 int32_t* status_dev);
+
 /* Batched form: n independent MPPI problems (instances) that share one cost map,
  * one cost and one FP32 6-32-32-4 network, each with its own K_i, T_i, x0, U and
  * iteration counter, advanced together by one persistent kernel launch per

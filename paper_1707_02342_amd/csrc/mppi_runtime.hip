@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -267,13 +268,14 @@ mppi_status drain_timing(mppi_ctx* c) {
   return MPPI_OK;
 }
 
-int blocks_for(const mppi_ctx* c, int sched) {
-  const int K = c->cfg.K;
+int blocks_for_k(int K, int sched) {
   if (sched == MPPI_SCHED_WAVE) return (K + kWaveSamplesPerBlock - 1) / kWaveSamplesPerBlock;
   if (sched == MPPI_SCHED_WIDE) return (K + kWideSamplesPerBlock - 1) / kWideSamplesPerBlock;
   if (sched == MPPI_SCHED_QUAD) return (K + kQuadSamplesPerBlock - 1) / kQuadSamplesPerBlock;
   return (K + kLaneBlockHost - 1) / kLaneBlockHost;
 }
+
+int blocks_for(const mppi_ctx* c, int sched) { return blocks_for_k(c->cfg.K, sched); }
 
 // The wave kernel keeps each lane's share of the steps (ceil(T/32) of them) in
 // registers; it is compiled for up to 4 (T <= 128) and up to 8 (T <= 256).
@@ -316,66 +318,101 @@ void launch_quad(int precision, int hidden, int G, hipStream_t stream, const Rol
 #undef MPPI_QUAD
 }
 
-RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x0_dev) {
+// The fields of a rollout launch that follow from the configuration, the cost, the map
+// geometry and the dynamics model; the caller sets the buffers and G.
+RolloutArgs config_args(const mppi_config& g, const mppi_cost& cost, int H, int W, float ox, float oy,
+                        float res, int hidden, int model, const float* x0_host) {
   RolloutArgs a{};
+  a.ckpt = nullptr;
+  a.ckpt_every = 1;
+  a.G = 0;
+  a.sg_window = g.sg_window;
+  a.update_U = 1;
+  for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
+  a.K = g.K;
+  a.T = g.T;
+  a.K_imp = importance_samples(g.K, g.explore);
+  a.cem_zeta = g.weighting == MPPI_WEIGHTS_CEM ? cem_elite_count(g.K, g.elite) : 0;
+  a.dt = g.dt;
+  a.inv_lambda = 1.0f / g.lambda;
+  a.gcs0 = g.gamma / g.sigma2[0];
+  a.gcs1 = g.gamma / g.sigma2[1];
+  a.u_lo0 = g.u_lo[0];
+  a.u_lo1 = g.u_lo[1];
+  a.u_hi0 = g.u_hi[0];
+  a.u_hi1 = g.u_hi[1];
+  a.nk.key_lo = (uint32_t)g.seed;
+  a.nk.key_hi = (uint32_t)(g.seed >> 32);
+  a.nk.iter = 0;
+  a.nk.instance = g.instance;
+  a.nk.sig0 = std::sqrt(g.sigma2[0]);
+  a.nk.sig1 = std::sqrt(g.sigma2[1]);
+  a.hidden = hidden;
+  a.model = model;
+  a.recede = 0;
+  a.u0_out = nullptr;
+  a.x_copy = nullptr;
+  a.cost.H = H;
+  a.cost.W = W;
+  a.cost.ox = ox;
+  a.cost.oy = oy;
+  a.cost.res = res;
+  a.cost.w_map = cost.w_map;
+  a.cost.w_speed = cost.w_speed;
+  a.cost.w_slip = cost.w_slip;
+  a.cost.v_des = cost.v_des;
+  a.cost.crash_cost = cost.crash_cost;
+  a.cost.map_thresh = cost.map_thresh;
+  a.cost.slip_cost = cost.slip_cost;
+  a.cost.slip_thresh = cost.slip_thresh;
+  return a;
+}
+
+RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x0_dev) {
+  RolloutArgs a = config_args(c->cfg, c->cost, c->H, c->W, c->ox, c->oy, c->res, c->hidden, c->model, x0_host);
   a.U = c->d_U;
   a.map = c->d_map;
   a.params = c->d_params;
   a.decay = c->d_decay;
   a.x0_dev = x0_dev;
-  a.ckpt = nullptr;
-  a.ckpt_every = 1;
   a.part2 = c->d_part2;
   a.cnt = c->d_cnt;
   a.sg = c->d_sg;
   a.Uout = c->d_U;
   a.stats = c->d_stats;
   a.status = c->d_status;
-  a.G = 0;
-  a.sg_window = c->cfg.sg_window;
-  a.update_U = 1;
   a.S = c->d_S;
   a.part = c->d_part;
-  for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
-  a.K = c->cfg.K;
-  a.T = c->cfg.T;
-  a.K_imp = importance_samples(c->cfg.K, c->cfg.explore);
-  a.cem_zeta = c->cfg.weighting == MPPI_WEIGHTS_CEM ? cem_elite_count(c->cfg.K, c->cfg.elite) : 0;
   a.D = c->d_D;
-  a.dt = c->cfg.dt;
-  a.inv_lambda = 1.0f / c->cfg.lambda;
-  a.gcs0 = c->cfg.gamma / c->cfg.sigma2[0];
-  a.gcs1 = c->cfg.gamma / c->cfg.sigma2[1];
-  a.u_lo0 = c->cfg.u_lo[0];
-  a.u_lo1 = c->cfg.u_lo[1];
-  a.u_hi0 = c->cfg.u_hi[0];
-  a.u_hi1 = c->cfg.u_hi[1];
-  a.nk.key_lo = (uint32_t)c->cfg.seed;
-  a.nk.key_hi = (uint32_t)(c->cfg.seed >> 32);
   a.nk.iter = c->iter;
   a.iter_dev = c->d_iter;
-  a.hidden = c->hidden;
-  a.model = c->model;
-  a.recede = 0;
-  a.u0_out = nullptr;
-  a.x_copy = nullptr;
-  a.nk.instance = c->cfg.instance;
   a.nk.sig0 = c->sig[0];
   a.nk.sig1 = c->sig[1];
-  a.cost.H = c->H;
-  a.cost.W = c->W;
-  a.cost.ox = c->ox;
-  a.cost.oy = c->oy;
-  a.cost.res = c->res;
-  a.cost.w_map = c->cost.w_map;
-  a.cost.w_speed = c->cost.w_speed;
-  a.cost.w_slip = c->cost.w_slip;
-  a.cost.v_des = c->cost.v_des;
-  a.cost.crash_cost = c->cost.crash_cost;
-  a.cost.map_thresh = c->cost.map_thresh;
-  a.cost.slip_cost = c->cost.slip_cost;
-  a.cost.slip_thresh = c->cost.slip_thresh;
   return a;
+}
+
+// The schedule the automatic choice resolves to for the network of width h (measured
+// on MI355X at T = 100: the 32-lane schedule is fastest while the chains are few and
+// latency-bound, the matrix-core quad schedule once K fills the device).
+int auto_schedule_net(const mppi_config& g, int h) {
+  if (g.schedule != MPPI_SCHED_AUTO) return g.schedule;
+  return (g.precision == MPPI_PREC_FP32 && h == 32 && g.K <= kWaveAutoMaxK) ? MPPI_SCHED_WAVE : MPPI_SCHED_QUAD;
+}
+
+// Launch the rollout kernel of schedule `sched` (resolved, not AUTO) over G blocks.
+// The caller has checked that the schedule serves the model, width and precision.
+hipError_t launch_rollout(int sched, int precision, int G, hipStream_t stream, const RolloutArgs& a) {
+  if (sched == MPPI_SCHED_WAVE) {
+    launch_wave(G, a.T, stream, a);
+  } else if (sched == MPPI_SCHED_WIDE) {
+    launch_wide(G, a.T, stream, a);
+  } else if (sched == MPPI_SCHED_QUAD) {
+    launch_quad(precision, a.hidden, G, stream, a);
+  } else {
+    hipError_t e = launch_lane(precision, a.hidden, dim3(G), stream, a);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
 }
 
 // Enqueue one iteration: rollout kernel, then weights/update kernel.
@@ -402,21 +439,13 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
     if (!pt.e0 || !pt.e1) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
     HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
   }
-  if (sched == MPPI_SCHED_WAVE) {
-    if (c->model == kModelNet && c->hidden != 32)
-      return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
-    launch_wave(G, c->cfg.T, c->stream, a);
-  } else if (sched == MPPI_SCHED_WIDE) {
-    if (c->model != kModelNet || c->hidden != 32)
-      return fail(c, MPPI_E_INVAL, "wide schedule supports the h = 32 network only");
-    launch_wide(G, c->cfg.T, c->stream, a);
-  } else if (sched == MPPI_SCHED_QUAD) {
-    if (c->model != kModelNet) return fail(c, MPPI_E_INVAL, "quad schedule supports the network only");
-    launch_quad(c->cfg.precision, c->hidden, G, c->stream, a);
-  } else {
-    HIP_TRY(c, launch_lane(c->cfg.precision, c->hidden, dim3(G), c->stream, a));
-  }
-  HIP_TRY(c, hipGetLastError());
+  if (sched == MPPI_SCHED_WAVE && c->model == kModelNet && c->hidden != 32)
+    return fail(c, MPPI_E_INVAL, "wave schedule supports hidden 32 only");
+  if (sched == MPPI_SCHED_WIDE && (c->model != kModelNet || c->hidden != 32))
+    return fail(c, MPPI_E_INVAL, "wide schedule supports the h = 32 network only");
+  if (sched == MPPI_SCHED_QUAD && c->model != kModelNet)
+    return fail(c, MPPI_E_INVAL, "quad schedule supports the network only");
+  HIP_TRY(c, launch_rollout(sched, c->cfg.precision, G, c->stream, a));
   // Algorithm 3: the rollout launch leaves costs and delta rows; the update follows
   if (a.cem_zeta > 0) {
     // blocks sharing the elite-row sum: one per ~48 elite rows, at most 8, and never more
@@ -673,14 +702,7 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     if (st != MPPI_OK) return st;
     c->hidden = h;
     c->model = kModelNet;
-    if (c->cfg.schedule == MPPI_SCHED_AUTO) {
-      // measured on MI355X at T = 100: the 32-lane schedule is fastest while the chains
-      // are few (latency-bound), the matrix-core quad schedule once K fills the device
-      if (c->cfg.precision == MPPI_PREC_FP32 && h == 32 && c->cfg.K <= kWaveAutoMaxK)
-        c->schedule = MPPI_SCHED_WAVE;
-      else
-        c->schedule = MPPI_SCHED_QUAD;
-    }
+    c->schedule = auto_schedule_net(c->cfg, h);
     return MPPI_OK;
   });
 }
@@ -1513,3 +1535,174 @@ mppi_status mppi_batch_synchronize(mppi_batch* b) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Allocation-free iteration: the launch's scratch in a static device array
+// ===========================================================================
+namespace {
+
+constexpr int kNaMaxK = 16384;       // samples per call
+constexpr int kNaMaxWindow = 31;     // Savitzky-Golay window
+constexpr int kNaMaxDevices = 64;
+constexpr size_t kNaRow = 2 + 2 * (size_t)MPPI_T_MAX;   // floats per partial row at the largest T
+// partial rows of the schedules with the most blocks (8 samples per block)
+constexpr int kNaMaxBlocks = (kNaMaxK + kWaveSamplesPerBlock - 1) / kWaveSamplesPerBlock;
+constexpr int kNaMaxGroups = merge_groups(kNaMaxBlocks);
+constexpr size_t na_round(size_t n) { return (n + 63) / 64 * 64; }   // whole 256-byte lines
+// offsets (in 4-byte words) of the regions of the scratch
+constexpr size_t kNaPart = 0;                                                    // [G][2 + 2T]
+constexpr size_t kNaPart2 = kNaPart + na_round((size_t)kNaMaxBlocks * kNaRow);    // [groups][2 + 2T]
+constexpr size_t kNaCnt = kNaPart2 + na_round((size_t)kNaMaxGroups * kNaRow);     // [groups + 1] unsigned
+constexpr size_t kNaStats = kNaCnt + na_round((size_t)kNaMaxGroups + 1);          // [2 + 2T]
+constexpr size_t kNaStatus = kNaStats + na_round(kNaRow);                         // [1] int
+constexpr size_t kNaDecay = kNaStatus + na_round(1);                              // [T + 1]
+constexpr size_t kNaSg = kNaDecay + na_round((size_t)MPPI_T_MAX + 1);             // [T][window]
+constexpr size_t kNaS = kNaSg + na_round((size_t)MPPI_T_MAX * kNaMaxWindow);      // [K] when S_dev is NULL
+constexpr size_t kNaWords = kNaS + na_round((size_t)kNaMaxK);
+static_assert(sizeof(float) == sizeof(unsigned) && sizeof(float) == sizeof(int), "word-sized regions");
+
+// The scratch of mppi_iterate_noalloc (kNaWords 4-byte words, about 4.3 MiB), one copy on
+// every device the library runs on, held until the process ends.  In host code this name
+// is a host-side stand-in, not a device address: host code uses only the address that
+// hipGetSymbolAddress returned for the device (NaDevice::ptr).
+static __device__ __align__(256) float scratch[kNaWords];
+
+__global__ void na_clear_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Per device: the scratch's address and which tables it holds.
+struct NaDevice {
+  bool ready = false;
+  float* ptr = nullptr;        // device address of `scratch` on this device
+  bool tables = false;         // decay and smoothing tables loaded for the key below
+  int T = 0, window = 0, order = 0;
+  uint32_t decay_bits = 0;
+};
+std::mutex g_na_mutex;
+NaDevice g_na[kNaMaxDevices];
+
+// Set-up on the current device, once: the scratch's address, and its arrival counters
+// zeroed by a kernel (every launch leaves them at zero again).
+mppi_status na_setup(NaDevice& d) {
+  if (d.ready) return MPPI_OK;
+  float* p = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(nullptr, MPPI_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  const int n = kNaMaxGroups + 1;
+  hipLaunchKernelGGL(na_clear_kernel, dim3((n + 255) / 256), dim3(256), 0, nullptr,
+                     reinterpret_cast<unsigned*>(p + kNaCnt), n);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(nullptr, MPPI_E_DEVICE, "clearing the scratch counters: %s", hipGetErrorString(e));
+  d.ptr = p;
+  d.ready = true;
+  return MPPI_OK;
+}
+
+// The crash-decay and Savitzky-Golay tables of (T, window, order, decay) in the scratch,
+// made on the host exactly as mppi_create makes them.  Loaded only when the key changes,
+// after a device-wide synchronisation (an earlier call may still be reading them).
+mppi_status na_tables(NaDevice& d, const mppi_config& g, const mppi_cost& cost) {
+  uint32_t bits = 0;
+  std::memcpy(&bits, &cost.crash_decay, sizeof bits);
+  const int order = g.sg_window > 1 ? g.sg_order : 0;
+  if (d.tables && d.T == g.T && d.window == g.sg_window && d.order == order && d.decay_bits == bits)
+    return MPPI_OK;
+  d.tables = false;
+  float decay[MPPI_T_MAX + 1];
+  for (int t = 0; t <= g.T; ++t) decay[t] = (float)std::pow((double)cost.crash_decay, (double)t);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(d.ptr + kNaDecay, decay, sizeof(float) * (g.T + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess && g.sg_window > 1) {
+    const std::vector<float> rows = savgol_rows(g.T, g.sg_window, g.sg_order);
+    e = hipMemcpy(d.ptr + kNaSg, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return fail(nullptr, MPPI_E_DEVICE, "loading the scratch tables: %s", hipGetErrorString(e));
+  d.tables = true;
+  d.T = g.T;
+  d.window = g.sg_window;
+  d.order = order;
+  d.decay_bits = bits;
+  return MPPI_OK;
+}
+
+mppi_status iterate_noalloc(const mppi_config* cfg, const mppi_cost* cost, int device, void* hip_stream,
+                            const float* map_dev, int32_t H, int32_t W, float origin_x, float origin_y,
+                            float resolution, const int32_t dims[4], const float* params_dev,
+                            const float* x0_dev, uint32_t iter, float* U_dev, float* S_dev, int32_t* status_dev) {
+  mppi_status st = validate_config(cfg);
+  if (st != MPPI_OK) return st;
+  st = validate_cost(cost);
+  if (st != MPPI_OK) return st;
+  if (cfg->K > kNaMaxK) return fail(nullptr, MPPI_E_INVAL, "K=%d above this entry point's maximum %d", cfg->K, kNaMaxK);
+  if (cfg->sg_window > kNaMaxWindow)
+    return fail(nullptr, MPPI_E_INVAL, "sg_window=%d above this entry point's maximum %d", cfg->sg_window,
+                kNaMaxWindow);
+  if (cfg->weighting != MPPI_WEIGHTS_IT)
+    return fail(nullptr, MPPI_E_INVAL, "this entry point forms Algorithm 2's weights only");
+  if (!map_dev || !dims || !params_dev || !x0_dev || !U_dev)
+    return fail(nullptr, MPPI_E_INVAL, "map_dev, dims, params_dev, x0_dev and U_dev must not be NULL");
+  if (H < 2 || W < 2 || (int64_t)H * W > (int64_t)1 << 30)
+    return fail(nullptr, MPPI_E_INVAL, "map size %d x %d unsupported", H, W);
+  if (!finite(origin_x) || !finite(origin_y) || !finite(resolution) || !(resolution > 0))
+    return fail(nullptr, MPPI_E_INVAL, "origin must be finite and resolution > 0");
+  const int h = dims[1];
+  if (dims[0] != 6 || dims[3] != 4 || dims[1] != dims[2] || (h != 32 && h != 64))
+    return fail(nullptr, MPPI_E_INVAL, "dims must be {6, h, h, 4} with h = 32 or 64");
+  const int sched = auto_schedule_net(*cfg, h);
+  if (multi_lane(sched) && (cfg->precision != MPPI_PREC_FP32 || h != 32))
+    return fail(nullptr, MPPI_E_INVAL, "the wave and wide schedules run the FP32 h = 32 network only");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, MPPI_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev || device >= kNaMaxDevices)
+    return fail(nullptr, MPPI_E_INVAL, "device %d outside [0, %d)", device, std::min(ndev, kNaMaxDevices));
+  std::lock_guard<std::mutex> lock(g_na_mutex);
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, MPPI_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  NaDevice& d = g_na[device];
+  st = na_setup(d);
+  if (st != MPPI_OK) return st;
+  st = na_tables(d, *cfg, *cost);
+  if (st != MPPI_OK) return st;
+  RolloutArgs a = config_args(*cfg, *cost, H, W, origin_x, origin_y, resolution, h, kModelNet, nullptr);
+  float* p = d.ptr;
+  a.U = U_dev;
+  a.Uout = U_dev;
+  a.map = map_dev;
+  a.params = params_dev;
+  a.decay = p + kNaDecay;
+  a.x0_dev = x0_dev;
+  a.S = S_dev ? S_dev : p + kNaS;
+  a.part = p + kNaPart;
+  a.part2 = p + kNaPart2;
+  a.cnt = reinterpret_cast<unsigned*>(p + kNaCnt);
+  a.sg = cfg->sg_window > 1 ? p + kNaSg : nullptr;
+  a.stats = p + kNaStats;
+  a.status = status_dev ? reinterpret_cast<int*>(status_dev) : reinterpret_cast<int*>(p + kNaStatus);
+  a.D = nullptr;
+  a.nk.iter = iter;
+  a.iter_dev = nullptr;
+  a.G = blocks_for_k(cfg->K, sched);
+  e = launch_rollout(sched, cfg->precision, a.G, (hipStream_t)hip_stream, a);
+  if (e != hipSuccess) return fail(nullptr, MPPI_E_DEVICE, "rollout launch: %s", hipGetErrorString(e));
+  return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" mppi_status mppi_iterate_noalloc(const mppi_config* cfg, const mppi_cost* cost, int device,
+                                            void* hip_stream, const float* map_dev, int32_t H, int32_t W,
+                                            float origin_x, float origin_y, float resolution,
+                                            const int32_t dims[4], const float* params_dev, const float* x0_dev,
+                                            uint32_t iter, float* U_dev, float* S_dev, int32_t* status_dev) {
+  g_create_error.clear();
+  try {
+    return iterate_noalloc(cfg, cost, device, hip_stream, map_dev, H, W, origin_x, origin_y, resolution, dims,
+                           params_dev, x0_dev, iter, U_dev, S_dev, status_dev);
+  } catch (...) {
+    return fail(nullptr, MPPI_E_DEVICE, "unexpected internal error");
+  }
+}

@@ -17,12 +17,12 @@ constexpr int kTMax = 256;
 // groups of merge_group_size(G) consecutive blocks, then the merge_groups(G) group
 // rows.  16 up to 256 blocks, ceil(sqrt(G)) beyond, so neither level grows faster
 // than sqrt(G).
-__host__ __device__ inline int merge_group_size(int G) {
+__host__ __device__ constexpr inline int merge_group_size(int G) {
   int s = 16;
   while (s * s < G) ++s;
   return s;
 }
-__host__ __device__ inline int merge_groups(int G) {
+__host__ __device__ constexpr inline int merge_groups(int G) {
   const int s = merge_group_size(G);
   return (G + s - 1) / s;
 }

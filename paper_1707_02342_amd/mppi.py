@@ -35,7 +35,7 @@ EXPORTED = [
     "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error", "mppi_batch_set_costmap",
     "mppi_batch_set_dynamics", "mppi_batch_set_controls", "mppi_batch_iterate",
     "mppi_batch_get_controls", "mppi_batch_get_costs", "mppi_batch_get_schedule",
-    "mppi_batch_synchronize",
+    "mppi_batch_synchronize", "mppi_iterate_noalloc",
 ]
 
 
@@ -114,6 +114,9 @@ def lib() -> C.CDLL:
         L.mppi_batch_get_costs.argtypes = [vp, C.c_int32, fp]
         L.mppi_batch_get_schedule.argtypes = [vp, i32p, i32p, C.POINTER(C.c_double)]
         L.mppi_batch_synchronize.argtypes = [vp]
+        L.mppi_iterate_noalloc.argtypes = [C.POINTER(mppi_config), C.POINTER(mppi_cost), C.c_int, vp, vp,
+                                           C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, i32p, vp, vp,
+                                           C.c_uint32, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("mppi_destroy", "mppi_last_error", "mppi_batch_destroy", "mppi_batch_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -363,6 +366,21 @@ def mppi_batch_get_schedule(b):
 
 def mppi_batch_synchronize(b) -> None:
     _bcheck(b, lib().mppi_batch_synchronize(b))
+
+
+def mppi_iterate_noalloc(cfg: mppi_config, cost: mppi_cost, device: int, stream: int, map_dev: int, H: int,
+                         W: int, origin_x: float, origin_y: float, resolution: float, hidden: int,
+                         params_dev: int, x0_dev: int, it: int, U_dev: int, S_dev: int = 0,
+                         status_dev: int = 0) -> None:
+    """One context-free iteration on device buffers (pointers as integers, e.g.
+    data_ptr()); nothing is allocated.  Errors raise with mppi_last_error(NULL)."""
+    dims = (C.c_int32 * 4)(6, hidden, hidden, 4)
+    vp = C.c_void_p
+    st = lib().mppi_iterate_noalloc(C.byref(cfg), C.byref(cost), device, vp(stream or None), vp(map_dev), H, W,
+                                    origin_x, origin_y, resolution, dims, vp(params_dev), vp(x0_dev), it,
+                                    vp(U_dev), vp(S_dev or None), vp(status_dev or None))
+    if st != MPPI_OK:
+        raise MppiError(st, mppi_last_error(None))
 
 
 class Batch:

@@ -115,3 +115,36 @@ def test_binding_fails_loudly_without_library(M, monkeypatch, tmp_path):
     monkeypatch.setattr(M, "LIB_PATH", tmp_path / "missing.so")
     with pytest.raises(ImportError):
         M.lib()
+
+
+@pytest.mark.parametrize("case", ["K", "window", "cem", "null_map", "null_U", "dims", "wave_h64", "bad_map"])
+def test_iterate_noalloc_rejects_before_device_work(M, case):
+    """The allocation-free entry point validates everything it can before touching a
+    device: its size limits, Algorithm 3, NULL buffers and the network shape."""
+    prob = synth.c1_problem()
+    cfg = M.make_config(prob)
+    cost = M.make_cost(prob.cost)
+    dims = (C.c_int32 * 4)(6, 32, 32, 4)
+    ptr = C.c_void_p(0x1000)            # never dereferenced: every case fails validation
+    args = dict(map_dev=ptr, H=256, W=256, params=ptr, x0=ptr, U=ptr)
+    if case == "K":
+        cfg.K = 16385
+    elif case == "window":
+        cfg.T, cfg.sg_window, cfg.sg_order = 64, 33, 2
+    elif case == "cem":
+        cfg.weighting = M.MPPI_WEIGHTS_CEM
+    elif case == "null_map":
+        args["map_dev"] = None
+    elif case == "null_U":
+        args["U"] = None
+    elif case == "dims":
+        dims = (C.c_int32 * 4)(6, 48, 48, 4)
+    elif case == "wave_h64":
+        cfg.schedule = M.MPPI_SCHED_WAVE
+        dims = (C.c_int32 * 4)(6, 64, 64, 4)
+    elif case == "bad_map":
+        args["H"] = 1
+    st = M.lib().mppi_iterate_noalloc(C.byref(cfg), C.byref(cost), 0, None, args["map_dev"], args["H"], 256,
+                                      0.0, 0.0, 0.1, dims, args["params"], args["x0"], 0, args["U"], None, None)
+    assert st == M.MPPI_E_INVAL
+    assert M.mppi_last_error(None) != ""
