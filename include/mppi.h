@@ -81,8 +81,14 @@ enum { MPPI_SCHED_AUTO = 0, MPPI_SCHED_LANE = 1, MPPI_SCHED_WAVE = 2, MPPI_SCHED
  * >= sg_window; precision not one of MPPI_PREC_*; schedule not one of MPPI_SCHED_*;
  * explore not in [0, 1]; weighting not one of MPPI_WEIGHTS_*; with MPPI_WEIGHTS_CEM,
  * elite not in [0, 1) or round(K (1 - elite)) < 1 (computed in FP64 from the FP32 value).
+ * K-shard form (the sample-level parallelism of Section III-D-5 spread over several
+ * devices or contexts): with k_total > 0 the context draws the samples of global indices
+ * k_base .. k_base + K - 1 of an iteration of k_total samples.  INVAL: k_total != 0 and
+ * k_total < k_base + K (or > 1<<30), k_total == 0 with k_base != 0, or a sharded
+ * context with MPPI_WEIGHTS_CEM (Algorithm 3 needs one selection over all samples).
  * Exploration samples (Algorithm 1's alpha and the disturbance discussion of
- * Section IV): sample k is drawn around zero when k >= ceil((1 - explore) K).  For every
+ * Section IV): sample k (global index) is drawn around zero when
+ * k >= ceil((1 - explore) k_total), k_total = K when unsharded.  For every
  * sample delta_t = v_t - u_t enters the running cost as gamma u_t^T Sigma^-1 delta_t
  * (the paper's gamma u^T Sigma^-1 v up to a constant shared by all samples) and the
  * update as U <- U + SGF * sum_k w_k delta_k (Eq. IT-Controls).  With explore = 0,
@@ -107,6 +113,10 @@ typedef struct {
                            0 = every sample around U                              */
   int32_t weighting;    /* MPPI_WEIGHTS_*                                          */
   float elite;          /* Algorithm 3's eliteness threshold (0.8: the best 20 %)  */
+  uint32_t k_base;      /* K-shard form: global index of this context's sample 0; the
+                           Philox counter's second word is the global index k_base + k */
+  int32_t k_total;      /* K-shard form: samples of the whole iteration over all shards
+                           (0 = unsharded: this context's K, with k_base = 0)         */
 } mppi_config;
 
 /* State cost c(x, t) at the post-step state x_t, t = 1..T (Section VI-C):
@@ -207,6 +217,27 @@ mppi_status mppi_run_receding(mppi_ctx* ctx, const float x0[7], int32_t n_iter,
  * synchronising call (mppi_get_controls, mppi_shift). */
 mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
 
+/* K-shard form, step 1 (Algorithm 2 over samples spread across shards): one iteration of
+ * this context's K samples from x0[7] (host) that ends, in place of the update, with the
+ * shard's merged partial in row_dev (device, [2 + 2T] floats, written by the launch):
+ *   row_dev[0] = rho_g = min_k S_k,  row_dev[1] = eta_g = sum_k exp(-(S_k - rho_g)/lambda),
+ *   row_dev[2 + 2t + i] = N_g[t][i] = sum_k exp(-(S_k - rho_g)/lambda) delta_{k,t,i}
+ * (eta_g = 0 when no sample of the shard has a finite cost).  U and the statistics are
+ * not changed; the iteration counter advances.  Enqueued, unless costs_out ([K] host
+ * floats, nullable) asks for the shard's S_k, which synchronises; row_dev must stay
+ * valid until the launch has run.  INVAL: row_dev NULL, a non-finite x0,
+ * MPPI_WEIGHTS_CEM.  STATE: map or dynamics not set. */
+mppi_status mppi_iterate_partial(mppi_ctx* ctx, const float x0[7], float* row_dev, float* costs_out);
+
+/* K-shard form, step 2: merge the n_rows partial rows of one iteration's shards (device,
+ * [n_rows][2 + 2T], e.g. gathered from every shard) exactly as the blocks of one launch
+ * are merged (rho = min_g rho_g, eta~ = sum_g exp(-(rho_g - rho)/lambda) eta_g,
+ * Delta = sum_g exp(-(rho_g - rho)/lambda) N_g / eta~), then smooth and update U and the
+ * statistics as mppi_iterate does.  The iteration counter does not advance.  Enqueued;
+ * the status (MPPI_E_NONFINITE when no shard had a finite cost) is read by the next
+ * synchronising call.  INVAL: rows_dev NULL or n_rows outside [1, 65536]. */
+mppi_status mppi_merge_update(mppi_ctx* ctx, const float* rows_dev, int32_t n_rows);
+
 /* Diagnostics of the most recent iteration (synchronises): rho = min_k S_k,
  * eta~ = sum_k exp(-(S_k - rho)/lambda), and the unsmoothed update
  * Delta_t = sum_k w_k delta_{k,t} ([T][2]).  With MPPI_WEIGHTS_CEM, rho is the largest
@@ -294,7 +325,7 @@ mppi_status mppi_iterate_noalloc(const mppi_config* cfg, const mppi_cost* cost, 
  * one cost and one FP32 6-32-32-4 network, each with its own K_i, T_i, x0, U and
  * iteration counter, advanced together by one persistent kernel launch per
  * mppi_batch_iterate (replayed from a HIP graph).  Instance i draws its noise with
- * Philox counter word 4 = cfg->instance + i.  cfg->schedule picks the work tiles:
+ * Philox counter word 4 = cfg->instance + i (cfg->k_base and cfg->k_total must be 0).  cfg->schedule picks the work tiles:
  * MPPI_SCHED_QUAD or AUTO (tiles of 64 samples, matrix-core network) or
  * MPPI_SCHED_LANE (tiles of 256); instance i then reproduces, bit for bit, a
  * single-problem context with K_i, T_i, that instance word and that schedule.

@@ -20,7 +20,10 @@ import numpy as np
 
 HERE = Path(__file__).resolve().parent
 SRC = HERE / "oracle.cpp"
-LIB = HERE / "liboracle.so"
+PLAIN_LIB = HERE / "liboracle.so"
+# the library loaded: MPPI_ORACLE_LIB names another build of the same source (the
+# sanitizer test mode, oracle/sanitize.py); by default the plain build
+LIB = Path(os.environ.get("MPPI_ORACLE_LIB", PLAIN_LIB))
 
 OK, E_INVAL, E_NONFINITE = 0, 1, 5
 WEIGHTS_IT, WEIGHTS_CEM = 0, 1
@@ -32,11 +35,11 @@ CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 def build(force: bool = True) -> Path:
     """Compile the oracle with g++ (plain C++17, no contraction, IEEE div/sqrt)."""
-    if force or not LIB.exists():
-        tmp = LIB.with_suffix(".so.tmp")
+    if force or not PLAIN_LIB.exists():
+        tmp = PLAIN_LIB.with_suffix(".so.tmp")
         subprocess.run(["g++", *CXXFLAGS, str(SRC), "-o", str(tmp)], check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, PLAIN_LIB)
+    return PLAIN_LIB
 
 
 class Problem(C.Structure):
@@ -63,6 +66,8 @@ def lib():
     global _lib
     if _lib is None:
         if not LIB.exists():
+            if LIB != PLAIN_LIB:
+                raise ImportError(f"{LIB} (MPPI_ORACLE_LIB) does not exist")
             build(force=True)
         L = C.CDLL(str(LIB))
         fp = C.POINTER(C.c_float)

@@ -1,7 +1,7 @@
 // Device-side primitives of the MPPI kernels (gfx950).
 //
 //  * Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11),
-//    counter (t, k, iter, instance), key (seed_lo, seed_hi).
+//    counter (t, k, iter, instance) with k the global sample index, key (seed_lo, seed_hi).
 //  * Box-Muller transform (Box & Muller 1958) on the first two words, with this
 //    project's FP32 log (exponent split + atanh series) and quadrant-reduced
 //    sin/cos (Taylor series in (pi/2) r); every operation is an IEEE single
@@ -104,9 +104,10 @@ __device__ __forceinline__ void noise_cs(uint32_t w, float& c_out, float& s_out)
 }
 
 // eps_{k,t} for iteration `iter`: sqrt(Sigma_ii) * (R cos, R sin), R = sqrt(-2 ln u1).
+// k is the launch's sample index; the counter takes the global one, nk.k_base + k.
 __device__ __forceinline__ void draw_eps(uint32_t t, uint32_t k, const NoiseKey& nk, float& e0,
                                          float& e1) {
-  const U32x4 r = philox10(t, k, nk.iter, nk.instance, nk.key_lo, nk.key_hi);
+  const U32x4 r = philox10(t, nk.k_base + k, nk.iter, nk.instance, nk.key_lo, nk.key_hi);
   const float L = noise_ln(r.x);
   const float R = __builtin_sqrtf(-2.0f * L);
   float c, s;

@@ -386,6 +386,21 @@ struct FinalStage {
       if (a.recede) receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds);
     }
   }
+
+  // K-shard form: the merged row (rho, eta, N[2T] in lds) of this launch's samples goes to
+  // a.row_out in place of the update; U and the statistics are left unchanged.  Called
+  // by the whole block.
+  __device__ __forceinline__ void export_row(const RolloutArgs& a, const float* lds, float rho, float eta) {
+    const int tid = threadIdx.x, T2 = 2 * a.T;
+    __syncthreads();
+    for (int o = tid; o < T2; o += NT) a.row_out[2 + o] = lds[o];
+    if (tid == 0) {
+      a.row_out[0] = rho;
+      a.row_out[1] = eta;
+      *a.status = 0;
+      if (a.iter_dev) *a.iter_dev = a.nk.iter + 1u;
+    }
+  }
 };
 
 // Called by every rollout block with its partial row (rho_g, eta_g and N_g[2T] in
@@ -432,8 +447,12 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
       }
     }
     if (final_merge) {
-      const bool fin = (rho < kInf) && (eta > 0.0f);
-      fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, rho, fin ? eta : 0.0f);
+      if (a.row_out) {
+        fs.export_row(a, lds, rho, eta);
+      } else {
+        const bool fin = (rho < kInf) && (eta > 0.0f);
+        fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, rho, fin ? eta : 0.0f);
+      }
     }
   }
   __syncthreads();

@@ -93,4 +93,21 @@ __global__ __launch_bounds__(256) void noise_kernel(NoiseKey nk, int K, int T, f
   eps[2 * (size_t)idx + 1] = e1;
 }
 
+// K-shard merge: the n partial rows (rho_g, eta_g, N_g[T][2]) that the shards of one
+// iteration exported are merged exactly as the blocks of one launch are (Algorithm 2:
+// rho = min_g rho_g, eta~ = sum_g exp(-(rho_g - rho)/lambda) eta_g, Delta = the same
+// combination of the N_g over eta~), then smoothed and applied to U, with the statistics
+// and the status, by the final stage of the rollout kernels.  One block.
+__global__ __launch_bounds__(256) void merge_update_kernel(RolloutArgs a, const float* rows, int n) {
+  __shared__ float lds[2 * kTMax];
+  __shared__ float s_small[2 * kMergeChunk];
+  FinalStage<256, kModelNet, false> fs;
+  fs.prefetch(a);
+  float rho, eta;
+  merge_rows<256>(rows, n, 2 + 2 * a.T, 2 * a.T, a.inv_lambda, lds, s_small, rho, eta);
+  __syncthreads();
+  const bool fin = (rho < kInf) && (eta > 0.0f);
+  fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, rho, fin ? eta : 0.0f);
+}
+
 }  // namespace mppi

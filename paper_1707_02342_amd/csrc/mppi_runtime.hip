@@ -27,6 +27,7 @@ size_t wide_smem_bytes(int T);
 template <int NQ> __global__ void rollout_wide_kernel(RolloutArgs);
 template <int PREC, int HID> __global__ void rollout_quad_kernel(RolloutArgs);
 __global__ void shift_kernel(float*, int, float*);
+__global__ void merge_update_kernel(RolloutArgs, const float*, int);
 template <int HID>
 __global__ void plant_kernel(const float*, const float*, const float*, float*, float*, float, float,
                              float, float, float);
@@ -180,6 +181,15 @@ mppi_status validate_config(const mppi_config* c) {
     if (cem_elite_count(c->K, c->elite) < 1)
       return fail(nullptr, MPPI_E_INVAL, "round(K (1 - elite)) must be at least 1");
   }
+  if (c->k_total == 0) {
+    if (c->k_base != 0) return fail(nullptr, MPPI_E_INVAL, "k_base=%u needs k_total (the sharded iteration's size)", c->k_base);
+  } else {
+    if (c->k_total < 0 || c->k_total > (1 << 30) || (int64_t)c->k_base + c->K > (int64_t)c->k_total)
+      return fail(nullptr, MPPI_E_INVAL, "shard k_base=%u, K=%d does not fit k_total=%d (at most 1<<30)", c->k_base,
+                  c->K, c->k_total);
+    if (c->weighting == MPPI_WEIGHTS_CEM)
+      return fail(nullptr, MPPI_E_INVAL, "Algorithm 3 selects over all samples at once; shards merge Algorithm 2 only");
+  }
   return MPPI_OK;
 }
 
@@ -188,6 +198,14 @@ mppi_status validate_config(const mppi_config* c) {
 int importance_samples(int K, float explore) {
   const double n = std::ceil((1.0 - (double)explore) * (double)K);
   return (int)std::min<double>(std::max<double>(n, 0.0), (double)K);
+}
+
+// The same split in a shard's local indices: the iteration's first
+// ceil((1 - alpha) k_total) global samples are importance samples.
+int importance_samples_shard(const mppi_config& g) {
+  if (g.k_total == 0) return importance_samples(g.K, g.explore);
+  const double n = std::ceil((1.0 - (double)g.explore) * (double)g.k_total) - (double)g.k_base;
+  return (int)std::min<double>(std::max<double>(n, 0.0), (double)g.K);
 }
 
 mppi_status validate_cost(const mppi_cost* c) {
@@ -331,7 +349,7 @@ RolloutArgs config_args(const mppi_config& g, const mppi_cost& cost, int H, int 
   for (int i = 0; i < kStateDim; ++i) a.x0[i] = x0_host ? x0_host[i] : 0.0f;
   a.K = g.K;
   a.T = g.T;
-  a.K_imp = importance_samples(g.K, g.explore);
+  a.K_imp = importance_samples_shard(g);
   a.cem_zeta = g.weighting == MPPI_WEIGHTS_CEM ? cem_elite_count(g.K, g.elite) : 0;
   a.dt = g.dt;
   a.inv_lambda = 1.0f / g.lambda;
@@ -347,6 +365,8 @@ RolloutArgs config_args(const mppi_config& g, const mppi_cost& cost, int H, int 
   a.nk.instance = g.instance;
   a.nk.sig0 = std::sqrt(g.sigma2[0]);
   a.nk.sig1 = std::sqrt(g.sigma2[1]);
+  a.nk.k_base = g.k_base;
+  a.row_out = nullptr;
   a.hidden = hidden;
   a.model = model;
   a.recede = 0;
@@ -420,7 +440,7 @@ hipError_t launch_rollout(int sched, int precision, int G, hipStream_t stream, c
 // also the shift of U and the plant step of the state in x0_dev (in place), u_0 to
 // u0_out and the new state to x_copy (both device, nullable).
 mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0_dev, bool recede = false,
-                              float* u0_out = nullptr, float* x_copy = nullptr) {
+                              float* u0_out = nullptr, float* x_copy = nullptr, float* row_out = nullptr) {
   if (!c->have_map || !c->have_dyn)
     return fail(c, MPPI_E_STATE, "set the cost map and the dynamics before iterating");
   const int sched = c->schedule;
@@ -432,6 +452,9 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   a.recede = recede ? 1 : 0;
   a.u0_out = u0_out;
   a.x_copy = x_copy;
+  a.row_out = row_out;
+  if (row_out && (a.cem_zeta > 0 || recede))
+    return fail(c, MPPI_E_INVAL, "a shard's partial row is Algorithm 2's and ends no receding step");
   PendingTiming pt{};
   if (c->timing) {
     pt.e0 = take_event(c);
@@ -870,7 +893,8 @@ mppi_status mppi_get_noise(mppi_ctx* c, uint32_t iter, float* eps_out) {
     const size_t n = (size_t)c->cfg.K * c->cfg.T;
     float* d = nullptr;
     HIP_TRY(c, hipMalloc(&d, sizeof(float) * 2 * n));
-    NoiseKey nk{(uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32), iter, c->cfg.instance, c->sig[0], c->sig[1]};
+    NoiseKey nk{(uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32), iter, c->cfg.instance, c->sig[0], c->sig[1],
+                c->cfg.k_base};
     hipLaunchKernelGGL(noise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, nk, c->cfg.K,
                        c->cfg.T, d);
     hipError_t e = hipGetLastError();
@@ -928,6 +952,39 @@ mppi_status mppi_step_device(mppi_ctx* c, float* x_dev, float* u0_out_dev) {
   });
 }
 
+mppi_status mppi_iterate_partial(mppi_ctx* c, const float x0[7], float* row_dev, float* costs_out) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x0 || !row_dev) return fail(c, MPPI_E_INVAL, "x0 or row_dev is NULL");
+    for (int i = 0; i < kStateDim; ++i)
+      if (!finite(x0[i])) return fail(c, MPPI_E_INVAL, "x0[%d] is not finite", i);
+    if (c->cfg.weighting != MPPI_WEIGHTS_IT)
+      return fail(c, MPPI_E_INVAL, "a shard's partial row is Algorithm 2's (MPPI_WEIGHTS_IT)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    mppi_status st = enqueue_iteration(c, x0, nullptr, false, nullptr, nullptr, row_dev);
+    if (st != MPPI_OK || !costs_out) return st;
+    HIP_TRY(c, hipMemcpyAsync(costs_out, c->d_S, sizeof(float) * c->cfg.K, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MPPI_OK;
+  });
+}
+
+mppi_status mppi_merge_update(mppi_ctx* c, const float* rows_dev, int32_t n_rows) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!rows_dev || n_rows < 1 || n_rows > 65536)
+      return fail(c, MPPI_E_INVAL, "need rows_dev and 1..65536 rows");
+    HIP_TRY(c, hipSetDevice(c->device));
+    c->objective_ready = false;
+    RolloutArgs a = rollout_args(c, nullptr, nullptr);
+    a.iter_dev = nullptr;   // the shards' launches advanced the counter
+    a.G = 1;
+    hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(256), 0, c->stream, a, rows_dev, (int)n_rows);
+    HIP_TRY(c, hipGetLastError());
+    return MPPI_OK;
+  });
+}
+
 mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
   if (!c || !schedule) return MPPI_E_INVAL;
   *schedule = c->schedule;
@@ -975,6 +1032,8 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
       return fail(c, MPPI_E_INVAL, "the objective is defined for importance samples only (explore = 0)");
     if (c->cfg.weighting != MPPI_WEIGHTS_IT)
       return fail(c, MPPI_E_INVAL, "the objective is defined for Algorithm 2's weights only");
+    if (c->cfg.k_total != 0)
+      return fail(c, MPPI_E_INVAL, "the objective is evaluated over an unsharded iteration (k_total = 0)");
     HIP_TRY(c, hipSetDevice(c->device));
     const int K = c->cfg.K, T = c->cfg.T;
     const int n_ckpt = T / ckpt_every + 1;
@@ -1328,6 +1387,8 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
   if (!out) return bfail(nullptr, MPPI_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!cfg || !K || !T || n < 1 || n > 65536) return bfail(nullptr, MPPI_E_INVAL, "need 1..65536 instances with K and T");
+  if (cfg->k_base != 0 || cfg->k_total != 0)
+    return bfail(nullptr, MPPI_E_INVAL, "the batched form's instances are unsharded (k_base = k_total = 0)");
   int sgmax = 0;
   for (int i = 0; i < n; ++i) {
     mppi_config c = *cfg;

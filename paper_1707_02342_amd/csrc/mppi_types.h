@@ -34,6 +34,7 @@ struct NoiseKey {
   uint32_t iter;             // third counter word
   uint32_t instance;         // fourth counter word
   float sig0, sig1;
+  uint32_t k_base;           // global index of sample 0 (second counter word = k_base + k)
 };
 
 // Cost map geometry and state-cost weights.
@@ -91,6 +92,10 @@ struct RolloutArgs {
   int recede;
   float* u0_out;           // nullable: [2] u_0 of this step
   float* x_copy;           // nullable: [7] a copy of the new plant state
+  // K-shard form: when set, the final merge writes the launch's merged row
+  // (rho, eta, N[T][2]) here ([2 + 2T]) and leaves U, the statistics and the smoothing
+  // to a later merge of every shard's row (merge_update_kernel).
+  float* row_out;
 };
 
 constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)

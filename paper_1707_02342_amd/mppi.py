@@ -35,7 +35,7 @@ EXPORTED = [
     "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error", "mppi_batch_set_costmap",
     "mppi_batch_set_dynamics", "mppi_batch_set_controls", "mppi_batch_iterate",
     "mppi_batch_get_controls", "mppi_batch_get_costs", "mppi_batch_get_schedule",
-    "mppi_batch_synchronize", "mppi_iterate_noalloc",
+    "mppi_batch_synchronize", "mppi_iterate_noalloc", "mppi_iterate_partial", "mppi_merge_update",
 ]
 
 
@@ -45,7 +45,7 @@ class mppi_config(C.Structure):
                 ("u_hi", C.c_float * 2), ("sg_window", C.c_int32), ("sg_order", C.c_int32),
                 ("precision", C.c_int32), ("schedule", C.c_int32), ("seed", C.c_uint64),
                 ("instance", C.c_uint32), ("explore", C.c_float), ("weighting", C.c_int32),
-                ("elite", C.c_float)]
+                ("elite", C.c_float), ("k_base", C.c_uint32), ("k_total", C.c_int32)]
 
 
 class mppi_cost(C.Structure):
@@ -114,6 +114,8 @@ def lib() -> C.CDLL:
         L.mppi_batch_get_costs.argtypes = [vp, C.c_int32, fp]
         L.mppi_batch_get_schedule.argtypes = [vp, i32p, i32p, C.POINTER(C.c_double)]
         L.mppi_batch_synchronize.argtypes = [vp]
+        L.mppi_iterate_partial.argtypes = [vp, fp, vp, fp]
+        L.mppi_merge_update.argtypes = [vp, vp, C.c_int32]
         L.mppi_iterate_noalloc.argtypes = [C.POINTER(mppi_config), C.POINTER(mppi_cost), C.c_int, vp, vp,
                                            C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, i32p, vp, vp,
                                            C.c_uint32, vp, vp, vp]
@@ -233,6 +235,19 @@ def mppi_run_receding(ctx, x0, n_iter: int):
 def mppi_step_device(ctx, x_dev_ptr: int, u0_dev_ptr: int = 0) -> None:
     """One receding-horizon step on device data (pointers as integers, e.g. data_ptr())."""
     _check(ctx, lib().mppi_step_device(ctx, C.c_void_p(x_dev_ptr), C.c_void_p(u0_dev_ptr or None)))
+
+
+def mppi_iterate_partial(ctx, x0, row_dev_ptr: int, costs_out: Optional[np.ndarray] = None) -> None:
+    """K-shard form: one iteration of this context's samples whose merged row
+    (rho_g, eta_g, N_g[T][2]) goes to the device buffer at row_dev_ptr ([2 + 2T] floats);
+    the shard's costs into costs_out when given."""
+    x = _f32(x0)
+    _check(ctx, lib().mppi_iterate_partial(ctx, _fp(x), C.c_void_p(row_dev_ptr), _fp(costs_out)))
+
+
+def mppi_merge_update(ctx, rows_dev_ptr: int, n_rows: int) -> None:
+    """K-shard form: merge n_rows shard rows ([n_rows][2 + 2T] on the device) and update U."""
+    _check(ctx, lib().mppi_merge_update(ctx, C.c_void_p(rows_dev_ptr), n_rows))
 
 
 def mppi_get_stats(ctx, T: int):
@@ -451,6 +466,8 @@ def make_config(prob, precision: int = MPPI_PREC_FP32, schedule: int = MPPI_SCHE
     c.explore = float(getattr(prob, "explore", 0.0))
     c.weighting = int(getattr(prob, "weighting", MPPI_WEIGHTS_IT))
     c.elite = float(getattr(prob, "elite", 0.8))
+    c.k_base = int(getattr(prob, "k_base", 0))
+    c.k_total = int(getattr(prob, "k_total", 0))
     return c
 
 

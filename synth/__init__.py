@@ -269,6 +269,8 @@ class Problem:
     weighting: int = 0                   # 0: Algorithm 2 (information theoretic), 1: Algorithm 3 (CEM)
     elite: float = 0.8                   # Algorithm 3's eliteness threshold (percentile)
     cost: CostParams = field(default_factory=CostParams)
+    k_base: int = 0                      # K-shard form: global index of this shard's sample 0
+    k_total: int = 0                     # K-shard form: samples of the whole iteration (0: unsharded)
 
     @property
     def gamma_value(self) -> float:

@@ -42,12 +42,14 @@ def test_exports_every_declared_symbol(M):
 def test_struct_layout_matches_header(M):
     # int32 K, T; float dt, lambda, gamma, sigma2[2], u_lo[2], u_hi[2]; int32 sg_window, sg_order,
     # precision, schedule; uint64 seed; uint32 instance; float explore; int32 weighting;
-    # float elite -> 15*4 + pad 4 + 8 + 4 + 4 + 4 + 4 = 88
-    assert C.sizeof(M.mppi_config) == 88
+    # float elite; uint32 k_base; int32 k_total -> 15*4 + pad 4 + 8 + 6*4 = 96
+    assert C.sizeof(M.mppi_config) == 96
     assert M.mppi_config.seed.offset == 64
     assert M.mppi_config.explore.offset == 76
     assert M.mppi_config.weighting.offset == 80
     assert M.mppi_config.elite.offset == 84
+    assert M.mppi_config.k_base.offset == 88
+    assert M.mppi_config.k_total.offset == 92
     assert C.sizeof(M.mppi_cost) == 36
 
 
@@ -67,6 +69,7 @@ def _cfg(M, **kw):
     ("sigma2", (0.0, 0.3)), ("sigma2", (0.3, -1.0)), ("sigma2", (float("inf"), 0.3)),
     ("u_lo", (1.5, -1.0)), ("sg_window", 2), ("sg_window", 0), ("sg_window", 31),
     ("sg_order", 1), ("precision", 7), ("schedule", 9),
+    ("k_base", 5), ("k_total", 100), ("k_total", -1), ("k_total", (1 << 30) + 1),
 ])
 def test_create_rejects_invalid_config(M, field, value):
     cfg = _cfg(M, **{field: value})
@@ -148,3 +151,21 @@ def test_iterate_noalloc_rejects_before_device_work(M, case):
                                       0.0, 0.0, 0.1, dims, args["params"], args["x0"], 0, args["U"], None, None)
     assert st == M.MPPI_E_INVAL
     assert M.mppi_last_error(None) != ""
+
+
+def test_shard_config_rules(M):
+    """A shard must fit its iteration (k_base + K <= k_total), and Algorithm 3 and the
+    batched form are unsharded; all rejected before any device work."""
+    cost = M.make_cost(synth.c1_problem().cost)
+    out = C.c_void_p()
+    cfg = _cfg(M, k_base=200, k_total=400)          # K = 256: 200 + 256 > 400
+    assert M.lib().mppi_create(C.byref(cfg), C.byref(cost), 0, None, C.byref(out)) == M.MPPI_E_INVAL
+    cfg = _cfg(M, k_base=0, k_total=512, weighting=M.MPPI_WEIGHTS_CEM)
+    assert M.lib().mppi_create(C.byref(cfg), C.byref(cost), 0, None, C.byref(out)) == M.MPPI_E_INVAL
+    assert "Algorithm 3" in M.mppi_last_error(None)
+    cfg = _cfg(M, k_base=0, k_total=512)
+    Ks = (C.c_int32 * 1)(256)
+    Ts = (C.c_int32 * 1)(30)
+    assert M.lib().mppi_batch_create(C.byref(cfg), C.byref(cost), 1, Ks, Ts, 0, None, C.byref(out)) \
+        == M.MPPI_E_INVAL
+    assert "unsharded" in M.mppi_last_error(None)

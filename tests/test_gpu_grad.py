@@ -76,10 +76,12 @@ def test_checkpoint_interval_does_not_change_the_gradient(M, orc):
             assert np.abs(gth - ref[1]).max() <= 1e-4 * s
 
 
-def test_gradient_full_size(M, orc):
-    """The differentiation workload: K=4096, T=100, checkpoints every 10 steps."""
-    prob = synth.c5_problem(seed=0)
-    _grad_check(M, orc, prob, synth.C1_X0, synth.random_controls(100, 0, scale=0.2), it=0, ckpt=10)
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_gradient_full_size(M, orc, seed):
+    """The differentiation workload: K=4096, T=100, checkpoints every 10 steps, seeds 0-4
+    (the Philox key, the network and U all follow the seed)."""
+    prob = synth.c5_problem(seed=seed)
+    _grad_check(M, orc, prob, synth.C1_X0, synth.random_controls(100, seed, scale=0.2), it=seed, ckpt=10)
 
 
 def test_autograd_function(M, orc):
