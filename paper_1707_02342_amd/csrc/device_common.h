@@ -125,6 +125,15 @@ __device__ __forceinline__ float tanh_f(float x) {
   return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
+// The scale 2 log2(e) of tanh_f's argument, for kernels that fold it into the weights.
+constexpr float kTanhScale = 2.88539008177792681f;
+
+// tanh x from a = x * kTanhScale (formed by weights already multiplied by the scale).
+__device__ __forceinline__ float tanh_prescaled(float a) {
+  const float e = __builtin_amdgcn_exp2f(a);
+  return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+}
+
 // ---------------------------------------------------------------------------
 // Basis-function dynamics model (appendix; Section VI-B-1)
 // ---------------------------------------------------------------------------

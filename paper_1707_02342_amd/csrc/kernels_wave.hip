@@ -46,15 +46,24 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   static_assert(HID == 32, "the wave schedule maps 32 hidden units onto 32 lanes");
   extern __shared__ float smem[];
+  // Up to 128 steps (NQ = 4) the chain stores the uncompensated state hi_t and each
+  // increment y_t, and phase C forms the compensated sums from them lane-parallel;
+  // beyond (NQ = 8) the chain keeps the compensation itself (less LDS per block).
+  constexpr bool kDefer = NQ <= 4;
+  constexpr int kXW = kDefer ? 8 : 4;                // floats per step in sX
+  constexpr bool kNetV = MODEL == kModelNet;         // the chain reads the clamped controls from sV
   const int T = a.T;
   const int T4 = (T + 4) & ~3;                       // padded row counts (16-byte aligned)
-  float* sU = smem;                                  // [2T]
-  float* sE = sU + ((2 * T + 3) & ~3);               // [8][2T]
-  float* sX = sE + kWaveSlots * ((2 * T + 3) & ~3);  // [8][T4][4]
-  float* red = sX + kWaveSlots * T4 * 4;             // [4][2T]
-  float* scratch = red + 4 * ((2 * T + 3) & ~3);     // [16]
-  float* sB = scratch + 16;                          // basis model: [8][T][8] control terms
   const int eStride = (2 * T + 3) & ~3;
+  float* sU = smem;                                  // [2T]
+  float* sE = sU + eStride;                          // [8][2T] noise
+  float* sV = sE + kWaveSlots * eStride;             // network model: [8][2T] clamped controls g(v)
+  float* sX = sV + (kNetV ? kWaveSlots * eStride : 0);   // [8][T4][kXW]
+  // [4][2T] wave partials of phase D (in the deferred layout they reuse sX, which phase C
+  // has finished reading before the barrier that precedes them)
+  float* red = kDefer ? sX : sX + kWaveSlots * T4 * kXW;
+  float* scratch = kDefer ? sX + kWaveSlots * T4 * kXW : red + 4 * eStride;   // [16]
+  float* sB = scratch + 16;                          // basis model: [8][T][8] control terms
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -68,7 +77,8 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   const bool valid = k < a.K;
   const bool zm = k >= a.K_imp;   // exploration sample: v = eps, delta = eps - u
   float* myE = sE + slot * eStride;
-  float4* myX = reinterpret_cast<float4*>(sX + slot * T4 * 4);
+  float* myV = sV + slot * eStride;
+  float4* myX = reinterpret_cast<float4*>(sX + slot * T4 * kXW);   // [T4] (NQ = 8) or [T4][2] (hi, y)
 
   for (int i = threadIdx.x; i < 2 * T; i += kWaveBlock) sU[i] = a.U[i];
 
@@ -82,10 +92,11 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   const float* W3 = b2 + HID;
   const float* b3 = W3 + 4 * HID;
   const int j = 16 * r + col;
+  // layers 1 and 2 form tanh's argument already multiplied by 2 log2(e)
   float w1[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) w1[i] = kNet ? W1[j * 6 + i] : 0.0f;
-  const float bb1 = kNet ? b1[j] : 0.0f;
+  for (int i = 0; i < 6; ++i) w1[i] = kNet ? kTanhScale * W1[j * 6 + i] : 0.0f;
+  const float bb1 = kNet ? kTanhScale * b1[j] : 0.0f;
   float wP[16], wQ[16];
   int src[16];
   src[0] = col;
@@ -96,15 +107,20 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   src[13] = ror_src<13>(col); src[14] = ror_src<14>(col); src[15] = ror_src<15>(col);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    wP[s] = kNet ? W2[col * HID + 16 * r + src[s]] : 0.0f;
-    wQ[s] = kNet ? W2[(16 + col) * HID + 16 * r + src[s]] : 0.0f;
+    wP[s] = kNet ? kTanhScale * W2[col * HID + 16 * r + src[s]] : 0.0f;
+    wQ[s] = kNet ? kTanhScale * W2[(16 + col) * HID + 16 * r + src[s]] : 0.0f;
   }
-  const float bP = (kNet && r == 0) ? b2[col] : 0.0f;
-  const float bQ = (kNet && r == 1) ? b2[16 + col] : 0.0f;
-  float w3[4];
-#pragma unroll
-  for (int o = 0; o < 4; ++o) w3[o] = kNet ? W3[o * HID + j] : 0.0f;
-  const float b3c = kNet ? b3[comp] : 0.0f;
+  const float bP = (kNet && r == 0) ? kTanhScale * b2[col] : 0.0f;
+  const float bQ = (kNet && r == 1) ? kTanhScale * b2[16 + col] : 0.0f;
+  // layer 3 times dt, as a reduce-scatter over each quad with the weights placed per lane:
+  // lane L keeps output oA = L & 3 (its final one) and oB = oA ^ 2 (passed on in the second
+  // exchange), and sends outputs oA ^ 1 and oA ^ 3 to its partner L ^ 1, whose oA and oB they
+  // are; dt b3 enters once per output, in the lanes 0..3 of each sample
+  const float wKA = kNet ? a.dt * W3[comp * HID + j] : 0.0f;
+  const float wKB = kNet ? a.dt * W3[(comp ^ 2) * HID + j] : 0.0f;
+  const float wSA = kNet ? a.dt * W3[(comp ^ 1) * HID + j] : 0.0f;
+  const float wSB = kNet ? a.dt * W3[(comp ^ 3) * HID + j] : 0.0f;
+  const float bKA = (kNet && c32 < 4) ? a.dt * b3[comp] : 0.0f;
   // basis-function model: this lane's column of Theta with each basis function's
   // normaliser folded in (the chain multiplies raw products such as sin(u_delta) tan(alpha_f))
   constexpr int kRaw = 21;
@@ -118,8 +134,6 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   float kc[kRaw];
 #pragma unroll
   for (int i = 0; i < kRaw; ++i) kc[i] = kNet ? 0.0f : a.params[kRawIdx[i] * 4 + comp] * kRawScale[i];
-  const bool bit0 = (lane & 1) != 0;
-  const bool bit1 = (lane & 2) != 0;
 
   float x0v[kStateDim];
 #pragma unroll
@@ -145,6 +159,12 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
     if (i < NT && t < T) {
       myE[2 * t] = ea[i];
       myE[2 * t + 1] = eb[i];
+      if constexpr (kNetV) {
+        // g(v) of the step (v = u + eps, or eps for an exploration sample), for the chain
+        const float u0 = a.U[2 * t], u1 = a.U[2 * t + 1];
+        myV[2 * t] = fminf(fmaxf(zm ? ea[i] : u0 + ea[i], a.u_lo0), a.u_hi0);
+        myV[2 * t + 1] = fminf(fmaxf(zm ? eb[i] : u1 + eb[i], a.u_lo1), a.u_hi1);
+      }
     }
   }
   if constexpr (MODEL == kModelBasis) {
@@ -175,8 +195,9 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       }
     }
   }
-  Acc xd{x0v[3 + comp], 0.0f};
-  if (c32 < 4) sX[slot * T4 * 4 + c32] = x0v[3 + c32];
+  Acc xd{x0v[3 + comp], 0.0f};       // NQ = 8: compensated in the chain
+  float xh = x0v[3 + comp];           // NQ = 4: the uncompensated state hi_t
+  if (c32 < 4) sX[slot * T4 * kXW + c32] = x0v[3 + c32];
   if (a.ckpt && valid && c32 < kStateDim)
     a.ckpt[(size_t)k * (T / a.ckpt_every + 1) * kCkptStride + c32] = x0v[c32];
   __syncthreads();
@@ -185,6 +206,10 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   {
   float2 u = *reinterpret_cast<const float2*>(sU);
   float2 e = *reinterpret_cast<const float2*>(myE);
+  float2 vc = make_float2(0.0f, 0.0f);
+  if constexpr (kNetV) vc = *reinterpret_cast<const float2*>(myV);
+  // the lane's store slot in sX: hi_{t+1} (lanes with bit 2 clear) or y_t (bit 2 set)
+  const int xs_off = slot * T4 * kXW + ((lane & 4) ? 4 + comp : kXW + comp);
   // basis model: this step's control terms, also read one step ahead
   const float* myB = sB + slot * T * 8;
   float4 bq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -196,18 +221,22 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   for (int t = 0; t < T; ++t) {
     // next step's control and noise are read one step ahead (LDS latency off the chain)
     const int tn = min(t + 1, T - 1);
-    const float2 u_next = *reinterpret_cast<const float2*>(sU + 2 * tn);
-    const float2 e_next = *reinterpret_cast<const float2*>(myE + 2 * tn);
-    const float vc0 = fminf(fmaxf(zm ? e.x : u.x + e.x, a.u_lo0), a.u_hi0);
-    const float vc1 = fminf(fmaxf(zm ? e.y : u.y + e.y, a.u_lo1), a.u_hi1);
-    float f;
+    float2 u_next = u, e_next = e, vc_next = vc;
+    if constexpr (kNetV) {
+      vc_next = *reinterpret_cast<const float2*>(myV + 2 * tn);
+    } else {
+      u_next = *reinterpret_cast<const float2*>(sU + 2 * tn);
+      e_next = *reinterpret_cast<const float2*>(myE + 2 * tn);
+    }
+    const float vc0 = vc.x, vc1 = vc.y;
+    float y;   // dt * f of the lane's component
+    const float xcur = kDefer ? xh : xd.hi;
     if constexpr (MODEL == kModelBasis) {
       // bq = {sin u_delta, -tan u_delta, u_delta, 0}, cq = the control-only terms
       const float4 bq_next = *reinterpret_cast<const float4*>(myB + 8 * tn);
       const float cq_next = myB[8 * tn + 4 + comp];
-      const float xh = xd.hi;
-      const float roll = dpp_f<0x00>(xh), vx = dpp_f<0x55>(xh);   // quad_perm:[i,i,i,i]
-      const float vy = dpp_f<0xAA>(xh), om = dpp_f<0xFF>(xh);
+      const float roll = dpp_f<0x00>(xcur), vx = dpp_f<0x55>(xcur);   // quad_perm:[i,i,i,i]
+      const float vy = dpp_f<0xAA>(xcur), om = dpp_f<0xFF>(xcur);
       // tyre tangents: tan(arctan z) = z above v_x = 0.1, the steering alone below
       const bool mv = vx > 0.1f;
       const float rv = __builtin_amdgcn_rcpf(vx);
@@ -228,14 +257,13 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
         if (i + 2 < kRaw) p2 = __builtin_fmaf(kc[i + 2], raw[i + 2], p2);
         if (i + 3 < kRaw) p3 = __builtin_fmaf(kc[i + 3], raw[i + 3], p3);
       }
-      f = (p0 + p1) + (p2 + p3);
+      y = a.dt * ((p0 + p1) + (p2 + p3));
       bq = bq_next;
       cq = cq_next;
     } else {
       // layer 1
       float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
       acc1 = __builtin_fmaf(w1[5], vc1, acc1);
-      const float xh = xd.hi;
       // one asm block, so that no wait states are inserted between the four
       asm volatile(
           "s_nop 1\n\t"
@@ -243,8 +271,8 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
           "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1] row_mask:0xf bank_mask:0xf\n\t"
           "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2] row_mask:0xf bank_mask:0xf\n\t"
           "v_fmac_f32_dpp %0, %1, %5 quad_perm:[3,3,3,3] row_mask:0xf bank_mask:0xf"
-          : "+v"(acc1) : "v"(xh), "v"(w1[0]), "v"(w1[1]), "v"(w1[2]), "v"(w1[3]));
-      const float h1 = tanh_f(acc1);
+          : "+v"(acc1) : "v"(xcur), "v"(w1[0]), "v"(w1[1]), "v"(w1[2]), "v"(w1[3]));
+      const float h1 = tanh_prescaled(acc1);
       // layer 2: four interleaved chains (P, Q for even and odd rotations) so that no
       // accumulator is read by the instruction right after the one that wrote it
       float P = __builtin_fmaf(wP[0], h1, bP);
@@ -288,25 +316,28 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       P = P + P2;
       Q = Q + Q2;
       swap_rows(P, Q);                    // row 0: (P0, P1) -> out c;  row 1: (Q0, Q1) -> out 16+c
-      const float h2 = tanh_f(P + Q);
-      // layer 3: reduce-scatter of the four outputs over the row
-      const float a0 = w3[0] * h2, a1 = w3[1] * h2, a2 = w3[2] * h2, a3 = w3[3] * h2;
-      const float send0 = bit0 ? a0 : a1, keep0 = bit0 ? a1 : a0;
-      const float send1 = bit0 ? a2 : a3, keep1 = bit0 ? a3 : a2;
-      const float g0 = keep0 + dpp_f<kQuadXor1>(send0);        // output bit0
-      const float g1 = keep1 + dpp_f<kQuadXor1>(send1);        // output 2 + bit0
-      const float send2 = bit1 ? g0 : g1, keep2 = bit1 ? g1 : g0;
-      f = keep2 + dpp_f<kQuadXor2>(send2);                     // output lane & 3
-      f = f + dpp_f<kRowRor + 8>(f);
-      f = f + dpp_f<kRowRor + 4>(f);
-      f = add_rows(f) + b3c;
+      const float h2 = tanh_prescaled(P + Q);
+      // layer 3 (times dt): reduce-scatter of the four outputs over each quad, then the
+      // quads of the row and the two rows
+      const float A = __builtin_fmaf(wKA, h2, bKA) + dpp_f<kQuadXor1>(wSA * h2);   // output oA, lanes L, L^1
+      const float B = wKB * h2 + dpp_f<kQuadXor1>(wSB * h2);                         // output oB, lanes L, L^1
+      float g = A + dpp_f<kQuadXor2>(B);                                             // output oA, the quad
+      g = g + dpp_f<kRowRor + 8>(g);
+      g = g + dpp_f<kRowRor + 4>(g);
+      y = add_rows(g);
     }
-    xd.add(a.dt * f);
-    // every lane of a component holds the same bits (f and the update are formed alike
+    // every lane of a component holds the same bits (y and the update are formed alike
     // in all of them), so all lanes store: no branch in the step loop
-    sX[slot * T4 * 4 + (t + 1) * 4 + comp] = xd.value();
+    if constexpr (kDefer) {
+      xh = xh + y;
+      sX[xs_off + t * kXW] = (lane & 4) ? y : xh;   // y_t at entry t, hi_{t+1} at entry t + 1
+    } else {
+      xd.add(y);
+      sX[slot * T4 * kXW + (t + 1) * kXW + comp] = xd.value();
+    }
     u = u_next;
     e = e_next;
+    vc = vc_next;
   }
   }
   __syncthreads();
@@ -319,13 +350,57 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   // is issued before the first is used (one memory round trip), then the costs.
   const int npl = NT;
   const int tb = c32 * npl;
+  // x_d at the lane's steps, xv[q] = x_d(tb + q) for q = 0..NQ (the state before step
+  // tb + q and after step tb + q - 1).  Deferred layout: x_d(t) = hi_t + lo_t, where lo_t
+  // sums the rounding errors err_s = (hi_s + y_s) - fl(hi_s + y_s), s < t (error-free
+  // two-sum), in the lane and then by a scan across the lanes; the chain's own sums
+  // hi_{s+1} = fl(hi_s + y_s) are recomputed here.
+  float4 xv[NQ + 1];
+  if constexpr (kDefer) {
+    float4 hv[NQ], yv[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int t = tb + q;
+      const bool live = q < npl && t < T;
+      hv[q] = live ? myX[2 * t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      yv[q] = live ? myX[2 * t + 1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    float hs[NQ][4], lq[NQ][4];
+    float lsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const float hq[4] = {hv[q].x, hv[q].y, hv[q].z, hv[q].w};
+      const float yq[4] = {yv[q].x, yv[q].y, yv[q].z, yv[q].w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float e_;
+        two_sum(hq[c], yq[c], hs[q][c], e_);
+        lsum[c] = lsum[c] + e_;
+        lq[q][c] = lsum[c];
+      }
+    }
+    float pre[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pre[c] = scan32_excl(lsum[c], c32);
+    xv[0] = make_float4(hv[0].x + pre[0], hv[0].y + pre[1], hv[0].z + pre[2], hv[0].w + pre[3]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      xv[q + 1] = make_float4(hs[q][0] + (pre[0] + lq[q][0]), hs[q][1] + (pre[1] + lq[q][1]),
+                              hs[q][2] + (pre[2] + lq[q][2]), hs[q][3] + (pre[3] + lq[q][3]));
+  }
+  auto xpre = [&](int q) -> float4 {   // x_d before step tb + q
+    if constexpr (kDefer) return xv[q]; else return myX[tb + q];
+  };
+  auto xpost = [&](int q) -> float4 {  // x_d after step tb + q
+    if constexpr (kDefer) return xv[q + 1]; else return myX[tb + q + 1];
+  };
   float th_h = 0.0f, th_l = 0.0f;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = tb + q;
     if (q < npl && t < T) {
       float s_, e_;
-      two_sum(th_h, a.dt * myX[t].w, s_, e_);
+      two_sum(th_h, a.dt * xpre(q).w, s_, e_);
       th_h = s_;
       th_l += e_;
     }
@@ -348,7 +423,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       dpy[q] = 0.0f;
       const int t = tb + q;
       if (q < npl && t < T) {
-        const float4 xs = myX[t];
+        const float4 xs = xpre(q);
         float sn, cs;
         sincosf(th + thl, &sn, &cs);
         dpx[q] = a.dt * (cs * xs.y - sn * xs.z);
@@ -392,7 +467,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
         two_sum(py_h, dpy[q], s_, e_);
         py_h = s_;
         py_l += e_;
-        two_sum(th, a.dt * myX[t].w, s_, e_);
+        two_sum(th, a.dt * xpre(q).w, s_, e_);
         th = s_;
         thl += e_;
       }
@@ -419,7 +494,7 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
   for (int q = 0; q < NQ; ++q) {
     const int t = tb + q;
     if (q < npl && t < T) {
-      const float4 xn = myX[t + 1];
+      const float4 xn = xpost(q);
       const float px1 = pxh[q] + pxl[q], py1 = pyh[q] + pyl[q];
       if (a.ckpt && ((t + 1) % a.ckpt_every) == 0 && valid) {
         float* cp = a.ckpt + ((size_t)k * (T / a.ckpt_every + 1) + (t + 1) / a.ckpt_every) * kCkptStride;
@@ -490,11 +565,17 @@ template __global__ void rollout_wave_kernel<32, 4, kModelBasis>(RolloutArgs);
 template __global__ void rollout_wave_kernel<32, 8, kModelBasis>(RolloutArgs);
 
 // Dynamic LDS bytes the wave kernel needs for horizon T.
+// (The layout of the kernel's LDS: the deferred-compensation layout up to T = 128,
+// where launch_wave picks NQ = 4.)
 size_t wave_smem_bytes(int T, int model) {
   const size_t e = (size_t)((2 * T + 3) & ~3);
   const size_t T4 = (size_t)((T + 4) & ~3);
+  const bool defer = T <= 128;
+  const size_t v = model == kModelNet ? (size_t)kWaveSlots * e : 0;
+  const size_t x = (size_t)kWaveSlots * T4 * (defer ? 8 : 4);
+  const size_t red = defer ? 0 : 4 * e;
   const size_t basis = model == kModelBasis ? (size_t)kWaveSlots * T * 8 : 0;
-  return sizeof(float) * (e + kWaveSlots * e + kWaveSlots * T4 * 4 + 4 * e + 16 + basis);
+  return sizeof(float) * (e + kWaveSlots * e + v + x + red + 16 + basis);
 }
 
 }  // namespace mppi

@@ -98,6 +98,22 @@ __device__ __forceinline__ void scan32_excl2(float& hi, float& lo, int c32) {
   scan_step2<kRowBcast15, 0xA>(hi, lo);
 }
 
+// Exclusive scan of v over the 32 lanes of a half-wave (lane 0 of each half gets 0), in
+// DPP moves: shift up one lane, scan within each 16-lane row, add the first row's total
+// to the second row.
+__device__ __forceinline__ float scan32_excl(float v, int c32) {
+  const bool col0 = (c32 & 15) == 0;
+  const float sh = dpp_upd<kRowShr + 1>(0.0f, v);
+  const float bh = dpp_upd<kRowBcast15, 0xA>(0.0f, v);
+  v = col0 ? bh : sh;
+  v = v + dpp_upd<kRowShr + 1, 0xF>(0.0f, v);
+  v = v + dpp_upd<kRowShr + 2, 0xF>(0.0f, v);
+  v = v + dpp_upd<kRowShr + 4, 0xF>(0.0f, v);
+  v = v + dpp_upd<kRowShr + 8, 0xF>(0.0f, v);
+  v = v + dpp_upd<kRowBcast15, 0xA>(0.0f, v);
+  return v;
+}
+
 // Compensated sum of (hi, lo) over the 32 lanes, the same bits in every lane (the
 // error-free two-sum is symmetric in its operands): butterflies within each row, then
 // the two rows.
