@@ -6,16 +6,18 @@ a 2048 x 2048 elliptical track cost map at 0.05 m/cell, speed/slip/crash costs,
 lambda = 6.7, Savitzky-Golay window 9; 100 warm-started iterations per Philox seed
 0..9 on a synthetic plant (the same network, noise-free).  One step = one control
 step: an MPPI iteration (noise, rollouts, weights, weighted perturbation sum,
-smoothing, update), the shift of U and the plant step, fused in one kernel launch
-and driven through the C ABI (mppi_step_device on a device-resident plant state); all
-inputs are resident in HBM before timing, and the timed region allocates nothing and
-copies nothing to the host.
+smoothing, update), the shift of U and the plant step.  The timed region drives each
+seed's 100-step block through the C ABI as one mppi_run_receding_device call on a
+device-resident plant state (one multi-step launch on this workload); all inputs are
+resident in HBM before timing, and the timed region allocates nothing and copies
+nothing to the host.
 
-Prints one JSON line with the throughput, launch and host latencies (eager and
-HIP-graph-replayed), the launch's roofline figures (algorithmic FLOP of the dynamics
-network over the launch's average duration, measured with HIP events on the
-library's stream), the precision / batched / differentiation forms, and the CPU
-oracle's throughput on a bounded sample of the same workload.
+Prints one JSON line with the throughput, the device time per step inside the
+launches, the single-step launch figures (mppi_step_device: back to back and per
+launch), host latencies (eager and HIP-graph-replayed), the roofline figures
+(algorithmic FLOP of the dynamics network over the device time per step, measured with
+HIP events on the library's stream), the precision / batched / differentiation forms,
+and the CPU oracle's throughput on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -37,7 +39,7 @@ VALU_LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one FP32 op pe
 TRAFFIC_FILE = ROOT / "profiles" / "rollout_wave_k1920_t100_traffic.json"
 # the sources the benchmarked kernel (rollout_wave_kernel<32, 4, 0>) is built from: stored
 # counter readings are used only while these files are unchanged
-KERNEL_SOURCES = ["kernels_wave.hip", "wave_common.hip.h", "kernels_common.hip.h", "device_common.h",
+KERNEL_SOURCES = ["kernels_wave_split.hip", "kernels_wave.hip", "wave_common.hip.h", "kernels_common.hip.h", "device_common.h",
                   "mppi_types.h"]
 NET_FLOP_PER_STEP = {32: 2 * (6 * 32 + 32 * 32 + 32 * 4), 64: 2 * (6 * 64 + 64 * 64 + 64 * 4)}
 # basis-function model: Theta^T phi (25 x 4 multiply-adds) plus about 40 operations forming phi
@@ -440,15 +442,20 @@ def main():
             xd.copy_(x0_t)
         torch.cuda.synchronize()
 
-    def receding(n_steps):
+    def receding(n_steps, single=False):
         """n_steps control steps: blocks of up to 100 warm-started steps, one Philox seed
-        per block in turn, all enqueued back to back."""
+        per block in turn, all enqueued back to back.  A block is one
+        mppi_run_receding_device call (one multi-step launch on this workload), or with
+        single=True one mppi_step_device launch per step."""
         done, blk = 0, 0
         while done < n_steps:
             n = min(100, n_steps - done)
             ctx, ptr = ctls[blk % 10].ctx, xdev[blk % 10].data_ptr()
-            for _ in range(n):
-                M.mppi_step_device(ctx, ptr)
+            if single:
+                for _ in range(n):
+                    M.mppi_step_device(ctx, ptr)
+            else:
+                M.mppi_run_receding_device(ctx, ptr, n)
             done += n
             blk += 1
 
@@ -457,13 +464,31 @@ def main():
     # pass is not the throughput one).  These passes run before the timed region, so that
     # it starts on a device already at its steady clocks and caches.
     reset_all()
+    n_timed = max(args.steps, 500)
+    receding(n_timed)                                # untimed: every controller's first launches
+    torch.cuda.synchronize()
+    reset_all()
     for c in ctls:
         M.mppi_set_timing(c.ctx, True)
-    receding(max(args.steps, 500))
+    receding(n_timed)
+    blocks = np.concatenate([M.mppi_get_timing_samples(c.ctx) for c in ctls])
+    for c in ctls:
+        M.mppi_set_timing(c.ctx, False)
+    t_roll = float(blocks.sum()) / n_timed          # device ms per control step inside the launches
+    # one launch per step (mppi_step_device), for the per-launch latency figures
+    reset_all()
+    for c in ctls:
+        M.mppi_set_timing(c.ctx, True)
+    receding(n_timed, single=True)
     samples = np.concatenate([M.mppi_get_timing_samples(c.ctx) for c in ctls])
     for c in ctls:
         M.mppi_set_timing(c.ctx, False)
-    t_roll, n_roll = float(samples.sum()), len(samples)
+    torch.cuda.synchronize()
+    reset_all()
+    t0s = time.perf_counter()
+    receding(n_timed, single=True)
+    torch.cuda.synchronize()
+    single_step_us = (time.perf_counter() - t0s) * 1e6 / n_timed
 
     # host-observed latency of a control step, state in -> u_0 on the host: eager
     # (mppi_iterate + mppi_shift) and as a replayed HIP graph of mppi_step_device
@@ -497,17 +522,17 @@ def main():
         del g
     lat_eager, lat_graph = np.array(lat_eager), np.array(lat_graph)
 
-    # warm-up: `warmup` untimed control steps, spread over the controllers in turn, then
-    # all restart from x0, U = 0, iteration 0
+    # warm-up: `warmup` untimed control steps (one multi-step call), then all restart
+    # from x0, U = 0, iteration 0
     reset_all()
-    for i in range(args.warmup):
-        M.mppi_step_device(ctls[i % len(ctls)].ctx, xdev[i % len(ctls)].data_ptr())
+    if args.warmup:
+        M.mppi_run_receding_device(ctls[0].ctx, xdev[0].data_ptr(), args.warmup)
     torch.cuda.synchronize()
     reset_all()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     # timed region: `steps` receding-horizon control steps (iteration, shift and plant
-    # step fused in one launch each), no per-launch events, no allocation, no host copy
+    # step), no per-launch events, no allocation, no host copy
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
@@ -519,7 +544,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = K * T * args.steps / wall
 
-    roll_ms = t_roll / max(n_roll, 1)
+    roll_ms = t_roll
     flop = NET_FLOP_PER_STEP[prob.hidden] * K * T
     achieved = flop / (roll_ms * 1e-3) / 1e12
     traffic = stored_traffic() if schedule == M.MPPI_SCHED_WAVE else None
@@ -539,12 +564,15 @@ def main():
         "config": {"workload": "paper-shaped receding-horizon MPPI: K=1920, T=100, 6-32-32-4 tanh network, "
                                "2048x2048 elliptical track map, SGF window 9, 100 warm-started iterations "
                                "per Philox seed 0-9 on a synthetic plant; one step = iteration + shift + "
-                               "plant step (one launch)",
-                   "K": K, "T": T, "hidden": prob.hidden, "schedule": schedule},
+                               "plant step",
+                   "K": K, "T": T, "hidden": prob.hidden, "schedule": schedule,
+                   "launch": "mppi_run_receding_device, one launch per 100-step block"},
         "latency_us": {"step_device_back_to_back": dev_ms * 1e3 / args.steps,
-                       "launch_mean": roll_ms * 1e3,
-                       "launch_p50": float(np.percentile(samples, 50)) * 1e3,
-                       "launch_p99": float(np.percentile(samples, 99)) * 1e3,
+                       "kernel_per_step": roll_ms * 1e3,
+                       "single_step_launches_back_to_back": single_step_us,
+                       "single_step_launch_mean": float(np.mean(samples)) * 1e3,
+                       "single_step_launch_p50": float(np.percentile(samples, 50)) * 1e3,
+                       "single_step_launch_p99": float(np.percentile(samples, 99)) * 1e3,
                        "host_eager_p50": float(np.percentile(lat_eager, 50)),
                        "host_eager_p99": float(np.percentile(lat_eager, 99)),
                        "host_graph_p50": float(np.percentile(lat_graph, 50)),

@@ -199,9 +199,9 @@ mppi_status mppi_shift(mppi_ctx* ctx, float u0_out[2]);
 mppi_status mppi_plant_step(mppi_ctx* ctx, const float x[7], const float u[2], float x_out[7]);
 
 /* n_iter receding-horizon steps entirely on the device: iterate from x, shift,
- * then x <- F(x, g(u_0)) (Algorithm 1 on a synthetic plant), one kernel launch per
- * step (the last block of each launch applies the update, the shift and the plant
- * step).  u_hist ([n_iter][2]) and x_hist ([n_iter+1][7], x_hist[0] = x0) may be NULL.
+ * then x <- F(x, g(u_0)) (Algorithm 1 on a synthetic plant), launched as
+ * mppi_run_receding_device launches them (one multi-step launch where the split wave
+ * form applies, else one launch per step).  u_hist ([n_iter][2]) and x_hist ([n_iter+1][7], x_hist[0] = x0) may be NULL.
  * The results equal the host-driven loop mppi_iterate / mppi_shift / mppi_plant_step
  * bit for bit.  Synchronises at the end only. */
 mppi_status mppi_run_receding(mppi_ctx* ctx, const float x0[7], int32_t n_iter,
@@ -216,6 +216,21 @@ mppi_status mppi_run_receding(mppi_ctx* ctx, const float x0[7], int32_t n_iter,
  * valid until the launch has run.  The iteration's status is read by the next
  * synchronising call (mppi_get_controls, mppi_shift). */
 mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
+
+/* n_iter receding-horizon control steps on device data (Algorithm 1 with its last block
+ * on a synthetic plant): each step iterates from the state in x_dev (device, [7],
+ * updated in place by the noise-free plant step), shifts U, writes u_0 to u_hist_dev[2i..]
+ * and the new state to x_hist_dev[7i..] (device, [n_iter][2] and [n_iter][7], either may
+ * be NULL).  Enqueued, no synchronisation, no allocation.  With the wave schedule's split
+ * form (T <= 128, at most one block of 8 samples per compute unit) and Algorithm 2's
+ * weights, all n_iter steps run in ONE cooperative launch whose blocks keep the network in
+ * registers and wait for each step's update on the device; otherwise one launch per
+ * step.  Either way the results equal n_iter calls of mppi_step_device bit for bit.  The
+ * status of the last step (or MPPI_E_DEVICE if a block of the multi-step launch gave up
+ * waiting for a step) is read by the next synchronising call.  INVAL: x_dev NULL or
+ * n_iter outside [0, 1<<20]. */
+mppi_status mppi_run_receding_device(mppi_ctx* ctx, float* x_dev, int32_t n_iter, float* u_hist_dev,
+                                     float* x_hist_dev);
 
 /* K-shard form, step 1 (Algorithm 2 over samples spread across shards): one iteration of
  * this context's K samples from x0[7] (host) that ends, in place of the update, with the

@@ -18,7 +18,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libmppi.so"
 
-SOURCES = ["mppi_runtime.hip", "kernels_lane.hip", "kernels_wave.hip", "kernels_wide.hip", "kernels_quad.hip",
+SOURCES = ["mppi_runtime.hip", "kernels_lane.hip", "kernels_wave.hip", "kernels_wave_split.hip", "kernels_wide.hip", "kernels_quad.hip",
            "kernels_adjoint.hip", "kernels_update.hip", "kernels_cem.hip"]
 
 HIPFLAGS = [

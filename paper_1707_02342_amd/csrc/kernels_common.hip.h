@@ -237,8 +237,10 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
     if (o < T2) lds[o] = u_new[j];
   }
   __syncthreads();
-  for (int o = tid; o < T2; o += NT) a.Uout[o] = (o + 2 < T2) ? lds[o + 2] : 0.0f;
-  if (tid < 2 && a.u0_out) a.u0_out[tid] = lds[tid];
+  // U, u_0 and the plant state are written through to the device's point of coherence:
+  // in a multi-step launch the next step's blocks read them right after the step's signal
+  for (int o = tid; o < T2; o += NT) store_through(a.Uout + o, (o + 2 < T2) ? lds[o + 2] : 0.0f);
+  if (tid < 2 && a.u0_out) store_through(a.u0_out + tid, lds[tid]);
   float x[kStateDim];
 #pragma unroll
   for (int i = 0; i < kStateDim; ++i) x[i] = s_x[i];
@@ -298,8 +300,8 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
     float* xs = const_cast<float*>(a.x0_dev);
 #pragma unroll
     for (int i = 0; i < kStateDim; ++i) {
-      xs[i] = y[i];
-      if (a.x_copy) a.x_copy[i] = y[i];
+      store_through(xs + i, y[i]);
+      if (a.x_copy) store_through(a.x_copy + i, y[i]);
     }
   }
 }
@@ -325,12 +327,12 @@ struct FinalStage {
     if constexpr (RECEDE) {
       // one component per thread: vector loads, which unlike a uniform (scalar) load do
       // not hold up the LDS waits of the merge that follows
-      x_old = (a.recede && tid < kStateDim) ? a.x0_dev[tid] : 0.0f;
+      x_old = (a.recede && tid < kStateDim) ? load_through(a.x0_dev + tid) : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < kOut; ++j) {
       const int o = tid + j * NT;
-      u_old[j] = (o < T2) ? a.Uout[o] : 0.0f;
+      u_old[j] = (o < T2) ? load_through(a.Uout + o) : 0.0f;
 #pragma unroll
       for (int i = 0; i < kTapReg; ++i)
         taps[j][i] = (o < T2 && w > 1 && w <= kTapReg && i < w) ? a.sg[(size_t)(o >> 1) * w + i] : 0.0f;
@@ -373,7 +375,7 @@ struct FinalStage {
           }
         }
         u_new[j] = u_old[j] + upd;
-        if (!a.recede) a.Uout[o] = u_new[j];
+        if (!a.recede) store_through(a.Uout + o, u_new[j]);
       }
     }
     if (tid == 0) {
@@ -410,10 +412,12 @@ struct FinalStage {
 // Algorithm 2's normalisation, the Savitzky-Golay smoothing and the update
 // U <- U + SG * Delta.  With a single group the second level is skipped (merging one
 // row with scale exp(0) = 1 would return it unchanged).  Every decision is uniform
-// over the block, so all barriers are reached by all threads.
+// over the block, so all barriers are reached by all threads.  Returns, in every
+// thread, whether this block ran the final stage.
 template <int NT, int MODEL = kModelNet, bool RECEDE = true, int HC = 0>
-__device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
+__device__ bool finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
                                  const float* N_lds /* [2T] */, float* lds /* >= 2T floats */) {
+  bool ran_final = false;
   __shared__ unsigned s_flag;
   __shared__ float s_small[2 * kMergeChunk];
   const int tid = threadIdx.x;
@@ -436,17 +440,18 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
     if (final_merge) fs.prefetch(a);
     merge_rows<NT>(a.part + (size_t)grp * gsz * stride, n_in, stride, T2, a.inv_lambda, lds, s_small,
                    rho, eta);
-    if (tid == 0) a.cnt[grp] = 0u;
+    if (tid == 0) __hip_atomic_store(a.cnt + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ngrp > 1) {
       __syncthreads();
       final_merge = publish_and_count<NT>(a.part2 + (size_t)grp * stride, rho, eta, lds, T2, a.cnt + ngrp,
                                           (unsigned)ngrp, &s_flag, [&] { fs.prefetch(a); });
       if (final_merge) {
         merge_rows<NT>(a.part2, ngrp, stride, T2, a.inv_lambda, lds, s_small, rho, eta);
-        if (tid == 0) a.cnt[ngrp] = 0u;
+        if (tid == 0) __hip_atomic_store(a.cnt + ngrp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     if (final_merge) {
+      ran_final = true;
       if (a.row_out) {
         fs.export_row(a, lds, rho, eta);
       } else {
@@ -456,6 +461,7 @@ __device__ void finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
     }
   }
   __syncthreads();
+  return ran_final;
 }
 
 }  // namespace mppi

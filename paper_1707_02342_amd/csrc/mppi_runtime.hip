@@ -23,6 +23,10 @@ namespace mppi {
 hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
 template <int HID, int NQ, int MODEL> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T, int model);
+template <int MODEL> __global__ void rollout_wave_split_kernel(RolloutArgs);
+size_t wave_split_smem_bytes(int T, int model);
+constexpr int kWaveSplitBlockThreads = 512;   // 4 chain waves + 4 cost waves
+constexpr int kWaveSplitMaxT = 128;
 size_t wide_smem_bytes(int T);
 template <int NQ> __global__ void rollout_wide_kernel(RolloutArgs);
 template <int PREC, int HID> __global__ void rollout_quad_kernel(RolloutArgs);
@@ -101,6 +105,8 @@ struct mppi_ctx {
   float* d_gout = nullptr;    // reduced gradient [1412 + 2T]
   float* d_gred = nullptr;    // chunk sums of the gradient partials [16][1412 + 2T]
   unsigned* d_iter = nullptr; // the iteration counter (Philox counter word 3), advanced on the device
+  unsigned* d_step = nullptr; // step signal of multi-step receding launches (monotonic)
+  unsigned step_count = 0;    // its value after the launches enqueued so far
   int ckpt_cap = 0;           // n_ckpt the checkpoint buffer holds
   bool objective_ready = false;
   int obj_ckpt_every = 0;
@@ -295,9 +301,34 @@ int blocks_for_k(int K, int sched) {
 
 int blocks_for(const mppi_ctx* c, int sched) { return blocks_for_k(c->cfg.K, sched); }
 
-// The wave kernel keeps each lane's share of the steps (ceil(T/32) of them) in
-// registers; it is compiled for up to 4 (T <= 128) and up to 8 (T <= 256).
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+// The wave schedule.  While the launch fits the device in one block per compute unit
+// (the latency-bound regime) and T <= 128, the split kernel runs each block's kinematics
+// and cost in a second set of waves one chunk behind the chain; otherwise the wave
+// kernel, which keeps each lane's share of the steps (ceil(T/32) of them) in registers
+// and is compiled for up to 4 (T <= 128) and up to 8 (T <= 256).
 void launch_wave(int G, int T, hipStream_t stream, const RolloutArgs& a) {
+  if (T <= kWaveSplitMaxT && G <= device_cus()) {
+    const size_t smem = wave_split_smem_bytes(T, a.model);
+    if (a.model == kModelBasis)
+      hipLaunchKernelGGL((rollout_wave_split_kernel<kModelBasis>), dim3(G), dim3(kWaveSplitBlockThreads), smem,
+                         stream, a);
+    else
+      hipLaunchKernelGGL((rollout_wave_split_kernel<kModelNet>), dim3(G), dim3(kWaveSplitBlockThreads), smem,
+                         stream, a);
+    return;
+  }
   const size_t smem = wave_smem_bytes(T, a.model);
   if (a.model == kModelBasis) {
     if (T <= 128)
@@ -367,6 +398,9 @@ RolloutArgs config_args(const mppi_config& g, const mppi_cost& cost, int H, int 
   a.nk.sig1 = std::sqrt(g.sigma2[1]);
   a.nk.k_base = g.k_base;
   a.row_out = nullptr;
+  a.n_steps = 1;
+  a.step_flag = nullptr;
+  a.step_base = 0;
   a.hidden = hidden;
   a.model = model;
   a.recede = 0;
@@ -496,11 +530,74 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
   return MPPI_OK;
 }
 
+// Whether n receding steps can run as one multi-step launch of the split wave kernel:
+// the wave schedule's split form (T <= 128, one block per compute unit), Algorithm 2's
+// weights, and a device that launches cooperatively (every block resident at once).
+bool multi_step_ok(const mppi_ctx* c) {
+  if (c->schedule != MPPI_SCHED_WAVE || c->cfg.weighting != MPPI_WEIGHTS_IT || c->cfg.T > kWaveSplitMaxT) return false;
+  if (blocks_for(c, MPPI_SCHED_WAVE) > device_cus()) return false;
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess) return false;
+  return coop != 0;
+}
+
+// n receding-horizon steps on the state in x_dev (device, updated in place): u_0 of step i
+// to u_hist[2i..] and the state after step i to x_hist[7i..] (device, nullable).  One
+// cooperative launch when multi_step_ok, else one launch per step; the results are the
+// same bit for bit.
+mppi_status enqueue_receding_steps(mppi_ctx* c, float* x_dev, int n, float* u_hist, float* x_hist) {
+  if (!c->have_map || !c->have_dyn)
+    return fail(c, MPPI_E_STATE, "set the cost map and the dynamics before iterating");
+  if (n <= 0) return MPPI_OK;
+  if (n == 1 || !multi_step_ok(c)) {
+    for (int i = 0; i < n; ++i) {
+      mppi_status st = enqueue_iteration(c, nullptr, x_dev, true, u_hist ? u_hist + 2 * i : nullptr,
+                                         x_hist ? x_hist + kStateDim * i : nullptr);
+      if (st != MPPI_OK) return st;
+    }
+    return MPPI_OK;
+  }
+  const int G = blocks_for(c, MPPI_SCHED_WAVE);
+  if (G > c->part_cap) return fail(c, MPPI_E_INVAL, "internal: %d partial blocks > capacity %d", G, c->part_cap);
+  c->objective_ready = false;
+  RolloutArgs a = rollout_args(c, nullptr, x_dev);
+  a.G = G;
+  a.recede = 1;
+  a.u0_out = u_hist;
+  a.x_copy = x_hist;
+  a.n_steps = n;
+  a.step_flag = c->d_step;
+  a.step_base = c->step_count;
+  PendingTiming pt{};
+  if (c->timing) {
+    pt.e0 = take_event(c);
+    pt.e1 = take_event(c);
+    if (!pt.e0 || !pt.e1) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
+    HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
+  }
+  void* args[] = {&a};
+  const void* fn = c->model == kModelBasis ? reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelBasis>)
+                                           : reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelNet>);
+  HIP_TRY(c, hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWaveSplitBlockThreads), args,
+                                        (unsigned)wave_split_smem_bytes(c->cfg.T, c->model), c->stream));
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
+    c->pending.push_back(pt);
+  }
+  c->step_count += (unsigned)(n - 1);   // the launch signals steps 1 .. n-1
+  c->iter += (uint32_t)n;
+  return MPPI_OK;
+}
+
+constexpr int kStatusTimeoutHost = 6;   // the split kernel's status when a step signal never came
+
 mppi_status read_status(mppi_ctx* c) {
   int st = 0;
   HIP_TRY(c, hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (st == MPPI_E_NONFINITE) return fail(c, MPPI_E_NONFINITE, "no sample had a finite cost; U unchanged");
+  if (st == kStatusTimeoutHost)
+    return fail(c, MPPI_E_DEVICE, "a multi-step receding launch gave up waiting for a step signal");
   return MPPI_OK;
 }
 
@@ -562,6 +659,8 @@ void free_all(mppi_ctx* c) {
   c->d_cnt = nullptr;
   if (c->d_iter) (void)hipFree(c->d_iter);
   c->d_iter = nullptr;
+  if (c->d_step) (void)hipFree(c->d_step);
+  c->d_step = nullptr;
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
@@ -624,6 +723,8 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_iter, sizeof(unsigned)));
     HIP_TRY(c, hipMemsetAsync(c->d_iter, 0, sizeof(unsigned), c->stream));
+    HIP_TRY(c, hipMalloc(&c->d_step, sizeof(unsigned)));
+    HIP_TRY(c, hipMemsetAsync(c->d_step, 0, sizeof(unsigned), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_x, sizeof(float) * kStateDim));
     HIP_TRY(c, hipMalloc(&c->d_u0, sizeof(float) * 2));
     std::vector<float> decay(T + 1);
@@ -858,10 +959,8 @@ mppi_status mppi_run_receding(mppi_ctx* c, const float x0[7], int32_t n_iter, fl
     HIP_TRY(c, hipMemcpyAsync(c->d_x, x0, 7 * sizeof(float), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_hist_x, x0, 7 * sizeof(float), hipMemcpyHostToDevice, c->stream));
     int nonfinite = 0;
-    for (int i = 0; i < n_iter; ++i) {
-      mppi_status st = enqueue_iteration(c, nullptr, c->d_x, true, c->d_hist_u + 2 * i, c->d_hist_x + 7 * (i + 1));
-      if (st != MPPI_OK) return st;
-    }
+    mppi_status st = enqueue_receding_steps(c, c->d_x, n_iter, c->d_hist_u, c->d_hist_x + 7);
+    if (st != MPPI_OK) return st;
     if (u_hist && n_iter > 0)
       HIP_TRY(c, hipMemcpyAsync(u_hist, c->d_hist_u, sizeof(float) * 2 * n_iter, hipMemcpyDeviceToHost, c->stream));
     if (x_hist)
@@ -982,6 +1081,16 @@ mppi_status mppi_merge_update(mppi_ctx* c, const float* rows_dev, int32_t n_rows
     hipLaunchKernelGGL(merge_update_kernel, dim3(1), dim3(256), 0, c->stream, a, rows_dev, (int)n_rows);
     HIP_TRY(c, hipGetLastError());
     return MPPI_OK;
+  });
+}
+
+mppi_status mppi_run_receding_device(mppi_ctx* c, float* x_dev, int32_t n_iter, float* u_hist_dev,
+                                     float* x_hist_dev) {
+  if (!c) return MPPI_E_INVAL;
+  return guarded(c, [&]() -> mppi_status {
+    if (!x_dev || n_iter < 0 || n_iter > (1 << 20)) return fail(c, MPPI_E_INVAL, "bad x_dev or n_iter");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return enqueue_receding_steps(c, x_dev, n_iter, u_hist_dev, x_hist_dev);
   });
 }
 

@@ -96,6 +96,14 @@ struct RolloutArgs {
   // (rho, eta, N[T][2]) here ([2 + 2T]) and leaves U, the statistics and the smoothing
   // to a later merge of every shard's row (merge_update_kernel).
   float* row_out;
+  // Multi-step receding launch (the split wave kernel, launched cooperatively): n_steps
+  // receding steps in one launch (0 or 1: one step).  After the final stage of step s the
+  // merging block writes *step_flag = step_base + s + 1 and every block waits for that
+  // value before step s + 1; u0_out and x_copy then point to [n_steps][2] and
+  // [n_steps][7] histories (step s writes entry s).
+  int n_steps;
+  unsigned* step_flag;
+  unsigned step_base;
 };
 
 constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)

@@ -36,6 +36,7 @@ EXPORTED = [
     "mppi_batch_set_dynamics", "mppi_batch_set_controls", "mppi_batch_iterate",
     "mppi_batch_get_controls", "mppi_batch_get_costs", "mppi_batch_get_schedule",
     "mppi_batch_synchronize", "mppi_iterate_noalloc", "mppi_iterate_partial", "mppi_merge_update",
+    "mppi_run_receding_device",
 ]
 
 
@@ -115,6 +116,7 @@ def lib() -> C.CDLL:
         L.mppi_batch_get_schedule.argtypes = [vp, i32p, i32p, C.POINTER(C.c_double)]
         L.mppi_batch_synchronize.argtypes = [vp]
         L.mppi_iterate_partial.argtypes = [vp, fp, vp, fp]
+        L.mppi_run_receding_device.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.mppi_merge_update.argtypes = [vp, vp, C.c_int32]
         L.mppi_iterate_noalloc.argtypes = [C.POINTER(mppi_config), C.POINTER(mppi_cost), C.c_int, vp, vp,
                                            C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, i32p, vp, vp,
@@ -248,6 +250,13 @@ def mppi_iterate_partial(ctx, x0, row_dev_ptr: int, costs_out: Optional[np.ndarr
 def mppi_merge_update(ctx, rows_dev_ptr: int, n_rows: int) -> None:
     """K-shard form: merge n_rows shard rows ([n_rows][2 + 2T] on the device) and update U."""
     _check(ctx, lib().mppi_merge_update(ctx, C.c_void_p(rows_dev_ptr), n_rows))
+
+
+def mppi_run_receding_device(ctx, x_dev_ptr: int, n_iter: int, u_hist_dev_ptr: int = 0,
+                             x_hist_dev_ptr: int = 0) -> None:
+    """n_iter receding steps on device data (pointers as integers); enqueued."""
+    _check(ctx, lib().mppi_run_receding_device(ctx, C.c_void_p(x_dev_ptr), n_iter, C.c_void_p(u_hist_dev_ptr or None),
+                                               C.c_void_p(x_hist_dev_ptr or None)))
 
 
 def mppi_get_stats(ctx, T: int):
