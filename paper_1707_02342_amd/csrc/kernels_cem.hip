@@ -320,7 +320,8 @@ __global__ __launch_bounds__(kCemBlock) void cem_update_kernel(RolloutArgs a) {
       s_delta[tid] = s;
     }
   }
-  fs.apply(a, s_delta, zeff > 0, zeff > 0 ? 1.0f / (float)zeff : 0.0f, key_cost(zkey), (float)zeff);
+  fs.apply(a, s_delta, zeff > 0, zeff > 0 ? 1.0f / (float)zeff : 0.0f, a.params, key_cost(zkey), (float)zeff,
+           a.nk.iter, a.u0_out, a.x_copy);
 }
 
 template __global__ void cem_update_kernel<2, 0>(RolloutArgs);

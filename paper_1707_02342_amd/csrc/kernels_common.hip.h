@@ -221,7 +221,8 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
 // network width when the calling kernel fixes it (0: a.hidden), so that every sum is
 // unrolled and its weight loads issued together (the arithmetic is the same).
 template <int NT, int kOut, int MODEL, int HC = 0>
-__device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float x_lane, float* lds) {
+__device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float x_lane, float* lds,
+                              const float* params, float* u0_out, float* x_copy) {
   constexpr bool kMayBasis = MODEL != kModelNet;
   constexpr bool kMayNet = MODEL != kModelBasis;
   __shared__ float s_h[2 * 64];
@@ -240,12 +241,12 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   // U, u_0 and the plant state are written through to the device's point of coherence:
   // in a multi-step launch the next step's blocks read them right after the step's signal
   for (int o = tid; o < T2; o += NT) store_through(a.Uout + o, (o + 2 < T2) ? lds[o + 2] : 0.0f);
-  if (tid < 2 && a.u0_out) store_through(a.u0_out + tid, lds[tid]);
+  if (tid < 2 && u0_out) store_through(u0_out + tid, lds[tid]);
   float x[kStateDim];
 #pragma unroll
   for (int i = 0; i < kStateDim; ++i) x[i] = s_x[i];
   const int H = HC > 0 ? HC : a.hidden;
-  const float* W1 = a.params;
+  const float* W1 = params;
   const float* b1 = W1 + H * 6;
   const float* W2 = b1 + H;
   const float* b2 = W2 + H * H;
@@ -257,7 +258,7 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   const bool net = kMayNet && (!kMayBasis || a.model != kModelBasis);
   if constexpr (kMayBasis) {
     // output tid in thread tid, with the plant step's arithmetic
-    if (!net && tid < 4) s_f[tid] = basis_out(a.params, in, vc0, vc1, tid);
+    if (!net && tid < 4) s_f[tid] = basis_out(params, in, vc0, vc1, tid);
   }
   if (kMayNet && net && tid < H) {
     float acc = b1[tid];
@@ -301,7 +302,7 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
 #pragma unroll
     for (int i = 0; i < kStateDim; ++i) {
       store_through(xs + i, y[i]);
-      if (a.x_copy) store_through(a.x_copy + i, y[i]);
+      if (x_copy) store_through(x_copy + i, y[i]);
     }
   }
 }
@@ -339,8 +340,10 @@ struct FinalStage {
     }
   }
 
-  __device__ __forceinline__ void apply(const RolloutArgs& a, float* lds, bool fin, float scale,
-                                        float stat0, float stat1) {
+  // iter: the counter word of this iteration (the device counter becomes iter + 1);
+  // u0_out, x_copy: the receding step's outputs (nullable)
+  __device__ __forceinline__ void apply(const RolloutArgs& a, float* lds, bool fin, float scale, const float* params,
+                                        float stat0, float stat1, uint32_t iter, float* u0_out, float* x_copy) {
     const int tid = threadIdx.x, T2 = 2 * a.T, w = a.sg_window;
 #pragma unroll
     for (int j = 0; j < kOut; ++j) {
@@ -382,17 +385,18 @@ struct FinalStage {
       *a.status = fin ? 0 : kStatusNonfinite;
       a.stats[0] = stat0;
       a.stats[1] = stat1;
-      if (a.iter_dev) *a.iter_dev = a.nk.iter + 1u;   // nk.iter: the counter read at the start of the launch
+      if (a.iter_dev) *a.iter_dev = iter + 1u;
     }
     if constexpr (RECEDE) {
-      if (a.recede) receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds);
+      if (a.recede) receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds, params, u0_out, x_copy);
     }
   }
 
   // K-shard form: the merged row (rho, eta, N[2T] in lds) of this launch's samples goes to
   // a.row_out in place of the update; U and the statistics are left unchanged.  Called
   // by the whole block.
-  __device__ __forceinline__ void export_row(const RolloutArgs& a, const float* lds, float rho, float eta) {
+  __device__ __forceinline__ void export_row(const RolloutArgs& a, const float* lds, float rho, float eta,
+                                             uint32_t iter) {
     const int tid = threadIdx.x, T2 = 2 * a.T;
     __syncthreads();
     for (int o = tid; o < T2; o += NT) a.row_out[2 + o] = lds[o];
@@ -400,9 +404,19 @@ struct FinalStage {
       a.row_out[0] = rho;
       a.row_out[1] = eta;
       *a.status = 0;
-      if (a.iter_dev) *a.iter_dev = a.nk.iter + 1u;
+      if (a.iter_dev) *a.iter_dev = iter + 1u;
     }
   }
+};
+
+// What the final stage of one iteration writes besides U: the counter word of the
+// iteration (the device counter becomes iter + 1) and, in a receding step, where u_0 and
+// the new plant state are copied (nullable).  A launch that runs several receding steps
+// passes each step's own.
+struct StepTarget {
+  uint32_t iter;
+  float* u0_out;
+  float* x_copy;
 };
 
 // Called by every rollout block with its partial row (rho_g, eta_g and N_g[2T] in
@@ -416,7 +430,11 @@ struct FinalStage {
 // thread, whether this block ran the final stage.
 template <int NT, int MODEL = kModelNet, bool RECEDE = true, int HC = 0>
 __device__ bool finish_iteration(const RolloutArgs& a, int tile, float rho_b, float eta_b,
-                                 const float* N_lds /* [2T] */, float* lds /* >= 2T floats */) {
+                                 const float* N_lds /* [2T] */, float* lds /* >= 2T floats */,
+                                 const float* params = nullptr /* the model's parameters in LDS, or a.params */,
+                                 const StepTarget* target = nullptr /* default: a.nk.iter, a.u0_out, a.x_copy */) {
+  if (!params) params = a.params;
+  const StepTarget st = target ? *target : StepTarget{a.nk.iter, a.u0_out, a.x_copy};
   bool ran_final = false;
   __shared__ unsigned s_flag;
   __shared__ float s_small[2 * kMergeChunk];
@@ -453,10 +471,11 @@ __device__ bool finish_iteration(const RolloutArgs& a, int tile, float rho_b, fl
     if (final_merge) {
       ran_final = true;
       if (a.row_out) {
-        fs.export_row(a, lds, rho, eta);
+        fs.export_row(a, lds, rho, eta, st.iter);
       } else {
         const bool fin = (rho < kInf) && (eta > 0.0f);
-        fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, rho, fin ? eta : 0.0f);
+        fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, params, rho, fin ? eta : 0.0f, st.iter, st.u0_out,
+                 st.x_copy);
       }
     }
   }

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void merge_update_kernel(RolloutArgs a, const 
   merge_rows<256>(rows, n, 2 + 2 * a.T, 2 * a.T, a.inv_lambda, lds, s_small, rho, eta);
   __syncthreads();
   const bool fin = (rho < kInf) && (eta > 0.0f);
-  fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, rho, fin ? eta : 0.0f);
+  fs.apply(a, lds, fin, fin ? 1.0f / eta : 0.0f, a.params, rho, fin ? eta : 0.0f, a.nk.iter, a.u0_out, a.x_copy);
 }
 
 }  // namespace mppi

@@ -28,8 +28,10 @@
 // rollout kernel.  The costs equal the wave kernel's up to the summation order of the
 // compensation terms and of the kinematic scans.
 //
-// Multi-step receding launch (n_steps > 1, launched cooperatively so that every block is
-// resident): the block loops over the steps, keeping the network in registers.  The
+// Multi-step receding launch (the MULTI instances with n_steps > 1, launched
+// cooperatively so that every block is resident): the block loops over the steps,
+// keeping the chain's network constants in registers and the model's parameters (for the
+// plant step of the final stage) in LDS.  The
 // block that runs step s's final stage (update, shift, plant step; every store written
 // through) waits for those stores and then writes the step signal; every block draws step
 // s + 1's noise (which does not depend on U) while the merge completes, then waits for
@@ -42,6 +44,10 @@ namespace mppi {
 
 constexpr int kSplitBlock = 512;   // 4 chain waves + 4 cost waves, 8 samples
 constexpr int kSplitPairs = 4;     // sample pairs per block (one chain and one cost wave each)
+// floats of the model's parameters a multi-step launch stages in LDS (the space is sized
+// for the 6-32-32-4 network, 1412 floats; the basis model stages its Theta, 100)
+constexpr int kSplitParams = 6 * 32 + 32 + 32 * 32 + 32 + 4 * 32 + 4;
+constexpr int kSplitBasisParams = 25 * 4;
 
 namespace {
 
@@ -126,9 +132,20 @@ __device__ __forceinline__ bool wait_signal(const unsigned* f, unsigned target) 
 
 }  // namespace
 
+// The launch's arguments, read again at each step of a multi-step launch from the kernel
+// argument segment (the kernel's one explicit argument sits at its start) through a
+// pointer the compiler cannot see through: otherwise every field would be held in
+// scalar registers over all steps, and the surplus spilled to vector lanes and read back
+// in every phase of every step.
+__device__ __forceinline__ const RolloutArgs& reload_args() {
+  uint64_t v = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(v));
+  return *(const RolloutArgs*)(const __attribute__((address_space(4))) RolloutArgs*)v;
+}
+
 constexpr int kStatusTimeout = 6;   // a multi-step launch gave up waiting for a step signal
 
-template <int MODEL>
+template <int MODEL, bool MULTI>
 __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(RolloutArgs a) {
   constexpr int HID = 32;
   constexpr bool kNet = MODEL == kModelNet;
@@ -138,7 +155,7 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   const int T4 = (T + 4) & ~3;
   const int eStride = (2 * T + 3) & ~3;
   const int nch = (T + 31) >> 5;                     // chunks of 32 steps (at most 4)
-  const int n_steps = a.n_steps > 1 ? a.n_steps : 1;
+  const int n_steps = MULTI && a.n_steps > 1 ? a.n_steps : 1;
   float* sU = smem;                                  // [2T]
   float* sE = sU + eStride;                          // [8][2T] noise
   float* sV = sE + kWaveSlots * eStride;             // network: [8][2T] clamped controls
@@ -146,6 +163,7 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   unsigned* sFlag = reinterpret_cast<unsigned*>(sX + kWaveSlots * T4 * 8);   // [4] chain progress, [4] spare
   float* sS = reinterpret_cast<float*>(sFlag + 8);   // [8] costs
   float* sB = sS + 8;                                // basis model: [8][T][8] control terms
+  float* sP = sB + (kNet ? 0 : kWaveSlots * T * 8);  // multi-step: the model's parameters (the plant step)
   // after both roles: the block's N row (the clamped controls or the basis terms are no
   // longer read) and the merge's working row (the states are no longer read)
   float* N_lds = kNet ? sV : sB;
@@ -223,39 +241,37 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   const uint32_t iter0 = a.iter_dev ? *a.iter_dev : a.nk.iter;   // the device counter, advanced by the final merge
   if (tid < 2 * kSplitPairs) sFlag[tid] = 0u;
   if (tid == 0) s_abort = 0u;
+  if constexpr (MULTI)
+    for (int i = tid; i < (kNet ? kSplitParams : kSplitBasisParams); i += kSplitBlock) sP[i] = a.params[i];
   draw_block_noise(a, iter0, kb, T, eStride, sE);
   if (chain) __builtin_amdgcn_s_setprio(2);
 
-  float* const u_hist = a.u0_out;
-  float* const x_hist = a.x_copy;
   for (int step = 0; step < n_steps; ++step) {
-    // this step's counter word and history entries (the final stage reads them from a)
-    a.nk.iter = iter0 + (uint32_t)step;
-    if (n_steps > 1) {
-      a.u0_out = u_hist ? u_hist + 2 * step : nullptr;
-      a.x_copy = x_hist ? x_hist + kStateDim * step : nullptr;
-    }
-    const RolloutArgs& as = a;
+    const RolloutArgs& as = MULTI ? reload_args() : a;
+    // this step's counter word and history entries
+    const uint32_t iter = iter0 + (uint32_t)step;
+    float* const u0_out = (as.u0_out && MULTI) ? as.u0_out + 2 * step : as.u0_out;
+    float* const x_copy = (as.x_copy && MULTI) ? as.x_copy + kStateDim * step : as.x_copy;
     // ---- this step's U and plant state (after the previous step's signal) -------------
     if (step > 0) {
-      if (tid == 0 && !wait_signal(a.step_flag, a.step_base + (unsigned)step)) {
+      if (tid == 0 && !wait_signal(as.step_flag, as.step_base + (unsigned)step)) {
         s_abort = 1u;
-        __hip_atomic_store(a.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(as.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
       if (s_abort) break;
     }
-    for (int i = tid; i < 2 * T; i += kSplitBlock) sU[i] = step > 0 ? load_through(a.U + i) : a.U[i];
+    for (int i = tid; i < 2 * T; i += kSplitBlock) sU[i] = step > 0 ? load_through(as.U + i) : as.U[i];
     float x0v[kStateDim];
 #pragma unroll
     for (int i = 0; i < kStateDim; ++i)
-      x0v[i] = step > 0 ? load_through(a.x0_dev + i) : (a.x0_dev ? a.x0_dev[i] : a.x0[i]);
+      x0v[i] = step > 0 ? load_through(as.x0_dev + i) : (as.x0_dev ? as.x0_dev[i] : as.x0[i]);
     __syncthreads();
     // the controls of every sample and step; the state entry 0 of every sample
     for (int i = tid; i < kWaveSlots * T; i += kSplitBlock) {
       const int sl = i / T, t = i - sl * T;
       step_controls<MODEL>(as, sU[2 * t], sU[2 * t + 1], sE[sl * eStride + 2 * t], sE[sl * eStride + 2 * t + 1],
-                           kb + sl >= a.K_imp, sV + sl * eStride + 2 * t, sB + sl * T * 8 + 8 * t);
+                           kb + sl >= as.K_imp, sV + sl * eStride + 2 * t, sB + sl * T * 8 + 8 * t);
     }
     if (tid < kWaveSlots * 4) sX[(tid >> 2) * T4 * 8 + (tid & 3)] = x0v[3 + (tid & 3)];
     __syncthreads();
@@ -304,7 +320,7 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
               if (i + 2 < kRaw) p2 = __builtin_fmaf(kc[i + 2], raw[i + 2], p2);
               if (i + 3 < kRaw) p3 = __builtin_fmaf(kc[i + 3], raw[i + 3], p3);
             }
-            y = a.dt * ((p0 + p1) + (p2 + p3));
+            y = as.dt * ((p0 + p1) + (p2 + p3));
             bq = bq_next;
             cq = cq_next;
           } else {
@@ -408,7 +424,7 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
           lo[i] = lo[i] + last_of_half(ex + e_);       // the chunk's errors
         }
         // heading before the step: theta_0 + dt * (sum of the previous steps' theta_dot)
-        const float dth = live ? a.dt * xp[3] : 0.0f;
+        const float dth = live ? as.dt * xp[3] : 0.0f;
         float sh = dth, sl = 0.0f;
         scan32_excl2(sh, sl, c32);
         float th = th_h, thl = th_l;
@@ -421,8 +437,8 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
         // position after the step: p_0 + dt * (sum over s <= t of R(theta_s) v_s)
         float sn, cs;
         sincosf(th + thl, &sn, &cs);
-        const float dpx = live ? a.dt * (cs * xp[1] - sn * xp[2]) : 0.0f;
-        const float dpy = live ? a.dt * (sn * xp[1] + cs * xp[2]) : 0.0f;
+        const float dpx = live ? as.dt * (cs * xp[1] - sn * xp[2]) : 0.0f;
+        const float dpy = live ? as.dt * (sn * xp[1] + cs * xp[2]) : 0.0f;
         float qxh = dpx, qxl = 0.0f, qyh = dpy, qyl = 0.0f;
         scan32_excl2(qxh, qxl, c32);
         scan32_excl2(qyh, qyl, c32);
@@ -439,9 +455,9 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
         // cost of the post-step state and the control cost of the step
         int idx[4];
         float fx, fy;
-        map_taps(a.cost, pxh, pxl, pyh, pyl, idx, fx, fy);
-        const float mv[4] = {a.map[idx[0]], a.map[idx[1]], a.map[idx[2]], a.map[idx[3]]};
-        const float dec = a.decay[tc + 1];
+        map_taps(as.cost, pxh, pxl, pyh, pyl, idx, fx, fy);
+        const float mv[4] = {as.map[idx[0]], as.map[idx[1]], as.map[idx[2]], as.map[idx[3]]};
+        const float dec = as.decay[tc + 1];
         if (live) {
           const float px1 = pxh + pxl, py1 = pyh + pyl;
           if (as.ckpt && ((t + 1) % as.ckpt_every) == 0 && valid) {
@@ -449,15 +465,15 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
             cp[0] = px1; cp[1] = py1; cp[2] = th1;
             cp[3] = xn[0]; cp[4] = xn[1]; cp[5] = xn[2]; cp[6] = xn[3];
           }
-          Sacc.add(state_cost_h(a.cost, bilerp(mv, fx, fy), dec, xn[1], xn[2]));
+          Sacc.add(state_cost_h(as.cost, bilerp(mv, fx, fy), dec, xn[1], xn[2]));
           const float u0 = sU[2 * t], u1 = sU[2 * t + 1];
           const float d0 = zm ? myE[2 * t] - u0 : myE[2 * t];
           const float d1 = zm ? myE[2 * t + 1] - u1 : myE[2 * t + 1];
-          Sacc.add(a.gcs0 * (u0 * d0) + a.gcs1 * (u1 * d1));
+          Sacc.add(as.gcs0 * (u0 * d0) + as.gcs1 * (u1 * d1));
           ok = ok && finite_f(px1) && finite_f(py1) && finite_f(th1) && finite_f(xn[0]) && finite_f(xn[1]) &&
                finite_f(xn[2]) && finite_f(xn[3]);
-          if (a.cem_zeta > 0 && valid) {
-            float* drow = a.D + (size_t)k * 2 * T;
+          if (as.cem_zeta > 0 && valid) {
+            float* drow = as.D + (size_t)k * 2 * T;
             drow[2 * t] = d0;
             drow[2 * t + 1] = d1;
           }
@@ -467,11 +483,11 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
       sum32_2(S_h, S_l);
       float S = S_h + S_l;
       if (!valid || !all32(ok) || !finite_f(S)) S = kInf;
-      if (valid && c32 == 0) store_through(a.S + k, S);   // read by the host or Algorithm 3's update
+      if (valid && c32 == 0) store_through(as.S + k, S);   // read by the host or Algorithm 3's update
       if (c32 == 0) sS[slot] = S;
     }
     __syncthreads();
-    if (a.cem_zeta > 0) return;   // the cross-entropy update runs in the launch that follows
+    if (as.cem_zeta > 0) return;   // the cross-entropy update runs in the launch that follows
 
     // ---- the block's softmin partial (rho_g, eta_g, N_g) ------------------------------
     float Sk[kWaveSlots];
@@ -484,7 +500,7 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
     float eta = 0.0f;
 #pragma unroll
     for (int q = 0; q < kWaveSlots; ++q) {
-      wgt[q] = rel_weight(Sk[q], rho, a.inv_lambda);
+      wgt[q] = rel_weight(Sk[q], rho, as.inv_lambda);
       eta += wgt[q];
     }
     for (int o = tid; o < 2 * T; o += kSplitBlock) {
@@ -493,27 +509,31 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
 #pragma unroll
       for (int q = 0; q < kWaveSlots; ++q) {
         const float e = sE[q * eStride + o];
-        n = __builtin_fmaf(wgt[q], (kb + q >= a.K_imp) ? e - u : e, n);
+        n = __builtin_fmaf(wgt[q], (kb + q >= as.K_imp) ? e - u : e, n);
       }
       N_lds[o] = n;
     }
-    const bool ran_final = finish_iteration<kSplitBlock, MODEL, true, HID>(as, blockIdx.x, rho, eta, N_lds, lds);
+    const StepTarget target{iter, u0_out, x_copy};
+    const bool ran_final = finish_iteration<kSplitBlock, MODEL, true, HID>(as, blockIdx.x, rho, eta, N_lds, lds,
+                                                                           MULTI ? sP : as.params, &target);
     if (step + 1 < n_steps) {
       if (ran_final) {
         // every write-through store of the final stage has completed before the signal
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.step_flag, a.step_base + (unsigned)(step + 1), __ATOMIC_RELAXED,
+        if (tid == 0) __hip_atomic_store(as.step_flag, as.step_base + (unsigned)(step + 1), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
       }
       // the next step's noise does not depend on its U: drawn while the merge completes
-      draw_block_noise(a, iter0 + (uint32_t)(step + 1), kb, T, eStride, sE);
+      draw_block_noise(as, iter0 + (uint32_t)(step + 1), kb, T, eStride, sE);
     }
   }
 }
 
-template __global__ void rollout_wave_split_kernel<kModelNet>(RolloutArgs);
-template __global__ void rollout_wave_split_kernel<kModelBasis>(RolloutArgs);
+template __global__ void rollout_wave_split_kernel<kModelNet, false>(RolloutArgs);
+template __global__ void rollout_wave_split_kernel<kModelBasis, false>(RolloutArgs);
+template __global__ void rollout_wave_split_kernel<kModelNet, true>(RolloutArgs);
+template __global__ void rollout_wave_split_kernel<kModelBasis, true>(RolloutArgs);
 
 // Dynamic LDS bytes of the split kernel for horizon T (T <= 128).
 size_t wave_split_smem_bytes(int T, int model) {
@@ -521,7 +541,7 @@ size_t wave_split_smem_bytes(int T, int model) {
   const size_t T4 = (size_t)((T + 4) & ~3);
   const size_t v = model == kModelNet ? (size_t)kWaveSlots * e : 0;
   const size_t basis = model == kModelBasis ? (size_t)kWaveSlots * T * 8 : 0;
-  return sizeof(float) * (e + kWaveSlots * e + v + (size_t)kWaveSlots * T4 * 8 + 8 + 8 + basis);
+  return sizeof(float) * (e + kWaveSlots * e + v + (size_t)kWaveSlots * T4 * 8 + 8 + 8 + basis + kSplitParams);
 }
 
 }  // namespace mppi

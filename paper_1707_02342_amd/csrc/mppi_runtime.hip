@@ -23,7 +23,7 @@ namespace mppi {
 hipError_t launch_lane(int precision, int hidden, dim3 grid, hipStream_t stream, const RolloutArgs& a);
 template <int HID, int NQ, int MODEL> __global__ void rollout_wave_kernel(RolloutArgs);
 size_t wave_smem_bytes(int T, int model);
-template <int MODEL> __global__ void rollout_wave_split_kernel(RolloutArgs);
+template <int MODEL, bool MULTI> __global__ void rollout_wave_split_kernel(RolloutArgs);
 size_t wave_split_smem_bytes(int T, int model);
 constexpr int kWaveSplitBlockThreads = 512;   // 4 chain waves + 4 cost waves
 constexpr int kWaveSplitMaxT = 128;
@@ -322,11 +322,11 @@ void launch_wave(int G, int T, hipStream_t stream, const RolloutArgs& a) {
   if (T <= kWaveSplitMaxT && G <= device_cus()) {
     const size_t smem = wave_split_smem_bytes(T, a.model);
     if (a.model == kModelBasis)
-      hipLaunchKernelGGL((rollout_wave_split_kernel<kModelBasis>), dim3(G), dim3(kWaveSplitBlockThreads), smem,
-                         stream, a);
+      hipLaunchKernelGGL((rollout_wave_split_kernel<kModelBasis, false>), dim3(G), dim3(kWaveSplitBlockThreads),
+                         smem, stream, a);
     else
-      hipLaunchKernelGGL((rollout_wave_split_kernel<kModelNet>), dim3(G), dim3(kWaveSplitBlockThreads), smem,
-                         stream, a);
+      hipLaunchKernelGGL((rollout_wave_split_kernel<kModelNet, false>), dim3(G), dim3(kWaveSplitBlockThreads),
+                         smem, stream, a);
     return;
   }
   const size_t smem = wave_smem_bytes(T, a.model);
@@ -576,8 +576,9 @@ mppi_status enqueue_receding_steps(mppi_ctx* c, float* x_dev, int n, float* u_hi
     HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
   }
   void* args[] = {&a};
-  const void* fn = c->model == kModelBasis ? reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelBasis>)
-                                           : reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelNet>);
+  const void* fn = c->model == kModelBasis
+                       ? reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelBasis, true>)
+                       : reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelNet, true>);
   HIP_TRY(c, hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWaveSplitBlockThreads), args,
                                         (unsigned)wave_split_smem_bytes(c->cfg.T, c->model), c->stream));
   if (c->timing) {
@@ -709,7 +710,8 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
     if (cfg->weighting == MPPI_WEIGHTS_CEM) HIP_TRY(c, hipMalloc(&c->d_D, sizeof(float) * (size_t)K * 2 * T));
-    HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
+    // rows of 2 + 2T floats, padded to whole 16-byte chunks (the split wave kernel's merge)
+    HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * ((2 + 2 * T + 3) & ~3)));
     const int ngrp_cap = std::max({merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WAVE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WIDE)),
