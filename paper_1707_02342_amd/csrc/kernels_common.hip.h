@@ -208,14 +208,22 @@ __device__ bool publish_and_count(float* dst, float rho, float eta, const float*
   return publish_and_count<NT>(dst, rho, eta, N_lds, T2, cnt, expected, s_flag, [] {});
 }
 
+// The value of v in lane `src` of the calling wave (src uniform).
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+
 // The receding-horizon part of a control step (Algorithm 1's last block and the
 // plant), run by the final merge after the update: U is shifted (u_0 out,
 // u_{t-1} <- u_t, u_{T-1} <- (0, 0)), and the plant state in x0_dev advances by one
-// noise-free step x <- F(x, g(u_0)).  The network runs one neuron per lane of wave 0,
-// each neuron's sums in input order, so the new state equals a one-thread evaluation
-// bit for bit.  x_lane: component tid of the plant state before the step (threads
-// tid < 7), loaded by the merging block before its merge; every other block of the launch has read x0_dev before it published its
-// row, so x0_dev can be overwritten here.  lds (>= 2T floats) is free on entry.
+// noise-free step x <- F(x, g(u_0)).  The plant step runs in wave 0 alone, without
+// block barriers: the network one neuron per lane (the hidden width is at most 64), each
+// neuron's sum in input order with the previous layer's outputs read lane by lane, so
+// the new state equals a one-thread evaluation bit for bit.  x_lane: component tid of
+// the plant state before the step (threads tid < 7), loaded by the merging block before
+// its merge; every other block of the launch has read x0_dev before it published its
+// row, so x0_dev can be overwritten here.  lds (>= 2T floats) holds Delta on entry,
+// still read by the smoothing of other threads.
 // MODEL: the dynamics model the calling kernel serves (kModelAny: decided by a.model);
 // a kernel that serves one model compiles only that model's plant step.  HC: the
 // network width when the calling kernel fixes it (0: a.hidden), so that every sum is
@@ -225,13 +233,11 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
                               const float* params, float* u0_out, float* x_copy) {
   constexpr bool kMayBasis = MODEL != kModelNet;
   constexpr bool kMayNet = MODEL != kModelBasis;
-  __shared__ float s_h[2 * 64];
-  __shared__ float s_f[4];
   __shared__ float s_x[kStateDim];
   const int tid = threadIdx.x;
   const int T2 = 2 * a.T;
   if (tid < kStateDim) s_x[tid] = x_lane;
-  __syncthreads();
+  __syncthreads();   // every thread's smoothing has read Delta
 #pragma unroll
   for (int j = 0; j < kOut; ++j) {
     const int o = tid + j * NT;
@@ -242,68 +248,68 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   // in a multi-step launch the next step's blocks read them right after the step's signal
   for (int o = tid; o < T2; o += NT) store_through(a.Uout + o, (o + 2 < T2) ? lds[o + 2] : 0.0f);
   if (tid < 2 && u0_out) store_through(u0_out + tid, lds[tid]);
+  if (tid >= 64) return;
+  const int lane = tid;
   float x[kStateDim];
 #pragma unroll
   for (int i = 0; i < kStateDim; ++i) x[i] = s_x[i];
-  const int H = HC > 0 ? HC : a.hidden;
-  const float* W1 = params;
-  const float* b1 = W1 + H * 6;
-  const float* W2 = b1 + H;
-  const float* b2 = W2 + H * H;
-  const float* W3 = b2 + H;
-  const float* b3 = W3 + 4 * H;
   const float vc0 = fminf(fmaxf(lds[0], a.u_lo0), a.u_hi0);
   const float vc1 = fminf(fmaxf(lds[1], a.u_lo1), a.u_hi1);
   const float in[6] = {x[3], x[4], x[5], x[6], vc0, vc1};
   const bool net = kMayNet && (!kMayBasis || a.model != kModelBasis);
+  float f = 0.0f;   // output `lane` of the dynamics (lanes < 4)
   if constexpr (kMayBasis) {
-    // output tid in thread tid, with the plant step's arithmetic
-    if (!net && tid < 4) s_f[tid] = basis_out(params, in, vc0, vc1, tid);
+    if (!net && lane < 4) f = basis_out(params, in, vc0, vc1, lane);
   }
-  if (kMayNet && net && tid < H) {
-    float acc = b1[tid];
+  if constexpr (kMayNet) {
+    if (net) {
+      const int H = HC > 0 ? HC : a.hidden;
+      const float* W1 = params;
+      const float* b1 = W1 + H * 6;
+      const float* W2 = b1 + H;
+      const float* b2 = W2 + H * H;
+      const float* W3 = b2 + H;
+      const float* b3 = W3 + 4 * H;
+      const int n = lane < H ? lane : 0;   // the lane's neuron (lanes past H repeat neuron 0)
+      float acc = b1[n];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[tid * 6 + j], in[j], acc);
-    s_h[tid] = tanh_f(acc);
-  }
-  __syncthreads();
-  if (kMayNet && net && tid < H) {
-    float acc = b2[tid];
-    if constexpr (HC > 0) {
+      for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[n * 6 + j], in[j], acc);
+      const float h1 = tanh_f(acc);
+      acc = b2[n];
+      if constexpr (HC > 0) {
 #pragma unroll
-      for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W2[tid * HC + j], s_h[j], acc);
-    } else {
-      for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[tid * H + j], s_h[j], acc);
+        for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W2[n * HC + j], lane_value(h1, j), acc);
+      } else {
+        for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[n * H + j], lane_value(h1, j), acc);
+      }
+      const float h2 = tanh_f(acc);
+      const int o = lane & 3;
+      acc = b3[o];
+      if constexpr (HC > 0) {
+#pragma unroll
+        for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W3[o * HC + j], lane_value(h2, j), acc);
+      } else {
+        for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[o * H + j], lane_value(h2, j), acc);
+      }
+      f = acc;
     }
-    s_h[64 + tid] = tanh_f(acc);
   }
-  __syncthreads();
-  if (kMayNet && net && tid < 4) {
-    float acc = b3[tid];
-    if constexpr (HC > 0) {
+  const float fo[4] = {lane_value(f, 0), lane_value(f, 1), lane_value(f, 2), lane_value(f, 3)};
+  float sth, cth;
+  sincosf(x[2], &sth, &cth);
+  float y[kStateDim];
+  y[0] = x[0] + a.dt * (cth * x[4] - sth * x[5]);
+  y[1] = x[1] + a.dt * (sth * x[4] + cth * x[5]);
+  y[2] = x[2] + a.dt * x[6];
 #pragma unroll
-      for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W3[tid * HC + j], s_h[64 + j], acc);
-    } else {
-      for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[tid * H + j], s_h[64 + j], acc);
-    }
-    s_f[tid] = acc;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    float sth, cth;
-    sincosf(x[2], &sth, &cth);
-    float y[kStateDim];
-    y[0] = x[0] + a.dt * (cth * x[4] - sth * x[5]);
-    y[1] = x[1] + a.dt * (sth * x[4] + cth * x[5]);
-    y[2] = x[2] + a.dt * x[6];
+  for (int i = 0; i < 4; ++i) y[3 + i] = x[3 + i] + a.dt * fo[i];
+  // component `lane` by lane (lanes < 7), selected with constant indices
+  float yl = y[0];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) y[3 + i] = x[3 + i] + a.dt * s_f[i];
-    float* xs = const_cast<float*>(a.x0_dev);
-#pragma unroll
-    for (int i = 0; i < kStateDim; ++i) {
-      store_through(xs + i, y[i]);
-      if (x_copy) store_through(x_copy + i, y[i]);
-    }
+  for (int i = 1; i < kStateDim; ++i) yl = lane == i ? y[i] : yl;
+  if (lane < kStateDim) {
+    store_through(const_cast<float*>(a.x0_dev) + lane, yl);
+    if (x_copy) store_through(x_copy + lane, yl);
   }
 }
 

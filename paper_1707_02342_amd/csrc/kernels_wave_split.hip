@@ -14,8 +14,11 @@
 //    deferred form does -- layer 1 from quad_perm DPP operands, layer 2 in row_ror DPP
 //    operands of v_fmac_f32 and a v_permlane16_swap, layer 3 (times dt) as a
 //    reduce-scatter, the uncompensated state hi_{t+1} = hi_t + y_t and its increment
-//    y_t stored to LDS -- and publishes each finished chunk of 32 steps with a
-//    workgroup-scope release of a per-pair counter in LDS;
+//    y_t stored to LDS -- and publishes each finished chunk of steps with a
+//    workgroup-scope release of a per-pair counter in LDS.  The chunks hold 32 steps
+//    except the first, which holds the remainder of T: a chunk costs the cost wave
+//    about the same time whatever its length, and with the short chunk first the cost
+//    wave has finished every chunk but the last when the chain ends;
 //  cost wave (waves 4..7): follows the chain one chunk behind: for chunk c it waits
 //    (acquire) for the chain's counter, forms the compensated states x_d(t) = hi_t + lo_t
 //    (the two-sum errors of the chain's sums, scanned across the lanes), the heading and
@@ -154,7 +157,8 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   const int T = a.T;
   const int T4 = (T + 4) & ~3;
   const int eStride = (2 * T + 3) & ~3;
-  const int nch = (T + 31) >> 5;                     // chunks of 32 steps (at most 4)
+  const int nch = (T + 31) >> 5;                     // chunks of up to 32 steps (at most 4)
+  const int r0 = T - 32 * (nch - 1);                 // steps in chunk 0 (1..32); every later chunk has 32
   const int n_steps = MULTI && a.n_steps > 1 ? a.n_steps : 1;
   float* sU = smem;                                  // [2T]
   float* sE = sU + eStride;                          // [8][2T] noise
@@ -291,8 +295,8 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
       // the lane's store slot: hi_{t+1} (lanes with bit 2 clear) or y_t (bit 2 set)
       float* xs = myX + ((lane & 4) ? 4 + comp : 8 + comp);
       for (int c = 0; c < nch; ++c) {
-        const int t1 = min(T, 32 * c + 32);
-        for (int t = 32 * c; t < t1; ++t) {
+        const int t1 = r0 + 32 * c;
+        for (int t = c > 0 ? t1 - 32 : 0; t < t1; ++t) {
           const int tn = min(t + 1, T - 1);
           float y;   // dt * f of the lane's component
           if constexpr (MODEL == kModelBasis) {
@@ -404,8 +408,8 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
       bool ok = true;
       for (int c = 0; c < nch; ++c) {
         wait_count(chainCnt, (unsigned)(step * nch + c + 1));
-        const int t = 32 * c + c32;
-        const bool live = t < T;
+        const int t = (c > 0 ? r0 + 32 * (c - 1) : 0) + c32;
+        const bool live = c > 0 || c32 < r0;
         const int tc = min(t, T - 1);
         const float4 hv = live ? *reinterpret_cast<const float4*>(myX + 8 * tc) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         const float4 yv = live ? *reinterpret_cast<const float4*>(myX + 8 * tc + 4) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);

@@ -710,8 +710,7 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_U, 0, sizeof(float) * 2 * T, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_S, sizeof(float) * K));
     if (cfg->weighting == MPPI_WEIGHTS_CEM) HIP_TRY(c, hipMalloc(&c->d_D, sizeof(float) * (size_t)K * 2 * T));
-    // rows of 2 + 2T floats, padded to whole 16-byte chunks (the split wave kernel's merge)
-    HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * ((2 + 2 * T + 3) & ~3)));
+    HIP_TRY(c, hipMalloc(&c->d_part, sizeof(float) * (size_t)c->part_cap * (2 + 2 * T)));
     const int ngrp_cap = std::max({merge_groups(blocks_for(c, MPPI_SCHED_LANE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WAVE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WIDE)),
