@@ -44,6 +44,11 @@ KERNEL_SOURCES = ["kernels_wave_split.hip", "kernels_wave.hip", "wave_common.hip
 NET_FLOP_PER_STEP = {32: 2 * (6 * 32 + 32 * 32 + 32 * 4), 64: 2 * (6 * 64 + 64 * 64 + 64 * 4)}
 # basis-function model: Theta^T phi (25 x 4 multiply-adds) plus about 40 operations forming phi
 BASIS_FLOP_PER_STEP = 2 * 25 * 4 + 40
+# adjoint rollout per sample and step (h = 32): the forward network recomputed from the
+# checkpoint (2688) and the reverse sweep -- per layer the transposed product for the
+# input cotangent and the outer product for the weight gradient, each the size of the
+# forward product (2 x 2688)
+ADJOINT_FLOP_PER_STEP = 3 * NET_FLOP_PER_STEP[32]
 
 
 def parse():
@@ -58,6 +63,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision/batched/differentiation forms")
     ap.add_argument("--precision-only", action="store_true",
                     help="only time the precision form (K=16384 and 65536), print its JSON and exit")
+    ap.add_argument("--differentiation-only", action="store_true",
+                    help="only time the differentiation form (K=4096, T=100), print its JSON and exit")
     ap.add_argument("--write-traffic", metavar="PMC_DIR",
                     help="reduce rocprofv3 FETCH_SIZE/WRITE_SIZE runs under PMC_DIR to the stored traffic "
                          "record under profiles/ and exit")
@@ -272,6 +279,42 @@ def measure_precision(M, stream, iters: int = 30):
     return prec
 
 
+def measure_differentiation(M, stream, iters: int = 30):
+    """The differentiation form: K=4096, T=100, the free-energy objective plus its adjoint
+    gradient with checkpoints every 10 steps; wall time per value-and-gradient, and the
+    adjoint rollout kernel's duration and roofline (HIP events on the library's stream)."""
+    import synth
+    prob = synth.c5_problem(seed=0)
+    U = synth.random_controls(prob.T, 0, scale=0.2)
+    with M.Controller(prob, synth.ring_map(), synth.mlp_params(32, 0), stream=int(stream.cuda_stream)) as c:
+        c.set_controls(U)
+        for _ in range(2):
+            c.objective(synth.C1_X0, 0, 10)
+            c.objective_backward()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            c.objective(synth.C1_X0, 0, 10)
+            c.objective_backward()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+        # kernel durations (HIP events on the library's stream): the objective's forward
+        # launch (slot 0) and the adjoint rollout kernel (slot 1)
+        M.mppi_set_timing(c.ctx, True)
+        for _ in range(iters):
+            c.objective(synth.C1_X0, 0, 10)
+            c.objective_backward()
+        (f_ms, a_ms), (f_n, a_n) = M.mppi_get_timing(c.ctx)
+        M.mppi_set_timing(c.ctx, False)
+    adj_ms = a_ms / a_n
+    adj_tf = ADJOINT_FLOP_PER_STEP * prob.K * prob.T / (adj_ms * 1e-3) / 1e12
+    return {"ms_per_value_and_gradient": ms,
+            "forward_kernel_ms": f_ms / f_n, "adjoint_kernel_ms": adj_ms,
+            "roofline": {"bound": "alu", "achieved": adj_tf, "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": adj_tf / PEAK_FP32_TFLOPS,
+                         "kernel": "adjoint_wave_kernel",
+                         "flop_per_launch": ADJOINT_FLOP_PER_STEP * prob.K * prob.T},
+            "workload": "K=4096, T=100, checkpoints every 10 steps, 1612 gradient entries"}
+
+
 def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
     """The three added forms on their own workloads (synthetic, seeded):
     precision: K=16384 and K=65536, T=100, 6-64-64-4 network, one iteration in FP32 and
@@ -300,29 +343,18 @@ def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
             b.iterate(x0s)
         b.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / iters
-        grid, order, tuned_us = b.schedule()
+        grid, order, tuned_us, tiles = b.schedule()
     work = float(sum(k * t for k, t in zip(Ks, Ts)))
     bt = work * NET_FLOP_PER_STEP[32] / (ms * 1e-3) / 1e12
     out["batched"] = {"ms_per_iteration": ms, "steps_per_s": work / (ms * 1e-3), "instances": len(Ks),
                       "roofline": {"bound": "mfma", "achieved": bt, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                                    "frac": bt / PEAK_FP32_TFLOPS},
                       "grid": grid, "order": order,
+                      "tiles": {1: "lane schedule, 256 samples per tile",
+                                4: "quad schedule, 64 samples per tile"}.get(tiles, tiles),
                       "workload": "512 instances, K_i in {512..4096}, T_i in {50..150}, 2048x2048 map"}
 
-    prob = synth.c5_problem(seed=0)
-    U = synth.random_controls(prob.T, 0, scale=0.2)
-    with M.Controller(prob, synth.ring_map(), synth.mlp_params(32, 0), stream=int(stream.cuda_stream)) as c:
-        c.set_controls(U)
-        for _ in range(2):
-            c.objective(synth.C1_X0, 0, 10)
-            c.objective_backward()
-        t0 = time.perf_counter()
-        for _ in range(iters):
-            c.objective(synth.C1_X0, 0, 10)
-            c.objective_backward()
-        ms = (time.perf_counter() - t0) * 1e3 / iters
-    out["differentiation"] = {"ms_per_value_and_gradient": ms,
-                              "workload": "K=4096, T=100, checkpoints every 10 steps, 1612 gradient entries"}
+    out["differentiation"] = measure_differentiation(M, stream, iters)
 
     emap = synth.ellipse_map()
     for name, prob, desc in (
@@ -418,6 +450,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.precision_only:
         print(json.dumps({"precision": measure_precision(M, stream, iters=10)}), flush=True)
+        return
+    if args.differentiation_only:
+        print(json.dumps({"differentiation": measure_differentiation(M, stream, iters=10)}), flush=True)
         return
     cmap = synth.ellipse_map()
     prob = synth.c2_problem(seed=0)

@@ -276,14 +276,17 @@ mppi_status mppi_get_schedule(const mppi_ctx* ctx, int32_t* schedule);
 
 /* Device time of the iteration kernel, measured with HIP events recorded on the
  * context's stream around every launch once enabled.  times_ms[0] = the rollout
- * kernel (which also forms the weights and updates U in its last block), summed
- * since timing was last enabled, counts[0] = launches; times_ms[1] and counts[1]
- * are 0 (reserved).  The events add stream markers between launches, so measure
- * throughput with timing off.  mppi_get_timing synchronises. */
+ * kernel (which also forms the weights and updates U in its last block; also the
+ * forward launch of mppi_objective), summed since timing was last enabled,
+ * counts[0] = launches; times_ms[1] and counts[1]
+ * the same for the adjoint rollout kernel of mppi_objective_backward (its two
+ * gradient reduction kernels excluded).  The events add stream markers between
+ * launches, so measure throughput with timing off.  mppi_get_timing synchronises. */
 mppi_status mppi_set_timing(mppi_ctx* ctx, int32_t enable);
 mppi_status mppi_get_timing(mppi_ctx* ctx, double times_ms[2], int64_t counts[2]);
-/* The individual launch durations (ms) behind mppi_get_timing, oldest first: up to
- * cap of them into ms_out; *n_out = how many were recorded.  Synchronises. */
+/* The individual launch durations (ms) behind mppi_get_timing's times_ms[0], oldest
+ * first: up to cap of them into ms_out; *n_out = how many were recorded.
+ * Synchronises. */
 mppi_status mppi_get_timing_samples(mppi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out);
 
 /* Differentiation form.  The free-energy objective of Eq. FreeEnergy estimated with
@@ -366,9 +369,14 @@ mppi_status mppi_batch_iterate(mppi_batch* b, const float* x0);
 /* Instance i's controls ([T_i][2]) / costs of its last iteration ([K_i]).  Synchronise. */
 mppi_status mppi_batch_get_controls(mppi_batch* b, int32_t i, float* U_out);
 mppi_status mppi_batch_get_costs(mppi_batch* b, int32_t i, float* S_out);
-/* The schedule the autotuner chose: persistent grid size, work order (0 = by
- * instance, 1 = longest horizon first) and its measured time per launch. */
-mppi_status mppi_batch_get_schedule(mppi_batch* b, int32_t* grid, int32_t* order, double* tuned_us);
+/* The schedule the autotuner chose: persistent grid size (blocks that take work
+ * items from the launch's queue), work order (0 = by instance, 1 = longest horizon
+ * first), its measured time per launch, and the rollout schedule of the tiles
+ * (MPPI_SCHED_QUAD: 64 samples per tile, four lanes per sample; MPPI_SCHED_LANE: 256
+ * samples, one lane each -- both are tried when the configuration's schedule is
+ * MPPI_SCHED_AUTO).  Any output pointer may be NULL. */
+mppi_status mppi_batch_get_schedule(mppi_batch* b, int32_t* grid, int32_t* order, double* tuned_us,
+                                    int32_t* schedule);
 mppi_status mppi_batch_synchronize(mppi_batch* b);
 
 #ifdef __cplusplus

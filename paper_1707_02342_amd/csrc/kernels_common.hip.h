@@ -73,6 +73,30 @@ __device__ __forceinline__ float load_through(const float* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The work queue of a persistent launch: queue[0] counts the work items handed out,
+// queue[1] the blocks that have found the queue empty.  Returns the calling block's next
+// item (the same in every thread), or -1 once all n_items have been handed out.  The
+// last block to find the queue empty resets both words (every other block has taken its
+// last item by then), so each launch, also one replayed from a captured graph, starts
+// from zero without a memset.  Every block calls it until it returns -1.
+__device__ __forceinline__ int next_work_item(unsigned* queue, int n_items) {
+  __shared__ int s_item;
+  __syncthreads();   // the block is done with its previous item
+  if (threadIdx.x == 0) {
+    int b = (int)atomicAdd(queue, 1u);
+    if (b >= n_items) {
+      b = -1;
+      if (atomicAdd(queue + 1, 1u) == gridDim.x - 1u) {
+        __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    s_item = b;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s_item);   // uniform: the item's data is read with scalar loads
+}
+
 constexpr int kMergeChunk = 64;
 constexpr int kStatusNonfinite = 5;
 

@@ -362,20 +362,23 @@ __global__ __launch_bounds__(kLaneBlock) void rollout_lane_kernel(RolloutArgs a)
 }
 
 // Batched form: many independent problems (instances) in one persistent launch.
-// items[b] = (instance, tile); block b processes items b, b + gridDim.x, ...  Each
-// instance's noise uses its own iteration counter (advanced by its final merge) and
-// its index as the fourth Philox counter word.  A tile's work and an instance's merge
-// order do not depend on which block runs it, so results are the same for every
-// grid size and item order.
+// items[b] = (instance, tile); each block takes items from the launch's work queue in
+// the order of the list.  Each instance's noise uses its own iteration counter
+// (advanced by its final merge) and its index as the fourth Philox counter word.  A
+// tile's work and an instance's merge order do not depend on which block runs it, so
+// results are the same for every grid size and item order.
 __global__ __launch_bounds__(kLaneBlock) void rollout_batch_kernel(const RolloutArgs* __restrict__ inst,
                                                                  const int2* __restrict__ items,
                                                                  int n_items, const float* __restrict__ map,
                                                                  const float* __restrict__ params,
-                                                                 const float* __restrict__ decay) {
+                                                                 const float* __restrict__ decay,
+                                                                 unsigned* __restrict__ queue) {
   __shared__ float sU[2 * kTMax];
   __shared__ float red[kLaneWaves * 2 * kTMax];
   __shared__ float scratch[kLaneWaves];
-  for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
+  for (;;) {
+    const int b = next_work_item(queue, n_items);
+    if (b < 0) break;
     const int2 it = items[b];
     RolloutArgs a = inst[it.x];
     // the shared inputs come from kernel arguments, so that the weights are read with

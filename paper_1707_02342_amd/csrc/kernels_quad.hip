@@ -548,10 +548,11 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   finish_iteration<kQuadBlock, kModelNet, RECEDE, HID>(a, tile, rho, eta, N_lds, red);
 }
 
-// h = 32 fits three waves per SIMD without spilling (168 registers); h = 64 keeps the
-// compiler's allocation.
+// Waves per SIMD: three at h = 32 (168 registers), two at h = 64 (at most 256: the
+// compiler's own choice would hold one wave per SIMD, 274 registers with accumulation
+// registers, and runs the FP32 form about a fifth slower at K = 65536).
 template <int PREC, int HID>
-__global__ __launch_bounds__(kQuadBlock, HID == 32 ? 3 : 1) void rollout_quad_kernel(RolloutArgs a) {
+__global__ __launch_bounds__(kQuadBlock, HID == 32 ? 3 : 2) void rollout_quad_kernel(RolloutArgs a) {
   if (a.iter_dev) a.nk.iter = *a.iter_dev;   // the device counter, advanced by the final merge
   __shared__ float sU[2 * kTMax];
   __shared__ float sE[kQuadWaves * kQuadChunk * 16 * 2 > 2 * kTMax ? kQuadWaves * kQuadChunk * 16 * 2 : 2 * kTMax];
@@ -560,20 +561,24 @@ __global__ __launch_bounds__(kQuadBlock, HID == 32 ? 3 : 1) void rollout_quad_ke
   quad_rollout_tile<PREC, HID>(a, blockIdx.x, sU, sE, sX, red);
 }
 
-// Batched form on quad tiles: block b processes items b, b + gridDim.x, ... (item =
-// (instance, tile of 64 samples)); the shared map, network and decay table come from
-// kernel arguments.  A tile's arithmetic and an instance's merge order do not depend
-// on the grid or the item order.
-__global__ __launch_bounds__(kQuadBlock) void rollout_batch_quad_kernel(const RolloutArgs* __restrict__ inst,
+// Batched form on quad tiles: each block takes items (instance, tile of 64 samples)
+// from the launch's work queue in the order of the items list; the shared map, network
+// and decay table come from kernel arguments.  A tile's arithmetic and an instance's
+// merge order do not depend on the grid or the item order.  Three waves per SIMD (a few
+// registers spill; about a tenth faster on the 512-instance workload than two).
+__global__ __launch_bounds__(kQuadBlock, 3) void rollout_batch_quad_kernel(const RolloutArgs* __restrict__ inst,
                                                                       const int2* __restrict__ items, int n_items,
                                                                       const float* __restrict__ map,
                                                                       const float* __restrict__ params,
-                                                                      const float* __restrict__ decay) {
+                                                                      const float* __restrict__ decay,
+                                                                      unsigned* __restrict__ queue) {
   __shared__ float sU[2 * kTMax];
   __shared__ float sE[kQuadWaves * kQuadChunk * 16 * 2 > 2 * kTMax ? kQuadWaves * kQuadChunk * 16 * 2 : 2 * kTMax];
   __shared__ float sX[kQuadWaves * (kQuadChunk + 1) * 16 * 4];
   __shared__ float red[kQuadWaves * 2 * kTMax + 8];
-  for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
+  for (;;) {
+    const int b = next_work_item(queue, n_items);
+    if (b < 0) break;
     const int2 it = items[b];
     RolloutArgs a = inst[it.x];
     a.map = map;

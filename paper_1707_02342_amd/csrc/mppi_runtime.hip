@@ -68,6 +68,7 @@ constexpr int kNumBasisHost = 25;          // basis functions of the basis-funct
 
 struct PendingTiming {
   hipEvent_t e0, e1;
+  int slot = 0;   // 0: the iteration's rollout launch, 1: the adjoint rollout kernel
 };
 
 }  // namespace
@@ -282,9 +283,9 @@ mppi_status drain_timing(mppi_ctx* c) {
     HIP_TRY(c, hipEventSynchronize(p.e1));
     float a = 0;
     HIP_TRY(c, hipEventElapsedTime(&a, p.e0, p.e1));
-    c->t_ms[0] += a;
-    c->t_cnt[0] += 1;
-    c->t_samples.push_back(a);
+    c->t_ms[p.slot] += a;
+    c->t_cnt[p.slot] += 1;
+    if (p.slot == 0) c->t_samples.push_back(a);
     c->event_pool.push_back(p.e0);
     c->event_pool.push_back(p.e1);
   }
@@ -1162,8 +1163,19 @@ mppi_status mppi_objective(mppi_ctx* c, const float x0[7], uint32_t iter, int32_
     a.ckpt_every = ckpt_every;
     a.G = G;
     a.update_U = 0;
+    PendingTiming pt{};
+    if (c->timing) {
+      pt.e0 = take_event(c);
+      pt.e1 = take_event(c);
+      if (!pt.e0 || !pt.e1) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
+      HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
+    }
     launch_wave(G, T, c->stream, a);
     HIP_TRY(c, hipGetLastError());
+    if (c->timing) {
+      HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
+      c->pending.push_back(pt);
+    }
     float st2[2];
     HIP_TRY(c, hipMemcpyAsync(st2, c->d_stats, sizeof(float) * 2, hipMemcpyDeviceToHost, c->stream));
     if (costs_out) HIP_TRY(c, hipMemcpyAsync(costs_out, c->d_S, sizeof(float) * K, hipMemcpyDeviceToHost, c->stream));
@@ -1213,8 +1225,20 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
     a.nk = r.nk;
     a.nk.iter = c->obj_iter;
     a.cost = r.cost;
+    PendingTiming pt{};
+    pt.slot = 1;
+    if (c->timing) {
+      pt.e0 = take_event(c);
+      pt.e1 = take_event(c);
+      if (!pt.e0 || !pt.e1) return fail(c, MPPI_E_DEVICE, "hipEventCreate failed");
+      HIP_TRY(c, hipEventRecord(pt.e0, c->stream));
+    }
     hipLaunchKernelGGL(adjoint_wave_kernel, dim3(G), dim3(kWaveBlockThreads), adjoint_smem_bytes(T, C), c->stream, a);
     HIP_TRY(c, hipGetLastError());
+    if (c->timing) {
+      HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
+      c->pending.push_back(pt);
+    }
     const int R = std::min(G, kGradChunks);
     hipLaunchKernelGGL(adjoint_reduce_partial_kernel, dim3((unsigned)((stride + 63) / 64), (unsigned)R), dim3(256), 0,
                        c->stream, c->d_gpart, G, (int)stride, R, c->d_gred);
@@ -1237,9 +1261,10 @@ mppi_status mppi_objective_backward(mppi_ctx* c, float* dJdU, float* dJdtheta) {
 // Batched form: many independent MPPI problems in one persistent launch
 // ===========================================================================
 namespace mppi {
-__global__ void rollout_batch_kernel(const RolloutArgs*, const int2*, int, const float*, const float*, const float*);
+__global__ void rollout_batch_kernel(const RolloutArgs*, const int2*, int, const float*, const float*, const float*,
+                                     unsigned*);
 __global__ void rollout_batch_quad_kernel(const RolloutArgs*, const int2*, int, const float*, const float*,
-                                          const float*);
+                                          const float*, unsigned*);
 }
 
 struct mppi_batch {
@@ -1248,7 +1273,7 @@ struct mppi_batch {
   int device = 0;
   hipStream_t stream = nullptr;
   int n = 0;
-  std::vector<int> K, T, G, tile0;       // per instance: samples, horizon, tiles, first item
+  std::vector<int> K, T, G;              // per instance: samples, horizon, tiles of the chosen schedule
   std::vector<size_t> Uoff, Soff, poff, p2off, coff, soff, sgoff;
   float* d_U = nullptr;
   float* d_S = nullptr;
@@ -1265,6 +1290,7 @@ struct mppi_batch {
   float* d_params = nullptr;
   RolloutArgs* d_args = nullptr;
   int2* d_items = nullptr;
+  unsigned* d_queue = nullptr;           // [2]: next work item, blocks that have found the queue empty
   int n_items = 0;
   int H = 0, W = 0;
   float ox = 0, oy = 0, res = 1;
@@ -1272,6 +1298,7 @@ struct mppi_batch {
   int grid = 0, order = 0;
   double tuned_us = 0;
   bool quad = true;                      // tiles of the quad schedule (64 samples) or the lane one (256)
+  bool may_quad = true, may_lane = true; // the schedules the autotuner may choose from
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool own_stream = false;
@@ -1306,7 +1333,7 @@ void batch_free(mppi_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   void* bufs[] = {b->d_U, b->d_S, b->d_part, b->d_part2, b->d_cnt, b->d_stats, b->d_status, b->d_sg,
-                  b->d_decay, b->d_x0, b->d_iter, b->d_map, b->d_params, b->d_args, b->d_items};
+                  b->d_decay, b->d_x0, b->d_iter, b->d_map, b->d_params, b->d_args, b->d_items, b->d_queue};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -1374,8 +1401,25 @@ std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
   return v;
 }
 
+// Tiles of the quad schedule (64 samples, four lanes each) or of the lane schedule (256
+// samples, one lane each): the per-instance tile counts and launch arguments.  The
+// partial rows and counters were allocated for the quad schedule's tile counts, which
+// are never smaller.
+mppi_status batch_set_tiles(mppi_batch* b, bool quad) {
+  const int tile = quad ? kQuadSamplesPerBlock : kLaneBlockHost;
+  b->quad = quad;
+  b->n_items = 0;
+  for (int i = 0; i < b->n; ++i) {
+    b->G[i] = (b->K[i] + tile - 1) / tile;
+    b->n_items += b->G[i];
+  }
+  std::vector<RolloutArgs> args = batch_args(b);
+  BHIP_TRY(b, hipMemcpy(b->d_args, args.data(), sizeof(RolloutArgs) * args.size(), hipMemcpyHostToDevice));
+  return MPPI_OK;
+}
+
 // Work items in the given order: 0 = instance by instance, 1 = longest horizon first
-// (then largest K), so that the long tiles start early in the persistent loop.
+// (then largest K), so that the work queue hands out the long tiles first.
 std::vector<int2> batch_items(const mppi_batch* b, int order) {
   std::vector<int> idx(b->n);
   for (int i = 0; i < b->n; ++i) idx[i] = i;
@@ -1400,17 +1444,20 @@ mppi_status batch_launch(mppi_batch* b, int grid) {
   if (b->quad)
     hipLaunchKernelGGL(rollout_batch_quad_kernel, dim3(grid), dim3(kQuadBlockThreads), 0, b->stream,
                        (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
-                       (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
+                       (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay, b->d_queue);
   else
     hipLaunchKernelGGL(rollout_batch_kernel, dim3(grid), dim3(kLaneBlockHost), 0, b->stream,
                        (const RolloutArgs*)b->d_args, (const int2*)b->d_items, b->n_items,
-                       (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay);
+                       (const float*)b->d_map, (const float*)b->d_params, (const float*)b->d_decay, b->d_queue);
   BHIP_TRY(b, hipGetLastError());
   return MPPI_OK;
 }
 
-// Times each (grid, order) candidate on the real problem, keeps the fastest, and
-// restores U and the iteration counters so tuning leaves no trace in the results.
+// Times each (schedule, order, grid) candidate on the real problem -- the quad
+// schedule's 64-sample tiles or the lane schedule's 256-sample tiles (both when the
+// configuration leaves the schedule to the library), the work order, and the number of
+// persistent blocks -- keeps the fastest, and restores U and the iteration counters so
+// tuning leaves no trace in the results.
 mppi_status batch_autotune(mppi_batch* b) {
   int ncu = 0;
   BHIP_TRY(b, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device));
@@ -1424,9 +1471,15 @@ mppi_status batch_autotune(mppi_batch* b) {
   BHIP_TRY(b, hipEventCreate(&e0));
   BHIP_TRY(b, hipEventCreate(&e1));
   double best = 1e30;
-  int best_grid = b->n_items, best_order = 0;
-  const int grids[] = {ncu, 2 * ncu, 4 * ncu, 8 * ncu, b->n_items};
-  for (int order = 0; order < 2; ++order) {
+  int best_grid = 1, best_order = 0;
+  bool best_quad = b->may_quad;
+  for (int qs = 0; qs < 2; ++qs) {
+   const bool quad = qs == 0;
+   if (quad ? !b->may_quad : !b->may_lane) continue;
+   mppi_status st0 = batch_set_tiles(b, quad);
+   if (st0 != MPPI_OK) return st0;
+   const int grids[] = {ncu, 2 * ncu, 4 * ncu, 8 * ncu, b->n_items};
+   for (int order = 0; order < 2; ++order) {
     std::vector<int2> items = batch_items(b, order);
     BHIP_TRY(b, hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
     for (int gsz : grids) {
@@ -1446,11 +1499,15 @@ mppi_status batch_autotune(mppi_batch* b) {
         best = ms;
         best_grid = grid;
         best_order = order;
+        best_quad = quad;
       }
     }
+   }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  mppi_status st1 = batch_set_tiles(b, best_quad);
+  if (st1 != MPPI_OK) return st1;
   std::vector<int2> items = batch_items(b, best_order);
   BHIP_TRY(b, hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->d_U, U0.data(), sizeof(float) * nU, hipMemcpyHostToDevice));
@@ -1464,8 +1521,6 @@ mppi_status batch_autotune(mppi_batch* b) {
 mppi_status batch_prepare(mppi_batch* b) {
   if (b->ready) return MPPI_OK;
   if (!b->have_map || !b->have_dyn) return bfail(b, MPPI_E_STATE, "set the cost map and the dynamics first");
-  std::vector<RolloutArgs> args = batch_args(b);
-  BHIP_TRY(b, hipMemcpy(b->d_args, args.data(), sizeof(RolloutArgs) * args.size(), hipMemcpyHostToDevice));
   mppi_status st = batch_autotune(b);
   if (st != MPPI_OK) return st;
   // capture the chosen launch once; every iteration replays it (a new cost map or
@@ -1528,7 +1583,9 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
   b->device = device;
   b->stream = (hipStream_t)hip_stream;
   b->n = n;
-  b->quad = cfg->schedule != MPPI_SCHED_LANE;
+  b->may_quad = cfg->schedule != MPPI_SCHED_LANE;
+  b->may_lane = cfg->schedule != MPPI_SCHED_QUAD;
+  b->quad = b->may_quad;
   auto body = [&]() -> mppi_status {
     BHIP_TRY(b, hipSetDevice(device));
     if (!b->stream) {   // graph capture needs a stream other than the null stream
@@ -1538,13 +1595,12 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     size_t u = 0, s = 0, p = 0, p2 = 0, cn = 0, so = 0, sg = 0;
     int items = 0, Tmax = 0;
     for (int i = 0; i < n; ++i) {
-      const int tile = b->quad ? kQuadSamplesPerBlock : kLaneBlockHost;
-      const int g = (K[i] + tile - 1) / tile;
+      // partial rows and counters for the quad schedule's tiles (at least the lane's)
+      const int g = (K[i] + kQuadSamplesPerBlock - 1) / kQuadSamplesPerBlock;
       const int ng = merge_groups(g);
       b->K.push_back(K[i]);
       b->T.push_back(T[i]);
       b->G.push_back(g);
-      b->tile0.push_back(items);
       b->Uoff.push_back(u);
       b->Soff.push_back(s);
       b->poff.push_back(p);
@@ -1581,6 +1637,8 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     BHIP_TRY(b, hipMemset(b->d_iter, 0, sizeof(unsigned) * n));
     BHIP_TRY(b, hipMalloc(&b->d_args, sizeof(RolloutArgs) * n));
     BHIP_TRY(b, hipMalloc(&b->d_items, sizeof(int2) * items));
+    BHIP_TRY(b, hipMalloc(&b->d_queue, sizeof(unsigned) * 2));
+    BHIP_TRY(b, hipMemset(b->d_queue, 0, sizeof(unsigned) * 2));
     std::vector<float> decay(Tmax + 1);
     for (int t = 0; t <= Tmax; ++t) decay[t] = (float)std::pow((double)cost->crash_decay, (double)t);
     BHIP_TRY(b, hipMalloc(&b->d_decay, sizeof(float) * (Tmax + 1)));
@@ -1690,8 +1748,10 @@ mppi_status mppi_batch_get_costs(mppi_batch* b, int32_t i, float* S_out) {
   return MPPI_OK;
 }
 
-mppi_status mppi_batch_get_schedule(mppi_batch* b, int32_t* grid, int32_t* order, double* tuned_us) {
+mppi_status mppi_batch_get_schedule(mppi_batch* b, int32_t* grid, int32_t* order, double* tuned_us,
+                                    int32_t* schedule) {
   if (!b) return MPPI_E_INVAL;
+  if (schedule) *schedule = b->quad ? MPPI_SCHED_QUAD : MPPI_SCHED_LANE;
   if (grid) *grid = b->grid;
   if (order) *order = b->order;
   if (tuned_us) *tuned_us = b->tuned_us;

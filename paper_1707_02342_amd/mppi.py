@@ -113,7 +113,7 @@ def lib() -> C.CDLL:
         L.mppi_batch_iterate.argtypes = [vp, fp]
         L.mppi_batch_get_controls.argtypes = [vp, C.c_int32, fp]
         L.mppi_batch_get_costs.argtypes = [vp, C.c_int32, fp]
-        L.mppi_batch_get_schedule.argtypes = [vp, i32p, i32p, C.POINTER(C.c_double)]
+        L.mppi_batch_get_schedule.argtypes = [vp, i32p, i32p, C.POINTER(C.c_double), i32p]
         L.mppi_batch_synchronize.argtypes = [vp]
         L.mppi_iterate_partial.argtypes = [vp, fp, vp, fp]
         L.mppi_run_receding_device.argtypes = [vp, vp, C.c_int32, vp, vp]
@@ -383,9 +383,10 @@ def mppi_batch_get_costs(b, i: int, K: int):
 
 
 def mppi_batch_get_schedule(b):
-    g, o, t = C.c_int32(), C.c_int32(), C.c_double()
-    _bcheck(b, lib().mppi_batch_get_schedule(b, C.byref(g), C.byref(o), C.byref(t)))
-    return g.value, o.value, t.value
+    """(grid, order, tuned_us, schedule) the autotuner chose."""
+    g, o, t, s = C.c_int32(), C.c_int32(), C.c_double(), C.c_int32()
+    _bcheck(b, lib().mppi_batch_get_schedule(b, C.byref(g), C.byref(o), C.byref(t), C.byref(s)))
+    return g.value, o.value, t.value, s.value
 
 
 def mppi_batch_synchronize(b) -> None:

@@ -223,6 +223,25 @@ def check_costs(orc, op, prob, cmap, params, x0, U0, eps, S, S_ref, impulses, ne
     return S_match, err, info
 
 
+def check_results(orc, prob, cmap, params, x0, U0, S, Ug, it=0, impulses=False, near_cap=1e-3, label="IT",
+                  **extra):
+    """One iteration's GPU costs S and updated controls Ug (from U0, iteration it) against
+    the oracle: the cost bar, the stage-isolated update (the oracle's weights and update
+    on the GPU's S and the same noise) and the end-to-end comparison."""
+    op = orc.OracleProblem(prob, cmap, params)
+    eps = orc.noise(op, it)
+    ref = orc.iterate(op, x0, U0, it)
+    assert ref.status == orc.OK
+    S_match, err, info = check_costs(orc, op, prob, cmap, params, x0, U0, eps, S, ref.S, impulses, near_cap)
+    st2, w, rho, eta = orc.weights(S.astype(np.float64), prob.lam)
+    delta = np.tensordot(w, deltas(prob, eps, U0), axes=(0, 0))
+    Mx = orc.sgf_matrix(prob.T, prob.sg_window, prob.sg_order)
+    U_iso = U0.astype(np.float64) + Mx @ delta
+    e_iso = float(np.abs(Ug - U_iso).max())
+    assert e_iso <= U_ATOL, f"stage-isolated |dU| {e_iso:.3e}"
+    end_to_end(orc, prob, S, S_match, eps, U0, Ug, e_iso, label, it=it, **info, **extra)
+
+
 def check_iteration(M, orc, prob, cmap, params, x0, U0, schedule, it=0, impulses=False, near_cap=1e-3):
     """One iteration against the oracle.  near_cap bounds the fraction of samples whose FP64
     trajectory passes the basis-function model's branch point (and are left out)."""

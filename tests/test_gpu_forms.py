@@ -127,21 +127,23 @@ def test_precision_form_h32_matches_fp32_closely(M, orc):
 # ---------------------------------------------------------------------------
 
 def _batch_vs_single(M, Ks, Ts, x0s, n_iter=3, check=None, schedule=4, base=None):
-    """The batch (tiles of the given schedule; AUTO means quad) against single-problem
-    contexts running the same schedule."""
+    """The batch (tiles of the given schedule; AUTO lets the autotuner choose quad or
+    lane tiles) against single-problem contexts running the schedule it used."""
     base = synth.c2_problem(seed=7) if base is None else base
     cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
     with M.Batch(base, Ks, Ts, cmap, params, schedule=schedule) as b:
         for _ in range(n_iter):
             b.iterate(x0s)
         b.synchronize()
-        grid, order, us = b.schedule()
+        grid, order, us, used = b.schedule()
         idx = range(len(Ks)) if check is None else check
         got = {i: (b.controls(i), b.costs(i)) for i in idx}
-    print(f"batch of {len(Ks)}: autotuned grid {grid}, order {order}, {us:.1f} us/launch", flush=True)
+    print(f"batch of {len(Ks)}: autotuned schedule {used}, grid {grid}, order {order}, {us:.1f} us/launch",
+          flush=True)
+    assert used == schedule or (schedule == 0 and used in (1, 4))
     for i in got:
         p = synth.with_(base, K=Ks[i], T=Ts[i], instance=i)
-        with M.Controller(p, cmap, params, schedule=schedule) as c:
+        with M.Controller(p, cmap, params, schedule=used) as c:
             for _ in range(n_iter):
                 S, _ = c.iterate(x0s[i], want_costs=True)
             U = c.controls()
@@ -182,7 +184,7 @@ def test_batch_full_size_spot_checks(M, orc):
     Ts = [b.T for b in inst]
     x0s = np.stack([b.x0 for b in inst])
     check = [0, 1, 77, 128, 255, 300, 411, 511]
-    got = _batch_vs_single(M, Ks, Ts, x0s, n_iter=2, check=check)
+    got = _batch_vs_single(M, Ks, Ts, x0s, n_iter=2, check=check, schedule=0)
     base = synth.c2_problem(seed=7)
     for i in (0, 411):
         p = synth.with_(base, K=Ks[i], T=Ts[i], instance=i)
@@ -197,6 +199,41 @@ def test_batch_full_size_spot_checks(M, orc):
         rel = np.abs(S[ok] - r1.S[ok]) / np.maximum(np.abs(r1.S[ok]), 1.0)
         print(f"instance {i}: K={Ks[i]} T={Ts[i]} S rel max {rel.max():.2e}", flush=True)
         assert rel.max() <= 1e-4   # second iteration starts from the GPU's own first update
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 4])
+def test_batch_full_size_first_iteration_vs_oracle(M, orc, schedule):
+    """512 instances, K_i in {512..4096}, T_i in {50..150}, one iteration from U = 0:
+    the costs and the updated controls of ten instances (every K_i and T_i among them)
+    against the oracle, to the bars of the single-problem parity tests (costs to 1e-5
+    relative, near-threshold impulses matched to the valid outcomes; U to 1e-5 stage-
+    isolated and end to end)."""
+    inst = synth.c4_instances(512, seed=0)
+    Ks = [b.K for b in inst]
+    Ts = [b.T for b in inst]
+    x0s = np.stack([b.x0 for b in inst])
+    base = synth.c2_problem(seed=7)
+    cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
+    # the first instance of each (K, T) class in the order of the list, up to ten
+    check, seen = [], set()
+    for i, (k, t) in enumerate(zip(Ks, Ts)):
+        if (k, t) not in seen and len(check) < 10:
+            seen.add((k, t))
+            check.append(i)
+    assert len(check) == 10 and {Ks[i] for i in check} == {512, 1024, 2048, 4096} \
+        and {Ts[i] for i in check} == {50, 75, 100, 150}
+    with M.Batch(base, Ks, Ts, cmap, params, schedule=schedule) as b:
+        b.iterate(x0s)
+        b.synchronize()
+        used = b.schedule()[3]
+        got = {i: (b.costs(i), b.controls(i)) for i in check}
+    print(f"schedule {schedule}: tiles of schedule {used}", flush=True)
+    for i in check:
+        p = synth.with_(base, K=Ks[i], T=Ts[i], instance=i)
+        S, Ug = got[i]
+        print(f"instance {i}: K={Ks[i]} T={Ts[i]}", flush=True)
+        pc.check_results(orc, p, cmap, params, x0s[i], np.zeros((Ts[i], 2), np.float32), S, Ug,
+                         impulses=True, label="IT batched", schedule=used, instance=i)
 
 
 def test_batch_new_map_and_network_take_effect(M):

@@ -117,3 +117,26 @@ def test_backward_requires_objective(M):
             c.objective_backward()
         with pytest.raises(M.MppiError):
             c.objective(synth.C1_X0, 0, ckpt_every=17)
+
+
+def test_adjoint_kernel_timing_slot(M):
+    """With timing on, every backward pass records its adjoint rollout kernel in the
+    second timing slot; the iteration slot counts the objective's forward launches, and
+    the gradient is the same as with timing off."""
+    prob = synth.with_(synth.c5_problem(seed=1), K=256, T=40)
+    with M.Controller(prob, synth.ring_map(), synth.mlp_params(32, 1)) as c:
+        c.set_controls(synth.random_controls(40, 1, scale=0.2))
+        c.objective(synth.C1_X0, 0)
+        g_off = c.objective_backward()
+        M.mppi_set_timing(c.ctx, True)
+        for _ in range(3):
+            c.objective(synth.C1_X0, 0)
+            g_on = c.objective_backward()
+        (t0, t1), (n0, n1) = M.mppi_get_timing(c.ctx)
+        samples = M.mppi_get_timing_samples(c.ctx)
+        M.mppi_set_timing(c.ctx, False)
+    assert (n0, n1) == (3, 3)
+    assert t0 > 0.0 and t1 > 0.0
+    assert len(samples) == 3 and abs(float(np.sum(samples)) - t0) <= 1e-3 * t0
+    np.testing.assert_array_equal(g_on[0], g_off[0])
+    np.testing.assert_array_equal(g_on[1], g_off[1])
