@@ -36,7 +36,9 @@ sys.path.insert(0, str(ROOT))
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector (and FP32 matrix) peak
 PEAK_BF16_TFLOPS = 2500.0         # MI355X published dense BF16/FP16 matrix peak
 VALU_LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one FP32 op per lane per cycle
-TRAFFIC_FILE = ROOT / "profiles" / "rollout_wave_k1920_t100_traffic.json"
+TRAFFIC_FILE = ROOT / "profiles" / "rollout_wave_split_k1920_t100_traffic.json"
+TRAFFIC_KERNEL = "rollout_wave_split_kernel<0, true>"   # the multi-step launch of the timed region
+STEPS_PER_LAUNCH = 100                                 # receding steps per launch in the timed region
 # the sources the benchmarked kernel (rollout_wave_kernel<32, 4, 0>) is built from: stored
 # counter readings are used only while these files are unchanged
 KERNEL_SOURCES = ["kernels_wave_split.hip", "kernels_wave.hip", "wave_common.hip.h", "kernels_common.hip.h", "device_common.h",
@@ -127,21 +129,23 @@ def precision_errors(K: int):
 
 
 def stored_traffic():
-    """HBM bytes per launch of the benchmarked kernel from the profiler's FETCH_SIZE and
-    WRITE_SIZE counters (scaled by a copy of known size), or None when the kernel's
-    sources changed after the counters were taken."""
+    """HBM bytes per receding step of the benchmarked kernel (a launch's bytes over its
+    steps) from the profiler's FETCH_SIZE and WRITE_SIZE counters (scaled by a copy of
+    known size), or None when the kernel's sources changed after the counters were
+    taken."""
     if not TRAFFIC_FILE.exists():
         return None
     rec = json.loads(TRAFFIC_FILE.read_text())
     if rec.get("sources_sha256") != kernel_sources_sha256():
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec["traffic_bytes_per_step"]
 
 
 def write_traffic(pmc_dir: str):
     """Reduce four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the benchmark and
     of --calibrate-copy, CSV output under pmc_dir/{FETCH_SIZE,WRITE_SIZE,FETCH_SIZE_copy,
-    WRITE_SIZE_copy}/) to per-launch HBM bytes of the rollout kernel."""
+    WRITE_SIZE_copy}/) to the HBM bytes per receding step of the multi-step rollout
+    kernel (the median over its 100-step launches, divided by 100)."""
     import csv
     import glob
 
@@ -150,7 +154,7 @@ def write_traffic(pmc_dir: str):
         vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(f)) if match(r["Kernel_Name"])]
         return float(np.median(vals)), len(vals)
 
-    is_roll = lambda n: "rollout_wave_kernel<32, 4, 0>" in n
+    is_roll = lambda n: TRAFFIC_KERNEL in n
     is_copy = lambda n: "copyBuffer" in n or "elementwise" in n
     fetch, nf = per_dispatch("FETCH_SIZE", is_roll)
     write, nw = per_dispatch("WRITE_SIZE", is_roll)
@@ -161,12 +165,15 @@ def write_traffic(pmc_dir: str):
     kib = COPY_BYTES / 1024.0
     fetch_scale = kib / largest("FETCH_SIZE_copy")
     write_scale = kib / largest("WRITE_SIZE_copy")
-    rec = {"kernel": "rollout_wave_kernel<32, 4, 0>",
-           "workload": "K=1920, T=100, 6-32-32-4 network, 2048x2048 map (bench.py default)",
+    per_launch = (fetch * fetch_scale + write * write_scale) * 1024.0
+    rec = {"kernel": TRAFFIC_KERNEL,
+           "workload": "K=1920, T=100, 6-32-32-4 network, 2048x2048 map (bench.py default), "
+                       f"{STEPS_PER_LAUNCH} receding steps per launch",
            "sources_sha256": kernel_sources_sha256(),
            "fetch_size_kib_per_launch_median": fetch, "fetch_dispatches": nf, "fetch_scale": fetch_scale,
            "write_size_kib_per_launch_median": write, "write_dispatches": nw, "write_scale": write_scale,
-           "traffic_bytes_per_launch": (fetch * fetch_scale + write * write_scale) * 1024.0,
+           "traffic_bytes_per_launch": per_launch, "steps_per_launch": STEPS_PER_LAUNCH,
+           "traffic_bytes_per_step": per_launch / STEPS_PER_LAUNCH,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/FETCH_SIZE -o c2 -- "
                         "python3 bench.py --steps 100 --warmup 5 --no-cpu --no-forms --latency-iters 5",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/WRITE_SIZE -o c2 -- "
@@ -484,7 +491,7 @@ def main():
         single=True one mppi_step_device launch per step."""
         done, blk = 0, 0
         while done < n_steps:
-            n = min(100, n_steps - done)
+            n = min(STEPS_PER_LAUNCH, n_steps - done)
             ctx, ptr = ctls[blk % 10].ctx, xdev[blk % 10].data_ptr()
             if single:
                 for _ in range(n):
@@ -614,7 +621,8 @@ def main():
                        "host_graph_p99": float(np.percentile(lat_graph, 99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "rollout (one receding step)", "flop_per_launch": flop},
+                     "kernel": "rollout_wave_split_kernel<kModelNet, true>, per receding step of its "
+                               f"{STEPS_PER_LAUNCH}-step launches", "flop_per_step": flop},
     }
     for cc in ctls:
         cc.close()
