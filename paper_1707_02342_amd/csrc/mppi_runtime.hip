@@ -113,6 +113,7 @@ struct mppi_ctx {
   int obj_ckpt_every = 0;
   uint32_t obj_iter = 0;
   int part_cap = 0;          // partial rows allocated
+  int ngrp_cap = 0;          // group rows allocated (arrival counters: ngrp_cap + 1)
   uint32_t iter = 0;
   int schedule = MPPI_SCHED_LANE;
   float sig[2] = {0, 0};
@@ -598,8 +599,13 @@ mppi_status read_status(mppi_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (st == MPPI_E_NONFINITE) return fail(c, MPPI_E_NONFINITE, "no sample had a finite cost; U unchanged");
-  if (st == kStatusTimeoutHost)
+  if (st == kStatusTimeoutHost) {
+    // the launch left mid-step: clear its arrival counters and the status for the next launch
+    (void)hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (c->ngrp_cap + 1), c->stream);
+    (void)hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream);
+    (void)hipStreamSynchronize(c->stream);
     return fail(c, MPPI_E_DEVICE, "a multi-step receding launch gave up waiting for a step signal");
+  }
   return MPPI_OK;
 }
 
@@ -717,6 +723,7 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
                                    merge_groups(blocks_for(c, MPPI_SCHED_WIDE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_QUAD))});
     HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)ngrp_cap * (2 + 2 * T)));
+    c->ngrp_cap = ngrp_cap;
     HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(unsigned) * (ngrp_cap + 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (ngrp_cap + 1), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_stats, sizeof(float) * (2 + 2 * T)));
