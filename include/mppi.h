@@ -227,8 +227,11 @@ mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
  * registers and wait for each step's update on the device; otherwise one launch per
  * step.  Either way the results equal n_iter calls of mppi_step_device bit for bit.  The
  * status of the last step (or MPPI_E_DEVICE if a block of the multi-step launch gave up
- * waiting for a step) is read by the next synchronising call.  INVAL: x_dev NULL or
- * n_iter outside [0, 1<<20]. */
+ * waiting for a step: U, the plant state and the histories are then partial, and the
+ * arrival counters are cleared for the next launch) is read by the next synchronising
+ * call.  A block gives up after 1 << 22 polls of the step signal (~0.1 s), or after the
+ * number of polls in the environment variable MPPI_STEP_SPIN_LIMIT at the time of the
+ * call (for tests of this path).  INVAL: x_dev NULL or n_iter outside [0, 1<<20]. */
 mppi_status mppi_run_receding_device(mppi_ctx* ctx, float* x_dev, int32_t n_iter, float* u_hist_dev,
                                      float* x_hist_dev);
 

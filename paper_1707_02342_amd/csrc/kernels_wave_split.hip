@@ -123,9 +123,9 @@ __device__ __forceinline__ void draw_block_noise(const RolloutArgs& a, uint32_t 
 }
 
 // Bounded wait of thread 0 for a device-scope counter written by another block (the
-// multi-step launch's step signal); false when the bound ran out.
-__device__ __forceinline__ bool wait_signal(const unsigned* f, unsigned target) {
-  for (int i = 0; i < (1 << 22); ++i) {
+// multi-step launch's step signal): at most `limit` polls; false when they ran out.
+__device__ __forceinline__ bool wait_signal(const unsigned* f, unsigned target, unsigned limit) {
+  for (unsigned i = 0; i < limit; ++i) {
     const unsigned v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)(v - target) >= 0) return true;
     __builtin_amdgcn_s_sleep(4);
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
     float* const x_copy = (as.x_copy && MULTI) ? as.x_copy + kStateDim * step : as.x_copy;
     // ---- this step's U and plant state (after the previous step's signal) -------------
     if (step > 0) {
-      if (tid == 0 && !wait_signal(as.step_flag, as.step_base + (unsigned)step)) {
+      if (tid == 0 && !wait_signal(as.step_flag, as.step_base + (unsigned)step,
+                                   as.spin_limit ? as.spin_limit : (1u << 22))) {
         s_abort = 1u;
         __hip_atomic_store(as.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -569,6 +570,8 @@ mppi_status enqueue_receding_steps(mppi_ctx* c, float* x_dev, int n, float* u_hi
   a.x_copy = x_hist;
   a.n_steps = n;
   a.step_flag = c->d_step;
+  // polls of a step-signal wait (0: the kernel's default), for tests of the give-up path
+  if (const char* e = std::getenv("MPPI_STEP_SPIN_LIMIT")) a.spin_limit = (unsigned)std::strtoul(e, nullptr, 10);
   a.step_base = c->step_count;
   PendingTiming pt{};
   if (c->timing) {

@@ -104,6 +104,7 @@ struct RolloutArgs {
   int n_steps;
   unsigned* step_flag;
   unsigned step_base;
+  unsigned spin_limit;   // polls of a step-signal wait before the launch gives up (0: 1 << 22)
 };
 
 constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)

@@ -150,3 +150,36 @@ def test_run_receding_device_rejects_bad_arguments(env):
         with pytest.raises(M.MppiError):
             M.mppi_run_receding_device(c.ctx, x.data_ptr(), -1)
         M.mppi_run_receding_device(c.ctx, x.data_ptr(), 0)
+
+
+def test_multi_step_give_up_then_recover(env, monkeypatch):
+    """A multi-step launch whose blocks may poll the step signal only once gives up (the
+    bound of the kernel's own wait, set from the host): the next synchronising call reports
+    MPPI_E_DEVICE.  The same context, reset to the start state, then runs a normal launch
+    that equals a fresh context's: the counters the aborted launch left were cleared."""
+    M, torch = env
+    prob = synth.c2_problem(seed=6)
+    cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
+    with M.Controller(prob, cmap, params) as c:
+        x = torch.tensor(synth.C2_X0, device="cuda")
+        monkeypatch.setenv("MPPI_STEP_SPIN_LIMIT", "1")
+        M.mppi_run_receding_device(c.ctx, x.data_ptr(), 8)
+        monkeypatch.delenv("MPPI_STEP_SPIN_LIMIT")
+        with pytest.raises(M.MppiError):
+            M.mppi_get_controls(c.ctx, prob.T)
+        c.set_controls(np.zeros((prob.T, 2), np.float32))
+        c.iteration = 0
+        got = _run_once(M, torch, c, prob, 8)
+    with M.Controller(prob, cmap, params) as fresh:
+        ref = _run_once(M, torch, fresh, prob, 8)
+    for a_, b_ in zip(got, ref):
+        np.testing.assert_array_equal(a_, b_)
+
+
+def _run_once(M, torch, c, prob, n):
+    x = torch.tensor(synth.C2_X0, device="cuda")
+    M.mppi_run_receding_device(c.ctx, x.data_ptr(), n)
+    torch.cuda.synchronize()
+    U, st = M.mppi_get_controls(c.ctx, prob.T)
+    assert st == M.MPPI_OK
+    return U, x.cpu().numpy()
