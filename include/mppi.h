@@ -222,16 +222,17 @@ mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
  * updated in place by the noise-free plant step), shifts U, writes u_0 to u_hist_dev[2i..]
  * and the new state to x_hist_dev[7i..] (device, [n_iter][2] and [n_iter][7], either may
  * be NULL).  Enqueued, no synchronisation, no allocation.  With the wave schedule's split
- * form (T <= 128, at most one block of 8 samples per compute unit) and Algorithm 2's
- * weights, all n_iter steps run in ONE cooperative launch whose blocks keep the network in
- * registers and wait for each step's update on the device; otherwise one launch per
+ * form (T <= 128; its blocks of 8 samples plus one merging block per group of about
+ * sqrt(K/8) of them fit one block per compute unit: K <= 1920 on 256 CUs) and Algorithm
+ * 2's weights, all n_iter steps run in ONE cooperative launch whose blocks keep the
+ * network in registers and run every step's update themselves; otherwise one launch per
  * step.  Either way the results equal n_iter calls of mppi_step_device bit for bit.  The
  * status of the last step (or MPPI_E_DEVICE if a block of the multi-step launch gave up
- * waiting for a step: U, the plant state and the histories are then partial, and the
- * arrival counters are cleared for the next launch) is read by the next synchronising
- * call.  A block gives up after 1 << 22 polls of the step signal (~0.1 s), or after the
- * number of polls in the environment variable MPPI_STEP_SPIN_LIMIT at the time of the
- * call (for tests of this path).  INVAL: x_dev NULL or n_iter outside [0, 1<<20]. */
+ * waiting for another: U, the plant state and the histories are then partial; the next
+ * launch is not affected) is read by the next synchronising call.  A block gives up after
+ * 1 << 20 polls of a wait (about half a second), or after the number of polls in the
+ * environment variable MPPI_STEP_SPIN_LIMIT at the time of the call (for tests of this
+ * path).  INVAL: x_dev NULL or n_iter outside [0, 1<<20]. */
 mppi_status mppi_run_receding_device(mppi_ctx* ctx, float* x_dev, int32_t n_iter, float* u_hist_dev,
                                      float* x_hist_dev);
 

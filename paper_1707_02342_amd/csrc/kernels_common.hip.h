@@ -252,9 +252,14 @@ __device__ __forceinline__ float lane_value(float v, int src) {
 // a kernel that serves one model compiles only that model's plant step.  HC: the
 // network width when the calling kernel fixes it (0: a.hidden), so that every sum is
 // unrolled and its weight loads issued together (the arithmetic is the same).
+// writer = false: a block that runs the step only for itself (the multi-step launch's
+// replicated final stage) writes nothing to global memory.  u_next, x_next (LDS,
+// nullable): where the shifted U ([2T]) and the new plant state ([7]) also go; x_next is
+// written by wave 0 and visible to the block after its next barrier.
 template <int NT, int kOut, int MODEL, int HC = 0>
 __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float x_lane, float* lds,
-                              const float* params, float* u0_out, float* x_copy) {
+                              const float* params, float* u0_out, float* x_copy, bool writer = true,
+                              float* u_next = nullptr, float* x_next = nullptr) {
   constexpr bool kMayBasis = MODEL != kModelNet;
   constexpr bool kMayNet = MODEL != kModelBasis;
   __shared__ float s_x[kStateDim];
@@ -270,8 +275,12 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
   __syncthreads();
   // U, u_0 and the plant state are written through to the device's point of coherence:
   // in a multi-step launch the next step's blocks read them right after the step's signal
-  for (int o = tid; o < T2; o += NT) store_through(a.Uout + o, (o + 2 < T2) ? lds[o + 2] : 0.0f);
-  if (tid < 2 && u0_out) store_through(u0_out + tid, lds[tid]);
+  for (int o = tid; o < T2; o += NT) {
+    const float v = (o + 2 < T2) ? lds[o + 2] : 0.0f;
+    if (writer) store_through(a.Uout + o, v);
+    if (u_next) u_next[o] = v;
+  }
+  if (writer && tid < 2 && u0_out) store_through(u0_out + tid, lds[tid]);
   if (tid >= 64) return;
   const int lane = tid;
   float x[kStateDim];
@@ -332,8 +341,11 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
 #pragma unroll
   for (int i = 1; i < kStateDim; ++i) yl = lane == i ? y[i] : yl;
   if (lane < kStateDim) {
-    store_through(const_cast<float*>(a.x0_dev) + lane, yl);
-    if (x_copy) store_through(x_copy + lane, yl);
+    if (writer) {
+      store_through(const_cast<float*>(a.x0_dev) + lane, yl);
+      if (x_copy) store_through(x_copy + lane, yl);
+    }
+    if (x_next) x_next[lane] = yl;
   }
 }
 
@@ -370,10 +382,31 @@ struct FinalStage {
     }
   }
 
+  // The same inputs for a block that already holds them: U in LDS (u_lds[2T]) and the
+  // plant state in registers (x[7], the same in every thread).
+  __device__ __forceinline__ void prefetch_local(const RolloutArgs& a, const float* u_lds, const float (&x)[kStateDim]) {
+    const int tid = threadIdx.x, T2 = 2 * a.T, w = a.sg_window;
+    if constexpr (RECEDE) {
+      x_old = x[0];
+#pragma unroll
+      for (int i = 1; i < kStateDim; ++i) x_old = tid == i ? x[i] : x_old;
+    }
+#pragma unroll
+    for (int j = 0; j < kOut; ++j) {
+      const int o = tid + j * NT;
+      u_old[j] = (o < T2) ? u_lds[o] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < kTapReg; ++i)
+        taps[j][i] = (o < T2 && w > 1 && w <= kTapReg && i < w) ? a.sg[(size_t)(o >> 1) * w + i] : 0.0f;
+    }
+  }
+
   // iter: the counter word of this iteration (the device counter becomes iter + 1);
-  // u0_out, x_copy: the receding step's outputs (nullable)
+  // u0_out, x_copy: the receding step's outputs (nullable).  writer, u_next, x_next: see
+  // receding_step (writer = false also leaves the statistics, the status and the counter).
   __device__ __forceinline__ void apply(const RolloutArgs& a, float* lds, bool fin, float scale, const float* params,
-                                        float stat0, float stat1, uint32_t iter, float* u0_out, float* x_copy) {
+                                        float stat0, float stat1, uint32_t iter, float* u0_out, float* x_copy,
+                                        bool writer = true, float* u_next = nullptr, float* x_next = nullptr) {
     const int tid = threadIdx.x, T2 = 2 * a.T, w = a.sg_window;
 #pragma unroll
     for (int j = 0; j < kOut; ++j) {
@@ -381,7 +414,7 @@ struct FinalStage {
       if (o < T2) {
         const float d = lds[o] * scale;
         lds[o] = d;
-        a.stats[2 + o] = d;
+        if (writer) a.stats[2 + o] = d;
       }
     }
     __syncthreads();
@@ -408,17 +441,18 @@ struct FinalStage {
           }
         }
         u_new[j] = u_old[j] + upd;
-        if (!a.recede) store_through(a.Uout + o, u_new[j]);
+        if (writer && !a.recede) store_through(a.Uout + o, u_new[j]);
       }
     }
-    if (tid == 0) {
+    if (writer && tid == 0) {
       *a.status = fin ? 0 : kStatusNonfinite;
       a.stats[0] = stat0;
       a.stats[1] = stat1;
       if (a.iter_dev) *a.iter_dev = iter + 1u;
     }
     if constexpr (RECEDE) {
-      if (a.recede) receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds, params, u0_out, x_copy);
+      if (a.recede)
+        receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds, params, u0_out, x_copy, writer, u_next, x_next);
     }
   }
 

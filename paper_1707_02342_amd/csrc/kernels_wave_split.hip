@@ -32,15 +32,24 @@
 // compensation terms and of the kinematic scans.
 //
 // Multi-step receding launch (the MULTI instances with n_steps > 1, launched
-// cooperatively so that every block is resident): the block loops over the steps,
-// keeping the chain's network constants in registers and the model's parameters (for the
-// plant step of the final stage) in LDS.  The
-// block that runs step s's final stage (update, shift, plant step; every store written
-// through) waits for those stores and then writes the step signal; every block draws step
-// s + 1's noise (which does not depend on U) while the merge completes, then waits for
-// the signal (bounded: a block that gives up sets the status and leaves the loop) and
-// reads the new U and plant state with device-coherent loads.  The results equal those
-// of one launch per step bit for bit.
+// cooperatively so that every block is resident): G rollout blocks and one merger block
+// per merge group.  A rollout block loops over the steps, keeping the chain's network
+// constants in registers and the model's parameters (for the plant step) in LDS.  At the
+// end of step s it writes its row through, waits for those stores, and writes the step
+// into its arrival word; it draws step s + 1's noise (which does not depend on U) and
+// waits until its copy of the group words shows step s for every group; it then merges
+// the group rows and runs the final stage itself -- normalisation, smoothing, update,
+// shift, plant step -- so that step s + 1 starts from U and the plant state in its own
+// LDS with no further memory round trip.  Every block computes the same values in the
+// same order; block 0 alone writes U, the plant state, the statistics and the histories.
+// A merger block waits until its group's arrival words show step s, merges the group's
+// rows into the group row and writes the step into every copy of its group word.  Every
+// signal is a word written through after the data it announces has reached the device's
+// point of coherence, and read with device-coherent loads; every word holds a step
+// number that only grows, so none is reset.  (Counting arrivals with atomic adds and
+// polling the count took ~4.5 us to be seen by the poller, against ~0.6 us for a written
+// word.)  Every wait is bounded: a block that gives up sets the status and leaves.  The
+// results equal those of one launch per step bit for bit.
 #include "wave_common.hip.h"
 
 namespace mppi {
@@ -122,13 +131,22 @@ __device__ __forceinline__ void draw_block_noise(const RolloutArgs& a, uint32_t 
   }
 }
 
-// Bounded wait of thread 0 for a device-scope counter written by another block (the
-// multi-step launch's step signal): at most `limit` polls; false when they ran out.
-__device__ __forceinline__ bool wait_signal(const unsigned* f, unsigned target, unsigned limit) {
+// A word that blocks of a multi-step launch poll, written through to the device's point
+// of coherence.
+__device__ __forceinline__ void store_word(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of wave 0 (all 64 lanes call it) until each of the n words w[0..n)
+// (n <= 64), written by other blocks with store_word, holds `target` or a later step
+// (wrapping comparison): at most `limit` polls; false when they ran out.  The same in
+// every lane.
+__device__ __forceinline__ bool wait_words(const unsigned* w, int n, unsigned target, unsigned limit) {
+  const int lane = threadIdx.x & 63;
   for (unsigned i = 0; i < limit; ++i) {
-    const unsigned v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((int)(v - target) >= 0) return true;
-    __builtin_amdgcn_s_sleep(4);
+    const unsigned v = lane < n ? __hip_atomic_load(w + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : target;
+    if (__all((int)(v - target) >= 0)) return true;
+    __builtin_amdgcn_s_sleep(1);
   }
   return false;
 }
@@ -139,14 +157,65 @@ __device__ __forceinline__ bool wait_signal(const unsigned* f, unsigned target, 
 // argument segment (the kernel's one explicit argument sits at its start) through a
 // pointer the compiler cannot see through: otherwise every field would be held in
 // scalar registers over all steps, and the surplus spilled to vector lanes and read back
-// in every phase of every step.
+// in every phase of every step.  Valid only in code inlined into the kernel: in a function
+// the kernel calls, the kernel argument segment pointer reads as null.
 __device__ __forceinline__ const RolloutArgs& reload_args() {
   uint64_t v = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
   asm volatile("" : "+s"(v));
   return *(const RolloutArgs*)(const __attribute__((address_space(4))) RolloutArgs*)v;
 }
 
-constexpr int kStatusTimeout = 6;   // a multi-step launch gave up waiting for a step signal
+constexpr int kStatusTimeout = 6;   // a multi-step launch gave up waiting for another block
+
+// Polls of one wait in a multi-step launch before the block gives up (0 in the arguments:
+// 1 << 20, about half a second).
+__device__ __forceinline__ unsigned spin_limit(const RolloutArgs& a) { return a.spin_limit ? a.spin_limit : (1u << 20); }
+
+// Multi-step launch, merger block of group grp = blockIdx.x - G: at every step, waits
+// (bounded) until the arrival word of each of the group's n_in rollout blocks shows the
+// step, merges their rows into this step's group row (two buffers, alternating by step: a
+// slow block may still read step s's group rows while step s + 1's are written), and
+// writes the step into every copy of the group's signal word.  Inlined into the kernel,
+// since it reads the arguments with reload_args().
+__device__ __forceinline__ void merge_group_rows(int n_steps, float* lds) {
+  __shared__ float s_small[2 * kMergeChunk];
+  __shared__ unsigned s_stop;
+  const int tid = threadIdx.x;
+  for (int step = 0; step < n_steps; ++step) {
+    const RolloutArgs& as = reload_args();
+    const int T2 = 2 * as.T, stride = 2 + T2;
+    const int gsz = merge_group_size(as.G);
+    const int ngrp = (as.G + gsz - 1) / gsz;
+    const int grp = (int)blockIdx.x - as.G;
+    const int n_in = min(gsz, as.G - grp * gsz);
+    const unsigned target = as.step_base + (unsigned)step + 1u;
+    if (tid < 64) {
+      const bool ok = wait_words(as.sync + kArriveOffset + grp * gsz, n_in, target, spin_limit(as));
+      if (tid == 0) {
+        if (!ok) __hip_atomic_store(as.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_stop = ok ? 0u : 1u;
+      }
+    }
+    __syncthreads();
+    if (s_stop) return;
+    float rho, eta;
+    merge_rows<kSplitBlock>(as.part + (size_t)grp * gsz * stride, n_in, stride, T2, as.inv_lambda, lds, s_small,
+                            rho, eta);
+    __syncthreads();
+    if (tid < 64) {
+      // the group row is written through and its stores complete before the signal words
+      float* dst = as.part2 + ((size_t)(step & 1) * ngrp + grp) * stride;
+      if (tid == 0) {
+        store_through(dst, rho);
+        store_through(dst + 1, eta);
+      }
+      for (int o = tid; o < T2; o += 64) store_through(dst + 2 + o, lds[o]);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (tid < kSignalCopies) store_word(as.sync + tid * kSignalSpacing + grp, target);
+    }
+    __syncthreads();
+  }
+}
 
 template <int MODEL, bool MULTI>
 __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(RolloutArgs a) {
@@ -154,6 +223,8 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   constexpr bool kNet = MODEL == kModelNet;
   extern __shared__ float smem[];
   __shared__ unsigned s_abort;
+  __shared__ float s_xn[kStateDim];                  // multi-step: the next step's plant state
+  __shared__ float s_small[2 * kMergeChunk];         // multi-step: the merge's row scales
   const int T = a.T;
   const int T4 = (T + 4) & ~3;
   const int eStride = (2 * T + 3) & ~3;
@@ -172,6 +243,12 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   // longer read) and the merge's working row (the states are no longer read)
   float* N_lds = kNet ? sV : sB;
   float* lds = sX;
+  if constexpr (MULTI) {
+    if ((int)blockIdx.x >= a.G) {   // a merger block (blocks G .. G + ngrp - 1)
+      merge_group_rows(n_steps, sX);
+      return;
+    }
+  }
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -256,21 +333,13 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
     const uint32_t iter = iter0 + (uint32_t)step;
     float* const u0_out = (as.u0_out && MULTI) ? as.u0_out + 2 * step : as.u0_out;
     float* const x_copy = (as.x_copy && MULTI) ? as.x_copy + kStateDim * step : as.x_copy;
-    // ---- this step's U and plant state (after the previous step's signal) -------------
-    if (step > 0) {
-      if (tid == 0 && !wait_signal(as.step_flag, as.step_base + (unsigned)step,
-                                   as.spin_limit ? as.spin_limit : (1u << 22))) {
-        s_abort = 1u;
-        __hip_atomic_store(as.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __syncthreads();
-      if (s_abort) break;
-    }
-    for (int i = tid; i < 2 * T; i += kSplitBlock) sU[i] = step > 0 ? load_through(as.U + i) : as.U[i];
+    // ---- this step's U and plant state: from global memory at the first step, from the
+    // block's own final stage of the previous step after that ------------------------------
+    if (step == 0)
+      for (int i = tid; i < 2 * T; i += kSplitBlock) sU[i] = as.U[i];
     float x0v[kStateDim];
 #pragma unroll
-    for (int i = 0; i < kStateDim; ++i)
-      x0v[i] = step > 0 ? load_through(as.x0_dev + i) : (as.x0_dev ? as.x0_dev[i] : as.x0[i]);
+    for (int i = 0; i < kStateDim; ++i) x0v[i] = step > 0 ? s_xn[i] : (as.x0_dev ? as.x0_dev[i] : as.x0[i]);
     __syncthreads();
     // the controls of every sample and step; the state entry 0 of every sample
     for (int i = tid; i < kWaveSlots * T; i += kSplitBlock) {
@@ -518,19 +587,49 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
       }
       N_lds[o] = n;
     }
-    const StepTarget target{iter, u0_out, x_copy};
-    const bool ran_final = finish_iteration<kSplitBlock, MODEL, true, HID>(as, blockIdx.x, rho, eta, N_lds, lds,
-                                                                           MULTI ? sP : as.params, &target);
-    if (step + 1 < n_steps) {
-      if (ran_final) {
-        // every write-through store of the final stage has completed before the signal
+    if constexpr (MULTI) {
+      // ---- multi-step launch: the row goes to the group's merger block; this block then
+      // merges the group rows and runs the final stage itself ---------------------------
+      const int T2 = 2 * T, stride = 2 + T2;
+      const int gsz = merge_group_size(as.G);
+      const int ngrp = (as.G + gsz - 1) / gsz;
+      const unsigned target = as.step_base + (unsigned)step + 1u;
+      FinalStage<kSplitBlock, MODEL, true, HID> fs;
+      fs.prefetch_local(as, sU, x0v);
+      __syncthreads();   // the block's N row is complete
+      if (tid < 64) {
+        // the row is written through and its stores complete before the arrival word
+        float* dst = as.part + (size_t)blockIdx.x * stride;
+        if (tid == 0) {
+          store_through(dst, rho);
+          store_through(dst + 1, eta);
+        }
+        for (int o = tid; o < T2; o += 64) store_through(dst + 2 + o, N_lds[o]);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(as.step_flag, as.step_base + (unsigned)(step + 1), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) store_word(as.sync + kArriveOffset + blockIdx.x, target);
       }
-      // the next step's noise does not depend on its U: drawn while the merge completes
-      draw_block_noise(as, iter0 + (uint32_t)(step + 1), kb, T, eStride, sE);
+      // the next step's noise does not depend on its U: drawn while the merges complete
+      if (step + 1 < n_steps) draw_block_noise(as, iter + 1u, kb, T, eStride, sE);
+      if (tid < 64) {
+        const bool ok = wait_words(as.sync + (blockIdx.x % kSignalCopies) * kSignalSpacing, ngrp, target,
+                                   spin_limit(as));
+        if (tid == 0 && !ok) {
+          s_abort = 1u;
+          __hip_atomic_store(as.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      __syncthreads();
+      if (s_abort) break;
+      float rho_m, eta_m;
+      merge_rows<kSplitBlock>(as.part2 + (size_t)(step & 1) * ngrp * stride, ngrp, stride, T2, as.inv_lambda, lds,
+                              s_small, rho_m, eta_m);
+      const bool fin = (rho_m < kInf) && (eta_m > 0.0f);
+      fs.apply(as, lds, fin, fin ? 1.0f / eta_m : 0.0f, sP, rho_m, fin ? eta_m : 0.0f, iter, u0_out, x_copy,
+               blockIdx.x == 0, sU, s_xn);
+      __syncthreads();   // the next step's U (sU) and plant state (s_xn)
+    } else {
+      const StepTarget target{iter, u0_out, x_copy};
+      finish_iteration<kSplitBlock, MODEL, true, HID>(as, blockIdx.x, rho, eta, N_lds, lds, as.params, &target);
     }
   }
 }

@@ -107,8 +107,8 @@ struct mppi_ctx {
   float* d_gout = nullptr;    // reduced gradient [1412 + 2T]
   float* d_gred = nullptr;    // chunk sums of the gradient partials [16][1412 + 2T]
   unsigned* d_iter = nullptr; // the iteration counter (Philox counter word 3), advanced on the device
-  unsigned* d_step = nullptr; // step signal of multi-step receding launches (monotonic)
-  unsigned step_count = 0;    // its value after the launches enqueued so far
+  unsigned* d_sync = nullptr; // signal words of multi-step receding launches ([kSyncWords(part_cap)])
+  unsigned step_count = 0;    // steps of the multi-step launches enqueued so far (their signal base)
   int ckpt_cap = 0;           // n_ckpt the checkpoint buffer holds
   bool objective_ready = false;
   int obj_ckpt_every = 0;
@@ -402,7 +402,7 @@ RolloutArgs config_args(const mppi_config& g, const mppi_cost& cost, int H, int 
   a.nk.k_base = g.k_base;
   a.row_out = nullptr;
   a.n_steps = 1;
-  a.step_flag = nullptr;
+  a.sync = nullptr;
   a.step_base = 0;
   a.hidden = hidden;
   a.model = model;
@@ -534,11 +534,15 @@ mppi_status enqueue_iteration(mppi_ctx* c, const float* x0_host, const float* x0
 }
 
 // Whether n receding steps can run as one multi-step launch of the split wave kernel:
-// the wave schedule's split form (T <= 128, one block per compute unit), Algorithm 2's
-// weights, and a device that launches cooperatively (every block resident at once).
+// the wave schedule's split form (T <= 128) with its rollout blocks and one merger block
+// per merge group fitting one block per compute unit (K <= 1920 on 256 CUs), Algorithm
+// 2's weights, and a device that launches cooperatively (every block resident at once).
 bool multi_step_ok(const mppi_ctx* c) {
   if (c->schedule != MPPI_SCHED_WAVE || c->cfg.weighting != MPPI_WEIGHTS_IT || c->cfg.T > kWaveSplitMaxT) return false;
-  if (blocks_for(c, MPPI_SCHED_WAVE) > device_cus()) return false;
+  // the rollout blocks and one merger block per merge group, one block per compute unit;
+  // a group's arrival words and the group words are each polled by one wave's lanes
+  const int G = blocks_for(c, MPPI_SCHED_WAVE);
+  if (G + merge_groups(G) > device_cus() || merge_group_size(G) > 64 || merge_groups(G) > 64) return false;
   int coop = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess) return false;
   return coop != 0;
@@ -562,6 +566,8 @@ mppi_status enqueue_receding_steps(mppi_ctx* c, float* x_dev, int n, float* u_hi
   }
   const int G = blocks_for(c, MPPI_SCHED_WAVE);
   if (G > c->part_cap) return fail(c, MPPI_E_INVAL, "internal: %d partial blocks > capacity %d", G, c->part_cap);
+  const int ngrp = merge_groups(G);
+  if (ngrp > c->ngrp_cap) return fail(c, MPPI_E_INVAL, "internal: %d merge groups > capacity %d", ngrp, c->ngrp_cap);
   c->objective_ready = false;
   RolloutArgs a = rollout_args(c, nullptr, x_dev);
   a.G = G;
@@ -569,7 +575,7 @@ mppi_status enqueue_receding_steps(mppi_ctx* c, float* x_dev, int n, float* u_hi
   a.u0_out = u_hist;
   a.x_copy = x_hist;
   a.n_steps = n;
-  a.step_flag = c->d_step;
+  a.sync = c->d_sync;
   // polls of a step-signal wait (0: the kernel's default), for tests of the give-up path
   if (const char* e = std::getenv("MPPI_STEP_SPIN_LIMIT")) a.spin_limit = (unsigned)std::strtoul(e, nullptr, 10);
   a.step_base = c->step_count;
@@ -584,18 +590,18 @@ mppi_status enqueue_receding_steps(mppi_ctx* c, float* x_dev, int n, float* u_hi
   const void* fn = c->model == kModelBasis
                        ? reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelBasis, true>)
                        : reinterpret_cast<const void*>(&rollout_wave_split_kernel<kModelNet, true>);
-  HIP_TRY(c, hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWaveSplitBlockThreads), args,
+  HIP_TRY(c, hipLaunchCooperativeKernel(fn, dim3(G + ngrp), dim3(kWaveSplitBlockThreads), args,
                                         (unsigned)wave_split_smem_bytes(c->cfg.T, c->model), c->stream));
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(pt.e1, c->stream));
     c->pending.push_back(pt);
   }
-  c->step_count += (unsigned)(n - 1);   // the launch signals steps 1 .. n-1
+  c->step_count += (unsigned)n;
   c->iter += (uint32_t)n;
   return MPPI_OK;
 }
 
-constexpr int kStatusTimeoutHost = 6;   // the split kernel's status when a step signal never came
+constexpr int kStatusTimeoutHost = 6;   // the split kernel's status when a wait of a multi-step launch gave up
 
 mppi_status read_status(mppi_ctx* c) {
   int st = 0;
@@ -603,11 +609,11 @@ mppi_status read_status(mppi_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (st == MPPI_E_NONFINITE) return fail(c, MPPI_E_NONFINITE, "no sample had a finite cost; U unchanged");
   if (st == kStatusTimeoutHost) {
-    // the launch left mid-step: clear its arrival counters and the status for the next launch
-    (void)hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (c->ngrp_cap + 1), c->stream);
+    // the launch left mid-step; the signal words it wrote hold steps below every later
+    // launch's, so only the status is cleared for the next launch
     (void)hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream);
     (void)hipStreamSynchronize(c->stream);
-    return fail(c, MPPI_E_DEVICE, "a multi-step receding launch gave up waiting for a step signal");
+    return fail(c, MPPI_E_DEVICE, "a multi-step receding launch gave up waiting for another block");
   }
   return MPPI_OK;
 }
@@ -670,8 +676,8 @@ void free_all(mppi_ctx* c) {
   c->d_cnt = nullptr;
   if (c->d_iter) (void)hipFree(c->d_iter);
   c->d_iter = nullptr;
-  if (c->d_step) (void)hipFree(c->d_step);
-  c->d_step = nullptr;
+  if (c->d_sync) (void)hipFree(c->d_sync);
+  c->d_sync = nullptr;
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
@@ -725,7 +731,8 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
                                    merge_groups(blocks_for(c, MPPI_SCHED_WAVE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_WIDE)),
                                    merge_groups(blocks_for(c, MPPI_SCHED_QUAD))});
-    HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)ngrp_cap * (2 + 2 * T)));
+    // two sets of group rows: a multi-step receding launch alternates them by step
+    HIP_TRY(c, hipMalloc(&c->d_part2, sizeof(float) * (size_t)2 * ngrp_cap * (2 + 2 * T)));
     c->ngrp_cap = ngrp_cap;
     HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(unsigned) * (ngrp_cap + 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * (ngrp_cap + 1), c->stream));
@@ -735,8 +742,8 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_cost* cost, int devic
     HIP_TRY(c, hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_iter, sizeof(unsigned)));
     HIP_TRY(c, hipMemsetAsync(c->d_iter, 0, sizeof(unsigned), c->stream));
-    HIP_TRY(c, hipMalloc(&c->d_step, sizeof(unsigned)));
-    HIP_TRY(c, hipMemsetAsync(c->d_step, 0, sizeof(unsigned), c->stream));
+    HIP_TRY(c, hipMalloc(&c->d_sync, sizeof(unsigned) * kSyncWords(c->part_cap)));
+    HIP_TRY(c, hipMemsetAsync(c->d_sync, 0, sizeof(unsigned) * kSyncWords(c->part_cap), c->stream));
     HIP_TRY(c, hipMalloc(&c->d_x, sizeof(float) * kStateDim));
     HIP_TRY(c, hipMalloc(&c->d_u0, sizeof(float) * 2));
     std::vector<float> decay(T + 1);

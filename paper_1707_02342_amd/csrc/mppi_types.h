@@ -8,6 +8,20 @@
 namespace mppi {
 
 constexpr int kStateDim = 7;
+
+// Multi-step receding launch: the words its blocks signal each other through (a device
+// buffer of kSyncWords(G) words per context, zero when the context is created).  Every
+// word holds a step number, step_base + s + 1 for step s of a launch, which grows over
+// the context's multi-step launches, so no word is ever reset.
+//   copy c < kSignalCopies of group word g: the last step whose group row g is out (the
+//     copies kSignalSpacing words, 4 KiB, apart; rollout block b polls copy
+//     b mod kSignalCopies, so that not every block polls the same memory);
+//   arrival word b (at kArriveOffset + b, b < G): the last step whose row of rollout
+//     block b is out.
+constexpr int kSignalCopies = 16;
+constexpr int kSignalSpacing = 1024;
+constexpr int kArriveOffset = kSignalCopies * kSignalSpacing;
+constexpr inline int kSyncWords(int G) { return kArriveOffset + G; }
 constexpr int kCtrlDim = 2;
 constexpr int kNetIn = 6;
 constexpr int kNetOut = 4;
@@ -59,13 +73,13 @@ struct RolloutArgs {
   const float* x0_dev;     // nullable: read x0 from here instead of x0[]
   float* S;                // [K] trajectory costs
   float* part;             // [G][2 + 2T] per-block (rho_g, eta_g, N_g[T][2])
-  float* part2;            // [merge_groups(G)][2 + 2T] per-group merges
+  float* part2;            // [2][merge_groups(G)][2 + 2T] per-group merges (the second set: multi-step)
   unsigned* cnt;           // [merge_groups(G) + 1] arrival counters, zero between launches
   const float* sg;         // [T][sg_window] smoothing rows (null when window == 1)
   float* Uout;             // [T][2], updated in place by the last block
   float* stats;            // [2 + 2T]: rho, eta~, Delta[T][2]
   int* status;             // 0 or MPPI_E_NONFINITE for this iteration
-  int G;                   // blocks of this launch
+  int G;                   // rollout blocks of this launch
   int sg_window;
   int update_U;            // 0: weights and Delta only (objective evaluation)
   unsigned* iter_dev;      // nullable: the iteration counter (read at the start of the launch in place
@@ -96,15 +110,15 @@ struct RolloutArgs {
   // (rho, eta, N[T][2]) here ([2 + 2T]) and leaves U, the statistics and the smoothing
   // to a later merge of every shard's row (merge_update_kernel).
   float* row_out;
-  // Multi-step receding launch (the split wave kernel, launched cooperatively): n_steps
-  // receding steps in one launch (0 or 1: one step).  After the final stage of step s the
-  // merging block writes *step_flag = step_base + s + 1 and every block waits for that
-  // value before step s + 1; u0_out and x_copy then point to [n_steps][2] and
-  // [n_steps][7] histories (step s writes entry s).
+  // Multi-step receding launch (the split wave kernel, launched cooperatively with G
+  // rollout blocks and merge_groups(G) merger blocks): n_steps receding steps in one launch
+  // (0 or 1: one step), step s signalled as step_base + s + 1 in the words of sync
+  // ([kSyncWords(G)], see kSignalCopies); u0_out and x_copy then point to [n_steps][2]
+  // and [n_steps][7] histories (step s writes entry s).
   int n_steps;
-  unsigned* step_flag;
+  unsigned* sync;
   unsigned step_base;
-  unsigned spin_limit;   // polls of a step-signal wait before the launch gives up (0: 1 << 22)
+  unsigned spin_limit;   // polls of one wait before the launch gives up (0: 1 << 20)
 };
 
 constexpr int kCkptStride = 8;   // floats per checkpointed state (7 + pad)

@@ -71,7 +71,7 @@ def test_multi_step_equals_single_steps_paper_shaped(env, n):
 
 def test_multi_step_then_single_steps(env):
     """A multi-step launch of 20 steps, then 5 single steps, equals 25 single steps (the
-    iteration counter and the step signal's bookkeeping carry over)."""
+    iteration counter and the signal words' step numbering carry over)."""
     M, torch = env
     prob = synth.c2_problem(seed=3)
     cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
@@ -153,10 +153,11 @@ def test_run_receding_device_rejects_bad_arguments(env):
 
 
 def test_multi_step_give_up_then_recover(env, monkeypatch):
-    """A multi-step launch whose blocks may poll the step signal only once gives up (the
-    bound of the kernel's own wait, set from the host): the next synchronising call reports
-    MPPI_E_DEVICE.  The same context, reset to the start state, then runs a normal launch
-    that equals a fresh context's: the counters the aborted launch left were cleared."""
+    """A multi-step launch whose blocks may poll another block's signal only once gives up
+    (the bound of the kernel's own wait, set from the host): the next synchronising call
+    reports MPPI_E_DEVICE.  The same context, reset to the start state, then runs a normal
+    launch that equals a fresh context's: the signal words the aborted launch left hold
+    steps below the next launch's."""
     M, torch = env
     prob = synth.c2_problem(seed=6)
     cmap, params = synth.ellipse_map(), synth.mlp_params(32, 0)
