@@ -152,8 +152,11 @@ mppi_status mppi_set_costmap(mppi_ctx* ctx, const float* map, int32_t H, int32_t
 /* Dynamics network f(x_d, g(v)) (Section VI-B-2).  dims = {6, h, h, 4} with
  * h = 32 or 64.  params = W1[h][6], b1[h], W2[h][h], b2[h], W3[4][h], b3[4]
  * (row-major [out][in]); inputs (roll, v_x, v_y, theta_dot, steer, throttle),
- * outputs d/dt of (roll, v_x, v_y, theta_dot).  Copied.  INVAL: other dims,
- * non-finite parameters, or a precision the given h does not support. */
+ * outputs d/dt of (roll, v_x, v_y, theta_dot).  Copied.  When the schedule resolves to
+ * QUAD this allocates, once per context, 8 bytes per sample and step (ceil(K/64) 64 T
+ * pairs of floats): the rollouts keep their noise there for the weighted perturbation
+ * sum instead of drawing it twice.  INVAL: other dims, non-finite parameters, or a
+ * precision the given h does not support.  NOMEM: that buffer could not be allocated. */
 mppi_status mppi_set_dynamics(mppi_ctx* ctx, const int32_t dims[4], const float* params);
 
 /* Basis-function dynamics model (Section VI-B-1 and the appendix), in place of the
@@ -354,7 +357,9 @@ mppi_status mppi_iterate_noalloc(const mppi_config* cfg, const mppi_cost* cost, 
  * cfg->K and cfg->T are ignored.  The first iterate times several launch shapes
  * (grid size and work order) on the real problem and keeps the fastest; U and the
  * counters are restored afterwards and every shape gives the same results.  With a
- * NULL stream the batch creates its own (graph capture needs a non-null stream).
+ * NULL stream the batch creates its own (graph capture needs a non-null stream).  With
+ * quad tiles allowed the batch also holds 8 bytes per sample and step of every instance
+ * (ceil(K_i/64) 64 T_i pairs of floats) for the tiles' noise.
  * INVAL: n outside [1, 65536], an instance's K/T invalid (as in mppi_config), a
  * precision other than FP32, or a schedule other than AUTO, LANE or QUAD. */
 typedef struct mppi_batch mppi_batch;

@@ -295,6 +295,8 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   const bool zm = k >= a.K_imp;   // exploration sample: v = eps, delta = eps - u
   float* wE = sE + wv * (kQuadChunk * 16 * 2);          // [chunk step][sample][2]
   float* wX = sX + wv * ((kQuadChunk + 1) * 16 * 4);    // [chunk step 0..16][sample][4]
+  // the stored noise of the wave's 16 samples ([T][16][2]), or null
+  float* wS = a.eps_store ? a.eps_store + ((size_t)tile * kQuadWaves + wv) * (size_t)T * 32 : nullptr;
 
   for (int i = threadIdx.x; i < 2 * T; i += kQuadBlock) sU[i] = a.U[i];
   __syncthreads();
@@ -325,6 +327,8 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
       draw_eps((uint32_t)ts, (uint32_t)(tile * kQuadSamples + wv * 16 + (p & 15)), a.nk, e0, e1);
       wE[p * 2] = e0;
       wE[p * 2 + 1] = e1;
+      // stored at (step, sample): the lane that reads it back below is this lane
+      if (wS && cs + (p >> 4) < T) *reinterpret_cast<float2*>(wS + (size_t)(cs * 16 + p) * 2) = make_float2(e0, e1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -528,17 +532,13 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
 #pragma unroll
   for (int m = 8; m >= 1; m >>= 1) esum += __shfl_xor(esum, m, 16);
   if (lane == 0) scratch[4 + wv] = esum;
-  // N[t] = sum_k e_k delta_{k,t}: lane group g regenerates steps t = g, g + 4, ... of its
-  // sample and the 16 samples of a row are summed with shuffles
-  for (int t0 = 0; t0 < T; t0 += 4) {
-    const int t = t0 + g;
-    float e0 = 0.0f, e1 = 0.0f;
-    if (t < T && valid) {
-      draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
-      if (zm) {
-        e0 -= sU[2 * t];
-        e1 -= sU[2 * t + 1];
-      }
+  // N[t] = sum_k e_k delta_{k,t}: lane group g takes steps t = g, g + 4, ... of its sample
+  // (the stored noise, written by this lane in the chunk draws, or drawn again) and the 16
+  // samples of a row are summed with shuffles
+  auto add_step = [&](int t, float e0, float e1) {
+    if (zm && t < T && valid) {
+      e0 -= sU[2 * t];
+      e1 -= sU[2 * t + 1];
     }
     float n0 = e * e0, n1 = e * e1;
 #pragma unroll
@@ -549,6 +549,27 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
     if (j == 0 && t < T) {
       red[wv * 2 * kTMax + 2 * t] = n0;
       red[wv * 2 * kTMax + 2 * t + 1] = n1;
+    }
+  };
+  if (wS) {
+    for (int t0 = 0; t0 < T; t0 += 16) {   // four loads in flight
+      float2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + 4 * q + g;
+        v[q] = (t < T && valid) ? *reinterpret_cast<const float2*>(wS + (size_t)(t * 16 + j) * 2)
+                                : make_float2(0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (t0 + 4 * q < T) add_step(t0 + 4 * q + g, v[q].x, v[q].y);
+    }
+  } else {
+    for (int t0 = 0; t0 < T; t0 += 4) {
+      const int t = t0 + g;
+      float e0 = 0.0f, e1 = 0.0f;
+      if (t < T && valid) draw_eps((uint32_t)t, (uint32_t)k, a.nk, e0, e1);
+      add_step(t, e0, e1);
     }
   }
   __syncthreads();

@@ -91,6 +91,7 @@ struct mppi_ctx {
   float* d_decay = nullptr;
   float* d_S = nullptr;
   float* d_D = nullptr;      // Algorithm 3 only: [K][T][2] delta rows
+  float* d_eps = nullptr;    // quad schedule: the noise of a launch's tiles [G][4][T][16][2]
   float* d_part = nullptr;
   float* d_part2 = nullptr;
   unsigned* d_cnt = nullptr;
@@ -401,6 +402,7 @@ RolloutArgs config_args(const mppi_config& g, const mppi_cost& cost, int H, int 
   a.nk.sig1 = std::sqrt(g.sigma2[1]);
   a.nk.k_base = g.k_base;
   a.row_out = nullptr;
+  a.eps_store = nullptr;
   a.n_steps = 1;
   a.sync = nullptr;
   a.step_base = 0;
@@ -441,6 +443,7 @@ RolloutArgs rollout_args(const mppi_ctx* c, const float* x0_host, const float* x
   a.S = c->d_S;
   a.part = c->d_part;
   a.D = c->d_D;
+  a.eps_store = c->d_eps;
   a.nk.iter = c->iter;
   a.iter_dev = c->d_iter;
   a.nk.sig0 = c->sig[0];
@@ -663,7 +666,7 @@ mppi_status upload_params(mppi_ctx* c, const float* params, size_t n) {
 }
 
 void free_all(mppi_ctx* c) {
-  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_D, &c->d_part, &c->d_part2,
+  float** bufs[] = {&c->d_U, &c->d_map, &c->d_params, &c->d_decay, &c->d_S, &c->d_D, &c->d_eps, &c->d_part, &c->d_part2,
                     &c->d_stats, &c->d_sg, &c->d_x, &c->d_u0, &c->d_hist_u, &c->d_hist_x,
                     &c->d_ckpt, &c->d_gpart, &c->d_gout, &c->d_gred};
   for (float** b : bufs) {
@@ -846,6 +849,9 @@ mppi_status mppi_set_dynamics(mppi_ctx* c, const int32_t dims[4], const float* p
     c->hidden = h;
     c->model = kModelNet;
     c->schedule = auto_schedule_net(c->cfg, h);
+    if (c->schedule == MPPI_SCHED_QUAD && !c->d_eps)   // the quad tiles' noise, 8 bytes per sample and step
+      HIP_TRY(c, hipMalloc(&c->d_eps, sizeof(float) * 2 * (size_t)blocks_for(c, MPPI_SCHED_QUAD) *
+                                          kQuadSamplesPerBlock * c->cfg.T));
     return MPPI_OK;
   });
 }
@@ -1291,11 +1297,12 @@ struct mppi_batch {
   hipStream_t stream = nullptr;
   int n = 0;
   std::vector<int> K, T, G;              // per instance: samples, horizon, tiles of the chosen schedule
-  std::vector<size_t> Uoff, Soff, poff, p2off, coff, soff, sgoff;
+  std::vector<size_t> Uoff, Soff, poff, p2off, coff, soff, sgoff, eoff;
   float* d_U = nullptr;
   float* d_S = nullptr;
   float* d_part = nullptr;
   float* d_part2 = nullptr;
+  float* d_eps = nullptr;                // quad tiles' noise, per instance [tiles][4][T][16][2]
   unsigned* d_cnt = nullptr;
   float* d_stats = nullptr;
   int* d_status = nullptr;
@@ -1349,7 +1356,7 @@ void batch_free(mppi_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  void* bufs[] = {b->d_U, b->d_S, b->d_part, b->d_part2, b->d_cnt, b->d_stats, b->d_status, b->d_sg,
+  void* bufs[] = {b->d_U, b->d_S, b->d_eps, b->d_part, b->d_part2, b->d_cnt, b->d_stats, b->d_status, b->d_sg,
                   b->d_decay, b->d_x0, b->d_iter, b->d_map, b->d_params, b->d_args, b->d_items, b->d_queue};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
@@ -1368,6 +1375,7 @@ std::vector<RolloutArgs> batch_args(const mppi_batch* b) {
     a.S = b->d_S + b->Soff[i];
     a.part = b->d_part + b->poff[i];
     a.part2 = b->d_part2 + b->p2off[i];
+    a.eps_store = b->d_eps ? b->d_eps + b->eoff[i] : nullptr;
     a.cnt = b->d_cnt + b->coff[i];
     a.sg = b->cfg.sg_window > 1 ? b->d_sg + b->sgoff[i] : nullptr;
     a.Uout = b->d_U + b->Uoff[i];
@@ -1609,7 +1617,7 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
       BHIP_TRY(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
       b->own_stream = true;
     }
-    size_t u = 0, s = 0, p = 0, p2 = 0, cn = 0, so = 0, sg = 0;
+    size_t u = 0, s = 0, p = 0, p2 = 0, cn = 0, so = 0, sg = 0, ep = 0;
     int items = 0, Tmax = 0;
     for (int i = 0; i < n; ++i) {
       // partial rows and counters for the quad schedule's tiles (at least the lane's)
@@ -1625,7 +1633,9 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
       b->coff.push_back(cn);
       b->soff.push_back(so);
       b->sgoff.push_back(sg);
+      b->eoff.push_back(ep);
       u += 2 * (size_t)T[i];
+      ep += 2 * (size_t)g * kQuadSamplesPerBlock * T[i];
       s += K[i];
       p += (size_t)g * (2 + 2 * T[i]);
       p2 += (size_t)ng * (2 + 2 * T[i]);
@@ -1642,6 +1652,7 @@ mppi_status mppi_batch_create(const mppi_config* cfg, const mppi_cost* cost, int
     BHIP_TRY(b, hipMalloc(&b->d_S, sizeof(float) * s));
     BHIP_TRY(b, hipMalloc(&b->d_part, sizeof(float) * p));
     BHIP_TRY(b, hipMalloc(&b->d_part2, sizeof(float) * p2));
+    if (b->may_quad) BHIP_TRY(b, hipMalloc(&b->d_eps, sizeof(float) * ep));   // 8 bytes per sample and step
     BHIP_TRY(b, hipMalloc(&b->d_cnt, sizeof(unsigned) * cn));
     BHIP_TRY(b, hipMemset(b->d_cnt, 0, sizeof(unsigned) * cn));
     BHIP_TRY(b, hipMalloc(&b->d_stats, sizeof(float) * so));

@@ -92,6 +92,10 @@ struct RolloutArgs {
                            // are exploration samples around zero (v = eps)
   int cem_zeta;            // 0: Algorithm 2's weights; > 0: Algorithm 3 with this many elite samples
   float* D;                // Algorithm 3 only: [K][T][2] delta rows (v - u) of every sample
+  // Quad schedule (nullable): the launch's noise, [tiles][4 waves][T][16][2], written as
+  // the rollout draws it and read back by the weighted perturbation sum in place of a
+  // second draw (the same values); null: drawn again.
+  float* eps_store;
   float dt;
   float inv_lambda;
   float gcs0, gcs1;        // gamma / Sigma_ii (control-cost weights)
