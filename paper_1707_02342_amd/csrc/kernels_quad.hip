@@ -316,39 +316,49 @@ __device__ void quad_rollout_tile(const RolloutArgs& a, int tile, float* sU, flo
   bool ok = true;
   wX[j * 4 + g] = xd.hi;             // chunk row 0 = the state entering the chunk
 
+  // noise pair p = lane + 64 q of the chunk starting at step c0 -> (step c0 + p / 16,
+  // sample p % 16): drawn, then kept in the chunk's rows and (stored noise) at (step,
+  // sample), where the lane that reads it back below is this lane
+  auto draw_pair = [&](int c0, int q, float& e0, float& e1) {
+    const int p = lane + 64 * q;
+    draw_eps((uint32_t)min(c0 + (p >> 4), T - 1), (uint32_t)(tile * kQuadSamples + wv * 16 + (p & 15)), a.nk, e0, e1);
+  };
+  auto keep_pair = [&](int c0, int q, float e0, float e1) {
+    const int p = lane + 64 * q;
+    wE[p * 2] = e0;
+    wE[p * 2 + 1] = e1;
+    if (wS && c0 + (p >> 4) < T) *reinterpret_cast<float2*>(wS + (size_t)(c0 * 16 + p) * 2) = make_float2(e0, e1);
+  };
+  // step s of the chunk starting at cs (the serial chain); lane groups 0 and 1 take control
+  // component g, 2 and 3 the constant inputs (both read by every lane and selected: no
+  // branch in the step, which with this code's shape kept the compiler from spilling
+  // registers of the h = 32 kernels)
+  auto chain_step = [&](int cs, int s) {
+    const int t = cs + s;
+    const int gc = g & 1;
+    const float e = wE[(s * 16 + j) * 2 + gc];
+    const float u = sU[2 * t + gc];
+    const float vc = fminf(fmaxf(zm ? e : u + e, lo_g), hi_g);
+    const float b1v = g < 2 ? vc : (g == 2 ? 1.0f : 0.0f);
+    if (g < 2) Sacc.add(gcs_g * (u * (zm ? e - u : e)));   // the control-cost term, one component per lane
+    const float f = net.eval(xd.hi, b1v);
+    xd.add(a.dt * f);
+    wX[((s + 1) * 16 + j) * 4 + g] = xd.value();
+  };
+
   for (int cs = 0; cs < T; cs += kQuadChunk) {
     const int n = min(kQuadChunk, T - cs);
-    // noise of the chunk: pair p = lane + 64 q -> (step cs + p / 16, sample p % 16)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int p = lane + 64 * q;
-      const int ts = min(cs + (p >> 4), T - 1);
       float e0, e1;
-      draw_eps((uint32_t)ts, (uint32_t)(tile * kQuadSamples + wv * 16 + (p & 15)), a.nk, e0, e1);
-      wE[p * 2] = e0;
-      wE[p * 2 + 1] = e1;
-      // stored at (step, sample): the lane that reads it back below is this lane
-      if (wS && cs + (p >> 4) < T) *reinterpret_cast<float2*>(wS + (size_t)(cs * 16 + p) * 2) = make_float2(e0, e1);
+      draw_pair(cs, q, e0, e1);
+      keep_pair(cs, q, e0, e1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the serial chain over the chunk
-    for (int s = 0; s < n; ++s) {
-      const int t = cs + s;
-      float b1v;
-      if (g < 2) {
-        const float e = wE[(s * 16 + j) * 2 + g];
-        const float u = sU[2 * t + g];
-        b1v = fminf(fmaxf(zm ? e : u + e, lo_g), hi_g);
-        Sacc.add(gcs_g * (u * (zm ? e - u : e)));   // the control-cost term, one component per lane
-      } else {
-        b1v = g == 2 ? 1.0f : 0.0f;
-      }
-      const float f = net.eval(xd.hi, b1v);
-      xd.add(a.dt * f);
-      wX[((s + 1) * 16 + j) * 4 + g] = xd.value();
-    }
+    for (int s = 0; s < n; ++s) chain_step(cs, s);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
