@@ -233,7 +233,7 @@ mppi_status mppi_step_device(mppi_ctx* ctx, float* x_dev, float* u0_out_dev);
  * status of the last step (or MPPI_E_DEVICE if a block of the multi-step launch gave up
  * waiting for another: U, the plant state and the histories are then partial; the next
  * launch is not affected) is read by the next synchronising call.  A block gives up after
- * 1 << 20 polls of a wait (about half a second), or after the number of polls in the
+ * 1 << 20 polls of a wait (of the order of a second), or after the number of polls in the
  * environment variable MPPI_STEP_SPIN_LIMIT at the time of the call (for tests of this
  * path).  INVAL: x_dev NULL or n_iter outside [0, 1<<20]. */
 mppi_status mppi_run_receding_device(mppi_ctx* ctx, float* x_dev, int32_t n_iter, float* u_hist_dev,

@@ -172,7 +172,7 @@ __device__ __forceinline__ const RolloutArgs& reload_args() {
 constexpr int kStatusTimeout = 6;   // a multi-step launch gave up waiting for another block
 
 // Polls of one wait in a multi-step launch before the block gives up (0 in the arguments:
-// 1 << 20, about half a second).
+// 1 << 20: each poll waits for its load, so of the order of a second).
 __device__ __forceinline__ unsigned spin_limit(const RolloutArgs& a) { return a.spin_limit ? a.spin_limit : (1u << 20); }
 
 // Multi-step launch, merger block of group grp = blockIdx.x - G: at every step, waits
