@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision/batched/differentiation forms")
     ap.add_argument("--precision-only", action="store_true",
                     help="only time the precision form (K=16384 and 65536), print its JSON and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched form (512 instances; for profiling its kernel)")
     ap.add_argument("--differentiation-only", action="store_true",
                     help="only time the differentiation form (K=4096, T=100), print its JSON and exit")
     ap.add_argument("--write-traffic", metavar="PMC_DIR",
@@ -322,6 +324,33 @@ def measure_differentiation(M, stream, iters: int = 30):
             "workload": "K=4096, T=100, checkpoints every 10 steps, 1612 gradient entries"}
 
 
+def measure_batched(M, iters: int = 30):
+    """The batched form: 512 instances (K_i in 512..4096, T_i in 50..150) advanced by one
+    replayed graph launch per iteration (the first iterate autotunes and captures it)."""
+    import synth
+    inst = synth.c4_instances(512, seed=0)
+    Ks, Ts = [b.K for b in inst], [b.T for b in inst]
+    x0s = np.stack([b.x0 for b in inst])
+    with M.Batch(synth.c2_problem(seed=0), Ks, Ts, synth.ellipse_map(), synth.mlp_params(32, 0)) as b:
+        b.iterate(x0s)              # autotunes and captures the launch
+        b.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            b.iterate(x0s)
+        b.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+        grid, order, tuned_us, tiles = b.schedule()
+    work = float(sum(k * t for k, t in zip(Ks, Ts)))
+    bt = work * NET_FLOP_PER_STEP[32] / (ms * 1e-3) / 1e12
+    return {"ms_per_iteration": ms, "steps_per_s": work / (ms * 1e-3), "instances": len(Ks),
+            "roofline": {"bound": "mfma", "achieved": bt, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": bt / PEAK_FP32_TFLOPS},
+            "grid": grid, "order": order,
+            "tiles": {1: "lane schedule, 256 samples per tile",
+                      4: "quad schedule, 64 samples per tile"}.get(tiles, tiles),
+            "workload": "512 instances, K_i in {512..4096}, T_i in {50..150}, 2048x2048 map"}
+
+
 def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
     """The three added forms on their own workloads (synthetic, seeded):
     precision: K=16384 and K=65536, T=100, 6-64-64-4 network, one iteration in FP32 and
@@ -339,27 +368,7 @@ def measure_forms(M, stream, iters: int = 30, laps_per_setting: int = 3):
     import synth
     out = {"precision": measure_precision(M, stream, iters)}
 
-    inst = synth.c4_instances(512, seed=0)
-    Ks, Ts = [b.K for b in inst], [b.T for b in inst]
-    x0s = np.stack([b.x0 for b in inst])
-    with M.Batch(synth.c2_problem(seed=0), Ks, Ts, synth.ellipse_map(), synth.mlp_params(32, 0)) as b:
-        b.iterate(x0s)              # autotunes and captures the launch
-        b.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(iters):
-            b.iterate(x0s)
-        b.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / iters
-        grid, order, tuned_us, tiles = b.schedule()
-    work = float(sum(k * t for k, t in zip(Ks, Ts)))
-    bt = work * NET_FLOP_PER_STEP[32] / (ms * 1e-3) / 1e12
-    out["batched"] = {"ms_per_iteration": ms, "steps_per_s": work / (ms * 1e-3), "instances": len(Ks),
-                      "roofline": {"bound": "mfma", "achieved": bt, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                                   "frac": bt / PEAK_FP32_TFLOPS},
-                      "grid": grid, "order": order,
-                      "tiles": {1: "lane schedule, 256 samples per tile",
-                                4: "quad schedule, 64 samples per tile"}.get(tiles, tiles),
-                      "workload": "512 instances, K_i in {512..4096}, T_i in {50..150}, 2048x2048 map"}
+    out["batched"] = measure_batched(M, iters)
 
     out["differentiation"] = measure_differentiation(M, stream, iters)
 
@@ -460,6 +469,9 @@ def main():
         return
     if args.differentiation_only:
         print(json.dumps({"differentiation": measure_differentiation(M, stream, iters=10)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": measure_batched(M, iters=30)}), flush=True)
         return
     cmap = synth.ellipse_map()
     prob = synth.c2_problem(seed=0)
