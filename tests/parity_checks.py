@@ -33,7 +33,7 @@ U_ATOL = 1e-5
 NEAR_WINDOW = 1e-4
 
 # Per-check records (one dict per checked iteration), written out by the test session
-# (conftest.py) to the file named by MPPI_PARITY_RECORD, or gpurun_out/parity_records.jsonl.
+# (conftest.py) to the file named by MPPI_PARITY_RECORD, or test_records/parity_records.jsonl.
 RECORDS = []
 CURRENT_TEST = {"id": None}
 
@@ -80,12 +80,12 @@ def summary_markdown(records) -> str:
 
 
 def write_records(root: Path):
-    """Appends this session's records to MPPI_PARITY_RECORD (default
-    gpurun_out/parity_records.jsonl) and writes beside it their per-test summary
+    """Appends this session's records to MPPI_PARITY_RECORD (default: the repository's
+    test_records/parity_records.jsonl) and writes beside it their per-test summary
     (parity_summary.md) and the precision form's records (precision_errors.jsonl)."""
     if not RECORDS:
         return None
-    path = Path(os.environ.get("MPPI_PARITY_RECORD", root / "gpurun_out" / "parity_records.jsonl"))
+    path = Path(os.environ.get("MPPI_PARITY_RECORD", root / "test_records" / "parity_records.jsonl"))
     path.parent.mkdir(parents=True, exist_ok=True)
     with open(path, "a") as f:
         for r in RECORDS:
