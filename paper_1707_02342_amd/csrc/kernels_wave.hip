@@ -264,9 +264,10 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       // layer 1
       float acc1 = __builtin_fmaf(w1[4], vc0, bb1);
       acc1 = __builtin_fmaf(w1[5], vc1, acc1);
-      // one asm block, so that no wait states are inserted between the four
+      // one asm block, so that no wait states are inserted between the four; the DPP
+      // source xcur was written before this step's two fmas of acc1 above, the two wait
+      // states a DPP read of a VALU result needs
       asm volatile(
-          "s_nop 1\n\t"
           "v_fmac_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0] row_mask:0xf bank_mask:0xf\n\t"
           "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1] row_mask:0xf bank_mask:0xf\n\t"
           "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2] row_mask:0xf bank_mask:0xf\n\t"
@@ -280,9 +281,9 @@ __global__ __launch_bounds__(kWaveBlock) void rollout_wave_kernel(RolloutArgs a)
       float P2 = wP[1] * dpp_f<kRowRor + 1>(h1);
       float Q2 = wQ[1] * dpp_f<kRowRor + 1>(h1);
       // rotations 2..15 in one asm block (no wait states inserted between them); the
-      // DPP source h1 was written two instructions before (the nop covers the hazard)
+      // DPP source h1 was written before the four instructions forming P, Q, P2 and Q2,
+      // which are the block's inputs: more than the two wait states a DPP read needs
       asm volatile(
-          "s_nop 1\n\t"
           "v_fmac_f32_dpp %0, %4, %5 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
           "v_fmac_f32_dpp %1, %4, %6 row_ror:2 row_mask:0xf bank_mask:0xf\n\t"
           "v_fmac_f32_dpp %2, %4, %7 row_ror:3 row_mask:0xf bank_mask:0xf\n\t"
