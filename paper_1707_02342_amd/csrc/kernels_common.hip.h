@@ -237,6 +237,24 @@ __device__ __forceinline__ float lane_value(float v, int src) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
 }
 
+// The plant layout of the network's parameter vector (width H, a multiple of 4), the same
+// number of floats: W1[H][6] and b1[H] in place, W2 as [H/4][H][4] (neuron n's weights
+// 4q .. 4q+3 in one 16-byte word, the words of consecutive neurons consecutive), b2[H]
+// in place, W3 as [H/4][4][4] (the same for the 4 outputs), b3[4] in place.  Returns
+// where element i of the parameter vector (W1[H][6], b1, W2[H][H], b2, W3[4][H], b3) goes.
+__host__ __device__ constexpr int plant_layout_index(int i, int H) {
+  const int oW2 = 7 * H, oW3 = 8 * H + H * H;
+  if (i >= oW2 && i < oW2 + H * H) {
+    const int n = (i - oW2) / H, j = (i - oW2) % H;
+    return oW2 + (((j >> 2) * H + n) << 2) + (j & 3);
+  }
+  if (i >= oW3 && i < oW3 + 4 * H) {
+    const int o = (i - oW3) / H, j = (i - oW3) % H;
+    return oW3 + (((j >> 2) * 4 + o) << 2) + (j & 3);
+  }
+  return i;   // W1 and the biases keep their places
+}
+
 // The receding-horizon part of a control step (Algorithm 1's last block and the
 // plant), run by the final merge after the update: U is shifted (u_0 out,
 // u_{t-1} <- u_t, u_{T-1} <- (0, 0)), and the plant state in x0_dev advances by one
@@ -256,7 +274,9 @@ __device__ __forceinline__ float lane_value(float v, int src) {
 // replicated final stage) writes nothing to global memory.  u_next, x_next (LDS,
 // nullable): where the shifted U ([2T]) and the new plant state ([7]) also go; x_next is
 // written by wave 0 and visible to the block after its next barrier.
-template <int NT, int kOut, int MODEL, int HC = 0>
+// PL: params holds the network in the plant layout (plant_layout_index; HC > 0), whose
+// weight reads are 16-byte words, consecutive over the lanes and independent of the sums.
+template <int NT, int kOut, int MODEL, int HC = 0, bool PL = false>
 __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], float x_lane, float* lds,
                               const float* params, float* u0_out, float* x_copy, bool writer = true,
                               float* u_next = nullptr, float* x_next = nullptr) {
@@ -304,27 +324,60 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
       const float* W3 = b2 + H;
       const float* b3 = W3 + 4 * H;
       const int n = lane < H ? lane : 0;   // the lane's neuron (lanes past H repeat neuron 0)
-      float acc = b1[n];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[n * 6 + j], in[j], acc);
-      const float h1 = tanh_f(acc);
-      acc = b2[n];
-      if constexpr (HC > 0) {
-#pragma unroll
-        for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W2[n * HC + j], lane_value(h1, j), acc);
-      } else {
-        for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[n * H + j], lane_value(h1, j), acc);
-      }
-      const float h2 = tanh_f(acc);
       const int o = lane & 3;
-      acc = b3[o];
-      if constexpr (HC > 0) {
+      if constexpr (PL) {
+        static_assert(HC > 0 && HC % 4 == 0, "the plant layout needs a fixed width, a multiple of 4");
+        // the same sums in the same order; every weight is read before the first sum
+        float4 w2[HC / 4], w3[HC / 4];
 #pragma unroll
-        for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W3[o * HC + j], lane_value(h2, j), acc);
+        for (int q = 0; q < HC / 4; ++q) {
+          w2[q] = *reinterpret_cast<const float4*>(W2 + ((q * HC + n) << 2));
+          w3[q] = *reinterpret_cast<const float4*>(W3 + ((q * 4 + o) << 2));
+        }
+        float acc = b1[n];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[n * 6 + j], in[j], acc);
+        const float h1 = tanh_f(acc);
+        acc = b2[n];
+#pragma unroll
+        for (int q = 0; q < HC / 4; ++q) {
+          acc = __builtin_fmaf(w2[q].x, lane_value(h1, 4 * q + 0), acc);
+          acc = __builtin_fmaf(w2[q].y, lane_value(h1, 4 * q + 1), acc);
+          acc = __builtin_fmaf(w2[q].z, lane_value(h1, 4 * q + 2), acc);
+          acc = __builtin_fmaf(w2[q].w, lane_value(h1, 4 * q + 3), acc);
+        }
+        const float h2 = tanh_f(acc);
+        acc = b3[o];
+#pragma unroll
+        for (int q = 0; q < HC / 4; ++q) {
+          acc = __builtin_fmaf(w3[q].x, lane_value(h2, 4 * q + 0), acc);
+          acc = __builtin_fmaf(w3[q].y, lane_value(h2, 4 * q + 1), acc);
+          acc = __builtin_fmaf(w3[q].z, lane_value(h2, 4 * q + 2), acc);
+          acc = __builtin_fmaf(w3[q].w, lane_value(h2, 4 * q + 3), acc);
+        }
+        f = acc;
       } else {
-        for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[o * H + j], lane_value(h2, j), acc);
+        float acc = b1[n];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc = __builtin_fmaf(W1[n * 6 + j], in[j], acc);
+        const float h1 = tanh_f(acc);
+        acc = b2[n];
+        if constexpr (HC > 0) {
+#pragma unroll
+          for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W2[n * HC + j], lane_value(h1, j), acc);
+        } else {
+          for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W2[n * H + j], lane_value(h1, j), acc);
+        }
+        const float h2 = tanh_f(acc);
+        acc = b3[o];
+        if constexpr (HC > 0) {
+#pragma unroll
+          for (int j = 0; j < HC; ++j) acc = __builtin_fmaf(W3[o * HC + j], lane_value(h2, j), acc);
+        } else {
+          for (int j = 0; j < H; ++j) acc = __builtin_fmaf(W3[o * H + j], lane_value(h2, j), acc);
+        }
+        f = acc;
       }
-      f = acc;
     }
   }
   const float fo[4] = {lane_value(f, 0), lane_value(f, 1), lane_value(f, 2), lane_value(f, 3)};
@@ -355,9 +408,9 @@ __device__ void receding_step(const RolloutArgs& a, const float (&u_new)[kOut], 
 // apply() then forms Delta = lds[0..2T) * scale,
 // smooths it, updates U, writes the statistics and the status, advances the iteration
 // counter and, in a receding step, shifts U and advances the plant.
-// RECEDE = false: a kernel that never runs a receding step (compiled out).  HC: see
+// RECEDE = false: a kernel that never runs a receding step (compiled out).  HC, PL: see
 // receding_step.
-template <int NT, int MODEL = kModelNet, bool RECEDE = true, int HC = 0>
+template <int NT, int MODEL = kModelNet, bool RECEDE = true, int HC = 0, bool PL = false>
 struct FinalStage {
   static constexpr int kOut = (2 * kTMax + NT - 1) / NT;
   static constexpr int kTapReg = 16;
@@ -452,7 +505,7 @@ struct FinalStage {
     }
     if constexpr (RECEDE) {
       if (a.recede)
-        receding_step<NT, kOut, MODEL, HC>(a, u_new, x_old, lds, params, u0_out, x_copy, writer, u_next, x_next);
+        receding_step<NT, kOut, MODEL, HC, PL>(a, u_new, x_old, lds, params, u0_out, x_copy, writer, u_next, x_next);
     }
   }
 

@@ -61,6 +61,19 @@ constexpr int kSplitPairs = 4;     // sample pairs per block (one chain and one 
 constexpr int kSplitParams = 6 * 32 + 32 + 32 * 32 + 32 + 4 * 32 + 4;
 constexpr int kSplitBasisParams = 25 * 4;
 
+// the plant layout moves each of the network's parameters to a place of its own in the
+// same space, and its 16-byte words (the W2 and W3 sections) start on 16-byte boundaries
+constexpr bool plant_layout_fits() {
+  bool seen[kSplitParams] = {};
+  for (int i = 0; i < kSplitParams; ++i) {
+    const int d = plant_layout_index(i, 32);
+    if (d < 0 || d >= kSplitParams || seen[d]) return false;
+    seen[d] = true;
+  }
+  return (7 * 32) % 4 == 0 && (8 * 32 + 32 * 32) % 4 == 0;
+}
+static_assert(plant_layout_fits(), "the plant layout must permute the 6-32-32-4 parameter vector");
+
 namespace {
 
 __device__ __forceinline__ void wait_count(unsigned* f, unsigned v) {
@@ -326,8 +339,12 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
   const uint32_t iter0 = a.iter_dev ? *a.iter_dev : a.nk.iter;   // the device counter, advanced by the final merge
   if (tid < 2 * kSplitPairs) sFlag[tid] = 0u;
   if (tid == 0) s_abort = 0u;
-  if constexpr (MULTI)
-    for (int i = tid; i < (kNet ? kSplitParams : kSplitBasisParams); i += kSplitBlock) sP[i] = a.params[i];
+  if constexpr (MULTI)   // the plant step's copy of the parameters (a network in its plant layout)
+    for (int i = tid; i < (kNet ? kSplitParams : kSplitBasisParams); i += kSplitBlock)
+      sP[kNet ? plant_layout_index(i, HID) : i] = a.params[i];
+  // four no-ops, once per launch: they move the chain loop below onto a 64-byte boundary
+  // (where the loop lands is worth ~1 us per paper-shaped step; see draw_block_noise)
+  if constexpr (MULTI) asm volatile("s_nop 0\n\ts_nop 0\n\ts_nop 0\n\ts_nop 0");
   draw_block_noise(a, iter0, kb, T, eStride, sE);
   if (chain) __builtin_amdgcn_s_setprio(2);
 
@@ -600,7 +617,7 @@ __global__ __launch_bounds__(kSplitBlock) void rollout_wave_split_kernel(Rollout
       const int gsz = merge_group_size(as.G);
       const int ngrp = (as.G + gsz - 1) / gsz;
       const unsigned target = as.step_base + (unsigned)step + 1u;
-      FinalStage<kSplitBlock, MODEL, true, HID> fs;
+      FinalStage<kSplitBlock, MODEL, true, HID, kNet> fs;
       fs.prefetch_local(as, sU, x0v);
       __syncthreads();   // the block's N row is complete
       if (tid < 64) {
