@@ -76,7 +76,11 @@ constexpr int kQPrecFP16 = 2;
 
 template <int PREC, int HID> struct QuadNet;
 
-// FP32: v_mfma_f32_16x16x4_f32, one k-row per lane group.
+// FP32: v_mfma_f32_16x16x4_f32, one k-row per lane group, for layers 1 and 2; layer 3
+// (4 outputs) on v_mfma_f32_4x4x1_16b_f32, whose 16 blocks of 4 lanes (one lane group,
+// 4 samples) each take the 4 outputs x 4 samples of one hidden unit per call, so that
+// no row of the product is idle: lane group g sums the hidden units 16m + 4g + r, and the
+// four groups' partial sums are then added across the rows (two permlane swaps).
 template <int HID>
 struct QuadNet<kQPrecFP32, HID> {
   static constexpr int NM = HID / 16;
@@ -106,11 +110,11 @@ struct QuadNet<kQPrecFP32, HID> {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         C2[m][r] = kTanhScale * b2[16 * m + 4 * g + r];
-        A3[m][r] = (i & 3) == 0 ? W3[(i >> 2) * HID + 16 * m + 4 * g + r] : 0.0f;
+        A3[m][r] = W3[(i & 3) * HID + 16 * m + 4 * g + r];   // output i & 3 of its block
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) C3[r] = r == 0 ? b3[g] : 0.0f;
+    for (int r = 0; r < 4; ++r) C3[r] = g == 0 ? b3[r] : 0.0f;   // row r of a block: output r
   }
 
   // f = derivative (lane group g) of this lane's sample; b0 = state component g,
@@ -140,12 +144,19 @@ struct QuadNet<kQPrecFP32, HID> {
     for (int m = 0; m < NM; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) h2[m][r] = tanh_prescaled(d2[m][r]);
-    qf32x4 d3 = C3;
+    qf32x4 d3 = C3;   // lane (g, i): d3[o] = group g's part of output o of sample i
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) d3 = __builtin_amdgcn_mfma_f32_16x16x4f32(A3[m][r], h2[m][r], d3, 0, 0, 0);
-    return d3[0];
+      for (int r = 0; r < 4; ++r) d3 = __builtin_amdgcn_mfma_f32_4x4x1f32(A3[m][r], h2[m][r], d3, 0, 0, 0);
+    // lane groups 0, 1 keep outputs 0, 1 and groups 2, 3 outputs 2, 3 (sums of groups
+    // g and g ^ 2), then each group keeps its own output (sum of the pair g, g ^ 1)
+    const auto p0 = __builtin_amdgcn_permlane32_swap(q_as_u(d3[0]), q_as_u(d3[2]), false, false);
+    const auto p1 = __builtin_amdgcn_permlane32_swap(q_as_u(d3[1]), q_as_u(d3[3]), false, false);
+    const float a = q_as_f(p0[0]) + q_as_f(p0[1]);
+    const float b = q_as_f(p1[0]) + q_as_f(p1[1]);
+    const auto p2 = __builtin_amdgcn_permlane16_swap(q_as_u(a), q_as_u(b), false, false);
+    return q_as_f(p2[0]) + q_as_f(p2[1]);
   }
 };
 
